@@ -1,0 +1,143 @@
+"""Throughput of the coupled step on one MI355X.
+
+Workload (default): 256^3 periodic box, two components at 0.35 +- 0.01 each
+(50:50), g = 0.08, tau = 1, 4806 spheres of radius 5 (volume fraction 0.15)
+at seeded random positions, neutral wettability, particle density 1, FP32.
+A step is one whole time step of the method (densities, virtual fluid,
+Shan-Chen force, collision, streaming with moving bounce-back, link and
+virtual-fluid force sums, pair forces, leap-frog, map update with covering
+and refilling).  Inputs are resident in HBM when the timed region starts.
+
+Prints one JSON line: MLUPS over all lattice sites, the roofline of the
+dominant kernel (the sweep that collides and streams the populations, timed
+with HIP events on its stream inside the timed region) and the FP64 oracle
+timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (2-comp D3Q19 + spheres) at 256^3 vs HBM roofline; jobs/hour + p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_site(precision, kernel):
+    """Populations read once and written once: 2 components x 19 x (4 or 8) B x 2."""
+    ts = 8 if precision == "fp64" else 4
+    return 2 * 19 * ts * 2
+
+
+def cpu_baseline(seconds_budget=20.0):
+    """The FP64 oracle, single-threaded, on a bounded sample of the workload:
+    a 64^3 box with the same volume fraction (75 spheres of radius 5) and the
+    same fluid parameters, stepped until about `seconds_budget` have passed."""
+    from oracle.oracle import Oracle
+    from paper_1004_4414_amd import workloads as W
+    n = 64
+    count = W.sphere_count((n, n, n), 0.15, 5.0)
+    p = W.params(nx=n, ny=n, nz=n, rho_init=(0.35, 0.35), noise_amp=0.01, g_br=0.08, seed=1003)
+    parts = W.make_particles(W.random_sphere_positions((n, n, n), count, 5.0, seed=1003), 5.0)
+    orc = Oracle(p)
+    orc.add_particles(parts)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.step(1)
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt > seconds_budget or steps >= 200:
+            break
+    return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"64^3 box, {count} spheres of radius 5 (volume fraction 0.15), g=0.08, "
+                       f"{steps} steps, single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--kernel", default="auto")
+    ap.add_argument("--workload", default="bijel256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs one GPU "
+              f"per lattice, independent boxes shard trivially)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1004_4414_amd import lbm, workloads as W
+
+    p, parts, _, precision = W.config(args.workload)
+    N = p["nx"] * p["ny"] * p["nz"]
+    lat = lbm.Lattice(p, precision=precision, kernel=args.kernel)
+    lat.add_particles(parts)
+    print(f"# workload {args.workload}: {p['nx']}x{p['ny']}x{p['nz']}, {len(parts['radius'])} spheres, "
+          f"{precision}, kernel {args.kernel}", file=sys.stderr, flush=True)
+    lat.step(args.warmup)
+    lat.synchronize()
+    lat.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat.synchronize()  # reports deferred device errors
+    k_ms, k_n = lat.kernel_timing(0)
+    s_ms, s_n = lat.kernel_timing(2)
+    lat.enable_timing(False)
+    obs = lat.observables()
+    print(f"# {args.steps} steps in {elapsed:.3f} s; sweep {k_ms / max(k_n, 1):.3f} ms x {k_n}; "
+          f"step (events) {s_ms / max(s_n, 1):.3f} ms; links {obs['n_links']}", file=sys.stderr, flush=True)
+
+    mlups = N * args.steps / elapsed / 1e6
+    bps = algorithmic_bytes_per_site(precision, args.kernel)
+    sweep_s = k_ms / 1e3 / max(k_n, 1)
+    achieved = bps * N / sweep_s / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "bijel256: 256^3 periodic, 50:50 at 0.35+-0.01, g=0.08, tau=1, "
+                        "4806 spheres r=5 (volume fraction 0.15), neutral wettability, FP32 populations"
+            if args.workload == "bijel256" else args.workload,
+            "sites": N,
+            "spheres": len(parts["radius"]),
+            "kernel": args.kernel,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "collide-and-stream sweep",
+            "bytes_per_site": bps,
+            "ms_per_launch": round(sweep_s * 1e3, 4),
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

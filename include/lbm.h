@@ -1,0 +1,220 @@
+/*
+ * lbm.h -- C interface of the MI355X (gfx950) library that advances a
+ * two-component Shan-Chen D3Q19 lattice Boltzmann fluid with suspended,
+ * moving, wettable spheres, the coupled method of Jansen & Harting, "From
+ * Bijels to Pickering emulsions: a lattice Boltzmann study" (Secs. II-IV).
+ *
+ * Conventions for every call:
+ *  - Return value: LB_OK (0) or a negative LB_E* code; the handle keeps a
+ *    message for the last failure, readable with lb_last_error().
+ *  - Host arrays passed in or out are plain host memory owned by the caller;
+ *    the library copies them and keeps no caller pointer.
+ *  - Device memory is owned by the handle, allocated through the caller's
+ *    lb_allocator (or hipMalloc when none is given) and released by
+ *    lb_destroy().
+ *  - All device work of a handle is enqueued on the HIP stream given to
+ *    lb_create(); lb_step() returns after enqueueing, and device-side failures
+ *    (non-finite mass, list capacity exceeded) surface at the next call that
+ *    synchronises (lb_synchronize, lb_observables, the getters).
+ *  - A handle is used from one host thread at a time.
+ *  - Results are deterministic: identical inputs give bit-identical outputs on
+ *    the same device (no floating-point atomics anywhere).
+ *
+ * Lattice: sites x = (ix, iy, iz), 0 <= ix < nx, ..., periodic in all axes;
+ * the linear site index is n = (iz * ny + iy) * nx + ix.
+ * Velocity order (index: c_i):  0: (0,0,0);
+ *   1: (+1,0,0)  2: (-1,0,0)  3: (0,+1,0)  4: (0,-1,0)  5: (0,0,+1)  6: (0,0,-1)
+ *   7: (+1,+1,0) 8: (-1,-1,0) 9: (+1,-1,0) 10: (-1,+1,0)
+ *  11: (+1,0,+1) 12: (-1,0,-1) 13: (+1,0,-1) 14: (-1,0,+1)
+ *  15: (0,+1,+1) 16: (0,-1,-1) 17: (0,+1,-1) 18: (0,-1,+1)
+ * Component 0 is "red", component 1 is "blue" (Sec. II).
+ * Population arrays exchanged with the host are double [2][19][nz][ny][nx]:
+ * the post-streaming populations f_i^c(x, t) at the start of a step.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,    /* invalid argument or parameter */
+    LB_ENOMEM = -2,    /* device allocation failed */
+    LB_EDEVICE = -3,   /* HIP runtime error */
+    LB_EOVERLAP = -4,  /* spheres overlap */
+    LB_ESTATE = -5,    /* call not allowed in the current state */
+    LB_EUNSTABLE = -6, /* the fluid mass became non-finite */
+    LB_ECAPACITY = -7  /* a per-particle list overflowed (a sphere moved too far in one step) */
+};
+
+enum { LB_FP64 = 0, LB_FP32 = 1 };
+
+/* Fluid kernel variants. LB_KERNEL_FUSED: one sweep per step that computes
+ * densities, virtual fluid, Shan-Chen force, collision and streaming with
+ * z-marching tiles; LB_KERNEL_TWOPASS: a density sweep, a virtual-fluid pass
+ * and a collide-and-stream sweep. Both compute the same step. */
+enum { LB_KERNEL_AUTO = 0, LB_KERNEL_FUSED = 1, LB_KERNEL_TWOPASS = 2 };
+
+typedef struct lb_handle lb_handle;
+
+/* Device allocator: alloc(bytes, ctx) returns device memory or NULL;
+ * free(ptr, ctx) releases it. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} lb_allocator;
+
+typedef struct {
+    int32_t nx, ny, nz;      /* periodic box, each >= 4 */
+    int32_t precision;       /* LB_FP64 or LB_FP32: storage and arithmetic of the fluid */
+    double tau[2];           /* BGK relaxation time per component, Sec. II, > 1/2 */
+    double g_br;             /* Shan-Chen coupling g_rb = g_br of Eq. (4); g_rr = g_bb = 0 */
+    double rho0;             /* reference density in the effective mass of Eq. (5), > 0 */
+    double w_face, w_edge;   /* weights of the 18-neighbour sum of Eq. (4): faces, edges */
+    int32_t velocity_mode;   /* 1: per-component u^c = j^c/rho^c as printed in Sec. II;
+                                0: common velocity sum_c(j^c/tau^c)/sum_c(rho^c/tau^c) */
+    int32_t eq_order;        /* 3: equilibrium of Eq. (3) as printed; 2: without cubic terms */
+    double rho_init[2];      /* mean initial density per component */
+    double noise_amp;        /* initial density = rho_init + noise_amp*(2U-1), U uniform */
+    uint64_t seed;           /* key of the SplitMix64 draws U (draw index 2n + c) */
+    double body_accel[3];    /* uniform acceleration of the fluid (channel-flow tests) */
+    int32_t wall_axis;       /* -1: none; 0..2: the planes 0 and n-1 of that axis are walls */
+    double wall_vel[2][3];   /* velocities of the low and the high wall */
+    double c0_mass_corr;     /* C_0 of the mass correction, Eq. (31); 0 switches it off */
+    double k_hertz;          /* K_Hertz of Eq. (21) */
+    double lub_hc, lub_hmin; /* lubrication cut-off and clamp gaps of Eq. (22); hc <= 0: off */
+    int32_t kernel;          /* LB_KERNEL_* */
+    int32_t tile[3];         /* tile edge lengths of the fused kernel; 0 = automatic */
+} lb_params;
+
+typedef struct {
+    double pos[3];    /* centre, in [0, n) per axis */
+    double vel[3];    /* velocity U(t - 1/2) */
+    double omega[3];  /* angular velocity Omega(t - 1/2) */
+    double radius;    /* > 0 and <= min(nx, ny, nz)/4 */
+    double density;   /* mass density, > 0; m = density 4/3 pi r^3 */
+    double color;     /* wettability Delta rho of Sec. IV (> 0 prefers red) */
+    int32_t prescribed; /* 1: velocities fixed, the sphere moves but is not integrated */
+} lb_particle;
+
+typedef struct {
+    double pos[3], vel[3], omega[3];
+    double force_fluid[3], torque_fluid[3];   /* bounce-back links + Shan-Chen, last step */
+    double force_total[3], torque_total[3];   /* everything applied in the last step */
+    double pending_impulse[3], pending_angular[3]; /* covering/refilling, applied next step */
+} lb_particle_state;
+
+typedef struct {
+    int64_t step;
+    double mass[2];              /* fluid mass per component (FP64 sums) */
+    double fluid_momentum[3];
+    double particle_momentum[3]; /* sum m U */
+    double pending_impulse[3];
+    int64_t n_links, n_shell;    /* bounce-back links and virtual-fluid sites now */
+    int64_t covered_total, uncovered_total, refill_fallback;
+    int32_t n_particles;
+    int32_t unstable;            /* 1 if a step produced a non-finite mass */
+} lb_observables_t;
+
+/* Fill p with the defaults: FP32, tau = 1, g_br = 0.08, rho0 = 1, weights
+ * (4, 2), velocity_mode 1, eq_order 3, rho_init 0.35 each, noise 0.01,
+ * seed 1, no walls, no body force, C_0 = 0, K_Hertz = 100, h_c = 2/3,
+ * h_min = 0.1, automatic kernel and tiles; the box is 16^3. */
+void lb_default_params(lb_params *p);
+
+/* Create a lattice with the initial random densities at rest (f = zeta_i rho).
+ * stream: a hipStream_t (NULL = the null stream). alloc may be NULL.
+ * Errors: LB_EINVAL (bad parameter), LB_ENOMEM, LB_EDEVICE. */
+int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_handle **out);
+
+/* Release the handle and all its device memory (after the stream drains). */
+void lb_destroy(lb_handle *h);
+
+/* Message of the last failure on h ("" if none); valid until the next call. */
+const char *lb_last_error(const lb_handle *h);
+
+/* Add n spheres (Sec. III); allowed only before the first lb_step. The sites
+ * inside a sphere (strict |x - R| < r on positions rounded to multiples of
+ * 2^-20) become solid and their fluid is removed. Errors: LB_EOVERLAP (two
+ * spheres closer than r_a + r_b, minimum image), LB_EINVAL (radius, density
+ * or position out of range, or walls present), LB_ESTATE (after stepping). */
+int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts);
+
+/* Enqueue nsteps time steps (nsteps >= 0). */
+int lb_step(lb_handle *h, int32_t nsteps);
+
+/* Wait for the stream; report deferred device failures. */
+int lb_synchronize(lb_handle *h);
+
+/* Conserved sums and bookkeeping counters of the current state (synchronises). */
+int lb_observables(lb_handle *h, lb_observables_t *out);
+
+/* Fields of the current state, each pointer may be NULL:
+ * rho [2][N] densities, j [2][N][3] momenta sum_i f c, force [2][N][3] the
+ * Shan-Chen (plus body) force on fluid and virtual-fluid sites, u [N][3] the
+ * mixture velocity sum_c (j^c + F^c/2) / sum_c rho^c of Eq. (7) on fluid
+ * sites (0 elsewhere). N = nx ny nz. (Synchronises.) */
+int lb_get_fields(lb_handle *h, double *rho, double *j, double *force, double *u);
+
+/* Post-streaming populations [2][19][N] (zero on solid sites). */
+int lb_get_populations(lb_handle *h, double *f);
+
+/* Overwrite the populations on fluid sites (values on solid sites ignored);
+ * rounded to the storage precision. */
+int lb_set_populations(lb_handle *h, const double *f);
+
+/* Solid map [N]: -1 fluid, p >= 0 owned by sphere p, -2 / -3 low / high wall. */
+int lb_get_owner(lb_handle *h, int32_t *owner);
+
+/* Number of spheres. */
+int lb_num_particles(const lb_handle *h, int32_t *n);
+
+/* Particle states, lb_num_particles entries. */
+int lb_get_particles(lb_handle *h, lb_particle_state *out);
+
+/* Overwrite R, U, Omega and the pending impulses of every sphere (15 doubles
+ * per sphere in that order) and rebuild the solid map, virtual-fluid sites
+ * and links from the new positions without touching the fluid. */
+int lb_set_particle_state(lb_handle *h, const double *state);
+
+/* Bounce-back links (fluid x, i with x + c_i inside the sphere) and
+ * virtual-fluid sites (solid sites of the sphere with a fluid 18-neighbour)
+ * of every sphere on the current map. */
+int lb_particle_counts(lb_handle *h, int32_t *links, int32_t *shell);
+
+/* Checkpoint: *bytes in = capacity of buf, out = bytes written (or needed when
+ * buf is NULL). Holds the parameters, step counter, populations, particles
+ * and the mass baseline of Eq. (31). */
+int lb_get_state(lb_handle *h, void *buf, size_t *bytes);
+
+/* Restore a checkpoint written by lb_get_state for the same box and precision. */
+int lb_set_state(lb_handle *h, const void *buf, size_t bytes);
+
+/* Sec. V: the paper's linear fit theta = 442 Delta rho + 90 (degrees) of the
+ * contact angle against the particle colour, inverted; theta in [0, 180]. */
+int lb_contact_angle_to_color(double theta_deg, double *color);
+
+/* Kernel timing for measurement, with HIP events recorded on the handle's
+ * stream around the launches of one step: which = 0 the sweep that collides
+ * and streams the populations, 1 the density sweep of the two-pass variant,
+ * 2 the whole step.  lb_enable_timing(h, 1) starts recording (and clears the
+ * totals); lb_kernel_timing synchronises and returns the summed milliseconds
+ * and the number of launches since then. */
+int lb_enable_timing(lb_handle *h, int32_t enable);
+int lb_kernel_timing(lb_handle *h, int32_t which, double *ms, int64_t *launches);
+
+/* Device bytes a handle with these parameters and n spheres of radius at most
+ * max_radius would allocate, before any lb_get_fields call. */
+int lb_footprint_bytes(const lb_params *p, int32_t n_particles, double max_radius, size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,858 @@
+// C interface (include/lbm.h): parameter validation, device memory through the
+// caller's allocator, stream-ordered orchestration of the kernels of one time
+// step, host copies of fields and state, and deferred device-error reporting.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_handle.h"
+
+using namespace lbm;
+
+namespace lbm {
+
+void *dev_alloc(lb_handle *h, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    void *p = nullptr;
+    if (h->have_alloc) {
+        p = h->alloc.alloc(bytes, h->alloc.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (!p) throw std::bad_alloc();
+    h->owned.push_back(p);
+    return p;
+}
+
+void dev_free(lb_handle *h, void *p) {
+    if (!p) return;
+    auto it = std::find(h->owned.begin(), h->owned.end(), p);
+    if (it != h->owned.end()) h->owned.erase(it);
+    if (h->have_alloc) h->alloc.free(p, h->alloc.ctx);
+    else (void)hipFree(p);
+}
+
+}  // namespace lbm
+
+namespace {
+
+int fail(lb_handle *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define LB_API_BEGIN try {
+#define LB_API_END                                                                    \
+    }                                                                                 \
+    catch (const lbm::HipFailure &e) {                                                \
+        return fail(h, LB_EDEVICE, e.what);                                           \
+    }                                                                                 \
+    catch (const std::bad_alloc &) {                                                  \
+        return fail(h, LB_ENOMEM, "device allocation failed");                        \
+    }
+
+const char *kStateMagic = "LBMSTATE";
+constexpr uint32_t kStateVersion = 1;
+
+// upper bound of the lattice sites of a sphere's outermost solid layer: those
+// sites lie within sqrt(2) inside the surface, so their unit cells lie in the
+// shell r - sqrt(2) - sqrt(3)/2 < |x - R| < r + sqrt(3)/2
+int shell_capacity(double r) {
+    const double a = r + 0.8661, b = std::max(0.0, r - 1.4143 - 0.8661);
+    return (int)std::ceil(4.0 / 3.0 * M_PI * (a * a * a - b * b * b)) + 32;
+}
+
+double minimg_host(double d, double L) {
+    while (d > 0.5 * L) d -= L;
+    while (d < -0.5 * L) d += L;
+    return d;
+}
+
+unsigned nblk(long long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+void set_dev_params(lb_handle *h) {
+    const lb_params &p = h->prm;
+    DevParams &d = h->dp;
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.nz = p.nz;
+    d.np = h->np;
+    d.N = h->N;
+    for (int c = 0; c < 2; ++c) {
+        d.tau[c] = p.tau[c];
+        d.rho_init[c] = p.rho_init[c];
+    }
+    d.g = p.g_br;
+    d.rho0 = p.rho0;
+    d.w_face = p.w_face;
+    d.w_edge = p.w_edge;
+    d.velocity_mode = p.velocity_mode;
+    d.eq_order = p.eq_order;
+    d.wall_axis = p.wall_axis;
+    for (int a = 0; a < 3; ++a) {
+        d.body[a] = p.body_accel[a];
+        d.wall_vel[0][a] = p.wall_vel[0][a];
+        d.wall_vel[1][a] = p.wall_vel[1][a];
+    }
+    d.c0 = p.c0_mass_corr;
+    d.k_hertz = p.k_hertz;
+    d.lub_hc = p.lub_hc;
+    d.lub_hmin = p.lub_hmin;
+    d.nu = 0.5 * ((p.tau[0] - 0.5) + (p.tau[1] - 0.5)) / 3.0;
+}
+
+int validate_params(const lb_params *p, std::string &msg) {
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return msg = "box edges must be >= 1", LB_EINVAL;
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    if (N > 0x7fffffffLL / 2) return msg = "box too large (sites must fit 30 bits)", LB_EINVAL;
+    if (p->precision != LB_FP64 && p->precision != LB_FP32) return msg = "unknown precision", LB_EINVAL;
+    for (int c = 0; c < 2; ++c)
+        if (!(p->tau[c] > 0.5)) return msg = "tau must exceed 1/2", LB_EINVAL;
+    if (!(p->rho0 > 0.0)) return msg = "rho0 must be positive", LB_EINVAL;
+    if (p->velocity_mode != 0 && p->velocity_mode != 1) return msg = "velocity_mode must be 0 or 1", LB_EINVAL;
+    if (p->eq_order != 2 && p->eq_order != 3) return msg = "eq_order must be 2 or 3", LB_EINVAL;
+    if (p->wall_axis < -1 || p->wall_axis > 2) return msg = "wall_axis must be -1, 0, 1 or 2", LB_EINVAL;
+    if (p->kernel < LB_KERNEL_AUTO || p->kernel > LB_KERNEL_TWOPASS) return msg = "unknown kernel", LB_EINVAL;
+    if (!std::isfinite(p->g_br) || !std::isfinite(p->noise_amp)) return msg = "non-finite parameter", LB_EINVAL;
+    return LB_OK;
+}
+
+size_t fluid_bytes(const lb_params *p) {
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    const size_t ts = p->precision == LB_FP64 ? 8 : 4;
+    size_t b = 0;
+    b += 2 * (size_t)(2 * Q) * N * ts;  // two population buffers
+    b += 5 * (size_t)N * ts;            // densities, shell force
+    b += 3 * (size_t)N * 4;             // info, owner, stage
+    b += 5 * (size_t)nblk(N) * 8 + 4096;
+    return b;
+}
+
+size_t particle_bytes(int np, double max_r) {
+    const size_t sc = (size_t)shell_capacity(max_r);
+    size_t b = (size_t)np * (34 * 8 + 11 * 4);
+    b += (size_t)np * sc * (18 * 8 + 4 + 2 * 4);
+    return b + 4096;
+}
+
+// rebuild the solid map, the class words and the per-sphere lists from the
+// current positions without touching the fluid
+void rebuild_map(lb_handle *h) {
+    launch_owner_reset(h);
+    launch_fill_int(h, h->stage, h->N, STAGE_NONE);
+    LB_HIP_CHECK(hipMemcpyAsync(h->dpart.Rprev, h->dpart.R, sizeof(double) * 3 * h->np, hipMemcpyDeviceToDevice,
+                                h->stream));
+    launch_map_mark(h, false);
+    launch_map_commit(h);
+    launch_info_dense(h);
+    launch_fill_int(h, h->stage, h->N, STAGE_NONE);
+    launch_build_lists(h);
+}
+
+void free_particles(lb_handle *h) {
+    for (void *p : h->part_allocs) dev_free(h, p);
+    h->part_allocs.clear();
+    h->dpart = DevParticles{};
+    h->np = 0;
+}
+
+template <typename T>
+void to_host_populations(lb_handle *h, double *out) {
+    const long long N = h->N;
+    std::vector<T> buf((size_t)2 * Q * N);
+    std::vector<int32_t> own((size_t)N);
+    LB_HIP_CHECK(hipMemcpyAsync(buf.data(), h->f[h->cur], buf.size() * sizeof(T), hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipMemcpyAsync(own.data(), h->owner, own.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    for (size_t k = 0; k < buf.size(); ++k) out[k] = own[k % N] == OWN_FLUID ? (double)buf[k] : 0.0;
+}
+
+template <typename T>
+void from_host_populations(lb_handle *h, const double *in) {
+    const long long N = h->N;
+    std::vector<T> buf((size_t)2 * Q * N);
+    std::vector<int32_t> own((size_t)N);
+    LB_HIP_CHECK(hipMemcpyAsync(own.data(), h->owner, own.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    for (size_t k = 0; k < buf.size(); ++k) buf[k] = own[k % N] == OWN_FLUID ? (T)in[k] : (T)0;
+    LB_HIP_CHECK(hipMemcpyAsync(h->f[h->cur], buf.data(), buf.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+}
+
+int check_device_state(lb_handle *h) {
+    DevState st;
+    LB_HIP_CHECK(hipMemcpyAsync(&st, h->dstate, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    if (st.unstable) return fail(h, LB_EUNSTABLE, "the fluid mass became non-finite");
+    if (st.overflow & 8) return fail(h, LB_EUNSTABLE, "a sphere moved one lattice site or more in one step");
+    if (st.overflow & 7) return fail(h, LB_ECAPACITY, "a per-sphere list overflowed");
+    return LB_OK;
+}
+
+void one_step(lb_handle *h) {
+    void *fin = h->f[h->cur], *fout = h->f[1 - h->cur];
+    hipEvent_t t_step = h->timing_begin(2);
+    hipEvent_t t_den = h->timing_begin(1);
+    launch_density(h, fin, true);
+    h->timing_end(1, t_den);
+    launch_finalize_mass(h);
+    launch_shell_fill(h);
+    hipEvent_t t_col = h->timing_begin(0);
+    launch_collide_stream(h, fin, fout);
+    h->timing_end(0, t_col);
+    if (h->np) {
+        launch_particle_fluid_force(h, fout);
+        launch_pair_forces(h);
+        launch_integrate(h);
+        launch_map_mark(h, true);
+        launch_map_events(h);
+        launch_cover_refill(h, fout);
+        launch_map_commit(h);
+        launch_map_info(h);
+        launch_build_lists(h);
+    }
+    h->timing_end(2, t_step);
+    h->cur = 1 - h->cur;
+    ++h->step;
+}
+
+void release_events(lb_handle *h) {
+    for (int k = 0; k < 3; ++k) {
+        for (auto &pr : h->ev_pairs[k]) {
+            h->ev_pool.push_back(pr.first);
+            h->ev_pool.push_back(pr.second);
+        }
+        h->ev_pairs[k].clear();
+    }
+}
+
+}  // namespace
+
+hipEvent_t lb_handle::timing_begin(int) {
+    if (!timing) return nullptr;
+    hipEvent_t e;
+    if (!ev_pool.empty()) {
+        e = ev_pool.back();
+        ev_pool.pop_back();
+    } else {
+        LB_HIP_CHECK(hipEventCreate(&e));
+    }
+    LB_HIP_CHECK(hipEventRecord(e, stream));
+    return e;
+}
+
+void lb_handle::timing_end(int kind, hipEvent_t start) {
+    if (!timing || !start) return;
+    hipEvent_t e;
+    if (!ev_pool.empty()) {
+        e = ev_pool.back();
+        ev_pool.pop_back();
+    } else {
+        LB_HIP_CHECK(hipEventCreate(&e));
+    }
+    LB_HIP_CHECK(hipEventRecord(e, stream));
+    ev_pairs[kind].emplace_back(start, e);
+}
+
+extern "C" {
+
+void lb_default_params(lb_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->nx = p->ny = p->nz = 16;
+    p->precision = LB_FP32;
+    p->tau[0] = p->tau[1] = 1.0;
+    p->g_br = 0.08;
+    p->rho0 = 1.0;
+    p->w_face = 4.0;
+    p->w_edge = 2.0;
+    p->velocity_mode = 1;
+    p->eq_order = 3;
+    p->rho_init[0] = p->rho_init[1] = 0.35;
+    p->noise_amp = 0.01;
+    p->seed = 1;
+    p->wall_axis = -1;
+    p->c0_mass_corr = 0.0;
+    p->k_hertz = 100.0;
+    p->lub_hc = 2.0 / 3.0;
+    p->lub_hmin = 0.1;
+    p->kernel = LB_KERNEL_AUTO;
+}
+
+int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_handle **out) {
+    if (!p || !out) return LB_EINVAL;
+    *out = nullptr;
+    std::string msg;
+    int rc = validate_params(p, msg);
+    if (rc != LB_OK) return rc;
+    lb_handle *h = new (std::nothrow) lb_handle();
+    if (!h) return LB_ENOMEM;
+    h->prm = *p;
+    h->stream = (hipStream_t)stream;
+    if (alloc && alloc->alloc && alloc->free) {
+        h->alloc = *alloc;
+        h->have_alloc = true;
+    }
+    h->N = (long long)p->nx * p->ny * p->nz;
+    h->tsize = p->precision == LB_FP64 ? 8 : 4;
+    h->kernel = p->kernel == LB_KERNEL_AUTO ? LB_KERNEL_TWOPASS : p->kernel;
+    for (int a = 0; a < 3; ++a) h->tile[a] = p->tile[a];
+    set_dev_params(h);
+    try {
+        const size_t fsz = (size_t)2 * Q * h->N * h->tsize;
+        h->f[0] = dev_alloc(h, fsz);
+        h->f[1] = dev_alloc(h, fsz);
+        h->rho = dev_alloc(h, (size_t)2 * h->N * h->tsize);
+        h->fsc = dev_alloc(h, (size_t)3 * h->N * h->tsize);
+        h->info = (uint32_t *)dev_alloc(h, (size_t)h->N * 4);
+        h->owner = (int32_t *)dev_alloc(h, (size_t)h->N * 4);
+        h->stage = (int32_t *)dev_alloc(h, (size_t)h->N * 4);
+        h->n_partial = (int)nblk(h->N);
+        h->partial = (double *)dev_alloc(h, (size_t)5 * h->n_partial * 8);
+        h->dstate = (DevState *)dev_alloc(h, sizeof(DevState));
+        LB_HIP_CHECK(hipMemsetAsync(h->dstate, 0, sizeof(DevState), h->stream));
+        LB_HIP_CHECK(hipMemsetAsync(h->f[1], 0, fsz, h->stream));
+        launch_fill_int(h, h->stage, h->N, STAGE_NONE);
+        launch_init_fluid(h);
+        LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    } catch (const lbm::HipFailure &e) {
+        std::string w = e.what;
+        lb_destroy(h);
+        (void)w;
+        return LB_EDEVICE;
+    } catch (const std::bad_alloc &) {
+        lb_destroy(h);
+        return LB_ENOMEM;
+    }
+    *out = h;
+    return LB_OK;
+}
+
+void lb_destroy(lb_handle *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    release_events(h);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    h->ev_pool.clear();
+    std::vector<void *> all = h->owned;
+    for (void *p : all) dev_free(h, p);
+    delete h;
+}
+
+const char *lb_last_error(const lb_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
+    if (!h) return LB_EINVAL;
+    if (h->step > 0) return fail(h, LB_ESTATE, "spheres can only be added before the first step");
+    if (n < 0 || (n > 0 && !parts)) return fail(h, LB_EINVAL, "bad particle array");
+    if (n == 0) return LB_OK;
+    if (h->prm.wall_axis >= 0) return fail(h, LB_EINVAL, "spheres and walls cannot be combined");
+    const int L[3] = {h->prm.nx, h->prm.ny, h->prm.nz};
+    const int minL = std::min(L[0], std::min(L[1], L[2]));
+    for (int k = 0; k < n; ++k) {
+        const lb_particle &q = parts[k];
+        if (!(q.radius > 0.0) || q.radius > 0.25 * minL || !(q.density > 0.0) || !std::isfinite(q.color))
+            return fail(h, LB_EINVAL, "sphere radius must be in (0, L/4] and density positive");
+        for (int a = 0; a < 3; ++a) {
+            if (!(q.pos[a] >= 0.0 && q.pos[a] < L[a])) return fail(h, LB_EINVAL, "sphere centre outside the box");
+            if (2 * (int)std::ceil(q.radius) + 7 > L[a]) return fail(h, LB_EINVAL, "box too small for the sphere");
+        }
+    }
+    // all spheres: existing then new
+    std::vector<double> pos, vel, om;
+    LB_API_BEGIN
+    const int old = h->np;
+    if (old) {
+        pos.resize(3 * old);
+        vel.resize(3 * old);
+        om.resize(3 * old);
+        LB_HIP_CHECK(hipMemcpyAsync(pos.data(), h->dpart.R, 24 * old, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipMemcpyAsync(vel.data(), h->dpart.U, 24 * old, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipMemcpyAsync(om.data(), h->dpart.W, 24 * old, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    }
+    std::vector<double> rad = h->h_rad, dens = h->h_dens, col = h->h_color;
+    std::vector<int32_t> pre = h->h_prescribed;
+    for (int k = 0; k < n; ++k) {
+        for (int a = 0; a < 3; ++a) {
+            pos.push_back(parts[k].pos[a]);
+            vel.push_back(parts[k].vel[a]);
+            om.push_back(parts[k].omega[a]);
+        }
+        rad.push_back(parts[k].radius);
+        dens.push_back(parts[k].density);
+        col.push_back(parts[k].color);
+        pre.push_back(parts[k].prescribed ? 1 : 0);
+    }
+    const int tot = old + n;
+    // overlap test, minimum image, against spheres on a coarse cell grid
+    {
+        double rmax = *std::max_element(rad.begin(), rad.end());
+        int nc[3];
+        for (int a = 0; a < 3; ++a) nc[a] = std::max(1, (int)(L[a] / (2 * rmax)));
+        std::vector<std::vector<int>> cells((size_t)nc[0] * nc[1] * nc[2]);
+        auto cell_of = [&](int p, int a) { return std::min(nc[a] - 1, (int)(pos[3 * p + a] / L[a] * nc[a])); };
+        for (int p = 0; p < tot; ++p)
+            cells[((size_t)cell_of(p, 2) * nc[1] + cell_of(p, 1)) * nc[0] + cell_of(p, 0)].push_back(p);
+        for (int p = old; p < tot; ++p) {
+            const int c0 = cell_of(p, 0), c1 = cell_of(p, 1), c2 = cell_of(p, 2);
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if ((nc[0] < 3 && dx) || (nc[1] < 3 && dy) || (nc[2] < 3 && dz)) continue;
+                        const size_t ci = ((size_t)((c2 + dz + nc[2]) % nc[2]) * nc[1] + (c1 + dy + nc[1]) % nc[1]) *
+                                              nc[0] + (c0 + dx + nc[0]) % nc[0];
+                        for (int q : cells[ci]) {
+                            if (q == p || (q >= old && q > p)) continue;
+                            double d2 = 0.0;
+                            for (int a = 0; a < 3; ++a) {
+                                const double d = minimg_host(pos[3 * q + a] - pos[3 * p + a], L[a]);
+                                d2 += d * d;
+                            }
+                            const double rs = rad[p] + rad[q];
+                            if (d2 <= rs * rs) return fail(h, LB_EOVERLAP, "spheres overlap");
+                        }
+                    }
+        }
+    }
+    // per-sphere list capacities
+    std::vector<int32_t> link_off(tot), link_cap(tot), shell_off(tot), shell_cap(tot), ev_off(tot), ev_cap(tot);
+    long long lsum = 0, ssum = 0, esum = 0;
+    for (int p = 0; p < tot; ++p) {
+        const int sc = shell_capacity(rad[p]);
+        shell_off[p] = (int32_t)ssum;
+        shell_cap[p] = sc;
+        ssum += sc;
+        link_off[p] = (int32_t)lsum;
+        link_cap[p] = 18 * sc;
+        lsum += 18LL * sc;
+        ev_off[p] = (int32_t)esum;
+        ev_cap[p] = sc;
+        esum += sc;
+    }
+    if (lsum > 0x7fffffffLL) return fail(h, LB_EINVAL, "too many spheres for the list capacity");
+    free_particles(h);
+    h->np = tot;
+    DevParticles &D = h->dpart;
+    double *dbl = (double *)dev_alloc(h, sizeof(double) * 34 * tot);
+    int32_t *i32 = (int32_t *)dev_alloc(h, sizeof(int32_t) * 11 * tot);
+    h->part_allocs.push_back(dbl);
+    h->part_allocs.push_back(i32);
+    D.R = dbl;
+    D.U = dbl + 3 * tot;
+    D.W = dbl + 6 * tot;
+    D.Rprev = dbl + 9 * tot;
+    D.Ffl = dbl + 12 * tot;
+    D.Tfl = dbl + 15 * tot;
+    D.Ftot = dbl + 18 * tot;
+    D.Ttot = dbl + 21 * tot;
+    D.P = dbl + 24 * tot;
+    D.PT = dbl + 27 * tot;
+    D.rad = dbl + 30 * tot;
+    D.mass = dbl + 31 * tot;
+    D.inertia = dbl + 32 * tot;
+    D.color = dbl + 33 * tot;
+    D.prescribed = i32;
+    D.link_off = i32 + tot;
+    D.link_cap = i32 + 2 * tot;
+    D.link_cnt = i32 + 3 * tot;
+    D.shell_off = i32 + 4 * tot;
+    D.shell_cap = i32 + 5 * tot;
+    D.shell_cnt = i32 + 6 * tot;
+    D.ev_off = i32 + 7 * tot;
+    D.ev_cap = i32 + 8 * tot;
+    D.cov_cnt = i32 + 9 * tot;
+    D.unc_cnt = i32 + 10 * tot;
+    D.links = (int64_t *)dev_alloc(h, sizeof(int64_t) * lsum);
+    D.shell = (int32_t *)dev_alloc(h, sizeof(int32_t) * ssum);
+    D.cov = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
+    D.unc = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
+    h->part_allocs.push_back(D.links);
+    h->part_allocs.push_back(D.shell);
+    h->part_allocs.push_back(D.cov);
+    h->part_allocs.push_back(D.unc);
+    // host image of the double block
+    std::vector<double> hd((size_t)34 * tot, 0.0);
+    for (int p = 0; p < tot; ++p) {
+        for (int a = 0; a < 3; ++a) {
+            hd[3 * p + a] = pos[3 * p + a];
+            hd[3 * tot + 3 * p + a] = vel[3 * p + a];
+            hd[6 * tot + 3 * p + a] = om[3 * p + a];
+            hd[9 * tot + 3 * p + a] = pos[3 * p + a];
+        }
+        const double m = dens[p] * (4.0 / 3.0) * M_PI * rad[p] * rad[p] * rad[p];
+        hd[30 * tot + p] = rad[p];
+        hd[31 * tot + p] = m;
+        hd[32 * tot + p] = 0.4 * m * rad[p] * rad[p];
+        hd[33 * tot + p] = col[p];
+    }
+    std::vector<int32_t> hi((size_t)11 * tot, 0);
+    for (int p = 0; p < tot; ++p) {
+        hi[p] = pre[p];
+        hi[tot + p] = link_off[p];
+        hi[2 * tot + p] = link_cap[p];
+        hi[4 * tot + p] = shell_off[p];
+        hi[5 * tot + p] = shell_cap[p];
+        hi[7 * tot + p] = ev_off[p];
+        hi[8 * tot + p] = ev_cap[p];
+    }
+    LB_HIP_CHECK(hipMemcpyAsync(dbl, hd.data(), hd.size() * 8, hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipMemcpyAsync(i32, hi.data(), hi.size() * 4, hipMemcpyHostToDevice, h->stream));
+    h->h_rad = rad;
+    h->h_dens = dens;
+    h->h_color = col;
+    h->h_prescribed = pre;
+    set_dev_params(h);
+    rebuild_map(h);
+    launch_zero_solid(h, h->f[h->cur]);  // the fluid inside the spheres is removed
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    return check_device_state(h);
+    LB_API_END
+}
+
+int lb_step(lb_handle *h, int32_t nsteps) {
+    if (!h) return LB_EINVAL;
+    if (nsteps < 0) return fail(h, LB_EINVAL, "nsteps must be >= 0");
+    LB_API_BEGIN
+    for (int s = 0; s < nsteps; ++s) one_step(h);
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_synchronize(lb_handle *h) {
+    if (!h) return LB_EINVAL;
+    LB_API_BEGIN
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    return check_device_state(h);
+    LB_API_END
+}
+
+int lb_observables(lb_handle *h, lb_observables_t *out) {
+    if (!h || !out) return LB_EINVAL;
+    LB_API_BEGIN
+    std::memset(out, 0, sizeof(*out));
+    launch_sums(h, h->f[h->cur]);
+    std::vector<double> part((size_t)5 * h->n_partial);
+    LB_HIP_CHECK(hipMemcpyAsync(part.data(), h->partial, part.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    DevState st;
+    LB_HIP_CHECK(hipMemcpyAsync(&st, h->dstate, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    for (int b = 0; b < h->n_partial; ++b) {
+        out->mass[0] += part[5 * b];
+        out->mass[1] += part[5 * b + 1];
+        for (int a = 0; a < 3; ++a) out->fluid_momentum[a] += part[5 * b + 2 + a];
+    }
+    out->step = h->step;
+    out->n_particles = h->np;
+    out->unstable = st.unstable;
+    out->covered_total = (int64_t)st.covered_total;
+    out->uncovered_total = (int64_t)st.uncovered_total;
+    out->refill_fallback = (int64_t)st.refill_fallback;
+    if (h->np) {
+        const int np = h->np;
+        std::vector<double> U(3 * np), P(3 * np);
+        std::vector<int32_t> lc(np), sc(np);
+        LB_HIP_CHECK(hipMemcpyAsync(U.data(), h->dpart.U, 24 * np, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipMemcpyAsync(P.data(), h->dpart.P, 24 * np, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipMemcpyAsync(lc.data(), h->dpart.link_cnt, 4 * np, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipMemcpyAsync(sc.data(), h->dpart.shell_cnt, 4 * np, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+        for (int p = 0; p < np; ++p) {
+            const double m = h->h_dens[p] * (4.0 / 3.0) * M_PI * h->h_rad[p] * h->h_rad[p] * h->h_rad[p];
+            for (int a = 0; a < 3; ++a) {
+                out->particle_momentum[a] += m * U[3 * p + a];
+                out->pending_impulse[a] += P[3 * p + a];
+            }
+            out->n_links += lc[p];
+            out->n_shell += sc[p];
+        }
+    }
+    return check_device_state(h);
+    LB_API_END
+}
+
+int lb_get_fields(lb_handle *h, double *rho, double *j, double *force, double *u) {
+    if (!h) return LB_EINVAL;
+    LB_API_BEGIN
+    const long long N = h->N;
+    if (!h->fields) h->fields = (double *)dev_alloc(h, sizeof(double) * 17 * N);
+    launch_density(h, h->f[h->cur], false);
+    launch_shell_fill(h);
+    launch_fields(h, h->f[h->cur], h->fields);
+    if (rho) LB_HIP_CHECK(hipMemcpyAsync(rho, h->fields, 16 * N, hipMemcpyDeviceToHost, h->stream));
+    if (j) LB_HIP_CHECK(hipMemcpyAsync(j, h->fields + 2 * N, 48 * N, hipMemcpyDeviceToHost, h->stream));
+    if (force) LB_HIP_CHECK(hipMemcpyAsync(force, h->fields + 8 * N, 48 * N, hipMemcpyDeviceToHost, h->stream));
+    if (u) LB_HIP_CHECK(hipMemcpyAsync(u, h->fields + 14 * N, 24 * N, hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    return check_device_state(h);
+    LB_API_END
+}
+
+int lb_get_populations(lb_handle *h, double *f) {
+    if (!h || !f) return LB_EINVAL;
+    LB_API_BEGIN
+    if (h->prm.precision == LB_FP64) to_host_populations<double>(h, f);
+    else to_host_populations<float>(h, f);
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_set_populations(lb_handle *h, const double *f) {
+    if (!h || !f) return LB_EINVAL;
+    LB_API_BEGIN
+    if (h->prm.precision == LB_FP64) from_host_populations<double>(h, f);
+    else from_host_populations<float>(h, f);
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_get_owner(lb_handle *h, int32_t *owner) {
+    if (!h || !owner) return LB_EINVAL;
+    LB_API_BEGIN
+    LB_HIP_CHECK(hipMemcpyAsync(owner, h->owner, 4 * h->N, hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_num_particles(const lb_handle *h, int32_t *n) {
+    if (!h || !n) return LB_EINVAL;
+    *n = h->np;
+    return LB_OK;
+}
+
+int lb_get_particles(lb_handle *h, lb_particle_state *out) {
+    if (!h || (!out && h->np)) return LB_EINVAL;
+    if (!h->np) return LB_OK;
+    LB_API_BEGIN
+    const int np = h->np;
+    std::vector<double> d((size_t)34 * np);
+    LB_HIP_CHECK(hipMemcpyAsync(d.data(), h->dpart.R, d.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    for (int p = 0; p < np; ++p)
+        for (int a = 0; a < 3; ++a) {
+            out[p].pos[a] = d[3 * p + a];
+            out[p].vel[a] = d[3 * np + 3 * p + a];
+            out[p].omega[a] = d[6 * np + 3 * p + a];
+            out[p].force_fluid[a] = d[12 * np + 3 * p + a];
+            out[p].torque_fluid[a] = d[15 * np + 3 * p + a];
+            out[p].force_total[a] = d[18 * np + 3 * p + a];
+            out[p].torque_total[a] = d[21 * np + 3 * p + a];
+            out[p].pending_impulse[a] = d[24 * np + 3 * p + a];
+            out[p].pending_angular[a] = d[27 * np + 3 * p + a];
+        }
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_set_particle_state(lb_handle *h, const double *state) {
+    if (!h || (!state && h->np)) return LB_EINVAL;
+    if (!h->np) return LB_OK;
+    LB_API_BEGIN
+    const int np = h->np;
+    const int L[3] = {h->prm.nx, h->prm.ny, h->prm.nz};
+    std::vector<double> R(3 * np), U(3 * np), W(3 * np), P(3 * np), PT(3 * np);
+    for (int p = 0; p < np; ++p)
+        for (int a = 0; a < 3; ++a) {
+            R[3 * p + a] = state[15 * p + a];
+            U[3 * p + a] = state[15 * p + 3 + a];
+            W[3 * p + a] = state[15 * p + 6 + a];
+            P[3 * p + a] = state[15 * p + 9 + a];
+            PT[3 * p + a] = state[15 * p + 12 + a];
+            if (!(R[3 * p + a] >= 0.0 && R[3 * p + a] < L[a]))
+                return fail(h, LB_EINVAL, "sphere centre outside the box");
+        }
+    LB_HIP_CHECK(hipMemcpyAsync(h->dpart.R, R.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipMemcpyAsync(h->dpart.U, U.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipMemcpyAsync(h->dpart.W, W.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipMemcpyAsync(h->dpart.P, P.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipMemcpyAsync(h->dpart.PT, PT.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
+    launch_zero_solid(h, h->f[h->cur]);
+    rebuild_map(h);
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    return check_device_state(h);
+    LB_API_END
+}
+
+int lb_particle_counts(lb_handle *h, int32_t *links, int32_t *shell) {
+    if (!h) return LB_EINVAL;
+    if (!h->np) return LB_OK;
+    LB_API_BEGIN
+    if (links)
+        LB_HIP_CHECK(hipMemcpyAsync(links, h->dpart.link_cnt, 4 * h->np, hipMemcpyDeviceToHost, h->stream));
+    if (shell)
+        LB_HIP_CHECK(hipMemcpyAsync(shell, h->dpart.shell_cnt, 4 * h->np, hipMemcpyDeviceToHost, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    return LB_OK;
+    LB_API_END
+}
+
+// checkpoint layout: magic[8], version, precision, nx, ny, nz, np (u32 each),
+// step (i64), DevState, populations (raw storage type), then per sphere
+// R U W P PT (15 doubles) radius density colour (3 doubles) prescribed (i32)
+int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
+    if (!h || !bytes) return LB_EINVAL;
+    const size_t fsz = (size_t)2 * Q * h->N * h->tsize;
+    const size_t need = 8 + 6 * 4 + 8 + sizeof(DevState) + fsz + (size_t)h->np * (18 * 8 + 4);
+    if (!buf) {
+        *bytes = need;
+        return LB_OK;
+    }
+    if (*bytes < need) return fail(h, LB_EINVAL, "checkpoint buffer too small");
+    LB_API_BEGIN
+    char *o = (char *)buf;
+    std::memcpy(o, kStateMagic, 8);
+    o += 8;
+    const uint32_t hdr[6] = {kStateVersion, (uint32_t)h->prm.precision, (uint32_t)h->prm.nx, (uint32_t)h->prm.ny,
+                             (uint32_t)h->prm.nz, (uint32_t)h->np};
+    std::memcpy(o, hdr, sizeof(hdr));
+    o += sizeof(hdr);
+    const int64_t st = h->step;
+    std::memcpy(o, &st, 8);
+    o += 8;
+    LB_HIP_CHECK(hipMemcpyAsync(o, h->dstate, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    o += sizeof(DevState);
+    LB_HIP_CHECK(hipMemcpyAsync(o, h->f[h->cur], fsz, hipMemcpyDeviceToHost, h->stream));
+    o += fsz;
+    if (h->np) {
+        const int np = h->np;
+        std::vector<double> d((size_t)34 * np);
+        LB_HIP_CHECK(hipMemcpyAsync(d.data(), h->dpart.R, d.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+        const int blocks[5] = {0, 3, 6, 24, 27};
+        for (int p = 0; p < np; ++p) {
+            double v[18];
+            for (int b = 0; b < 5; ++b)
+                for (int a = 0; a < 3; ++a) v[3 * b + a] = d[(size_t)blocks[b] * np + 3 * p + a];
+            v[15] = h->h_rad[p];
+            v[16] = h->h_dens[p];
+            v[17] = h->h_color[p];
+            std::memcpy(o, v, sizeof(v));
+            o += sizeof(v);
+            const int32_t pr = h->h_prescribed[p];
+            std::memcpy(o, &pr, 4);
+            o += 4;
+        }
+    }
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    *bytes = need;
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
+    if (!h || !buf) return LB_EINVAL;
+    const char *in = (const char *)buf;
+    if (bytes < 8 + 24 + 8 + sizeof(DevState) || std::memcmp(in, kStateMagic, 8) != 0)
+        return fail(h, LB_EINVAL, "not a checkpoint");
+    uint32_t hdr[6];
+    std::memcpy(hdr, in + 8, sizeof(hdr));
+    if (hdr[0] != kStateVersion || (int)hdr[1] != h->prm.precision || (int)hdr[2] != h->prm.nx ||
+        (int)hdr[3] != h->prm.ny || (int)hdr[4] != h->prm.nz)
+        return fail(h, LB_EINVAL, "checkpoint of a different lattice");
+    const int np = (int)hdr[5];
+    const size_t fsz = (size_t)2 * Q * h->N * h->tsize;
+    if (bytes < 8 + 24 + 8 + sizeof(DevState) + fsz + (size_t)np * (18 * 8 + 4))
+        return fail(h, LB_EINVAL, "truncated checkpoint");
+    LB_API_BEGIN
+    const char *p = in + 32;
+    int64_t st;
+    std::memcpy(&st, p, 8);
+    p += 8;
+    const char *dstate = p;
+    p += sizeof(DevState);
+    const char *pops = p;
+    p += fsz;
+    // spheres: rebuild the particle arrays as a fresh addition
+    if (np != h->np) {
+        if (h->step == 0 && h->np == 0 && np > 0) {
+            std::vector<lb_particle> parts(np);
+            const char *q = p;
+            for (int k = 0; k < np; ++k) {
+                double v[18];
+                std::memcpy(v, q, sizeof(v));
+                q += sizeof(v);
+                int32_t pr;
+                std::memcpy(&pr, q, 4);
+                q += 4;
+                for (int a = 0; a < 3; ++a) {
+                    parts[k].pos[a] = v[a];
+                    parts[k].vel[a] = v[3 + a];
+                    parts[k].omega[a] = v[6 + a];
+                }
+                parts[k].radius = v[15];
+                parts[k].density = v[16];
+                parts[k].color = v[17];
+                parts[k].prescribed = pr;
+            }
+            const int rc = lb_add_particles(h, np, parts.data());
+            if (rc != LB_OK) return rc;
+        } else {
+            return fail(h, LB_ESTATE, "checkpoint has a different number of spheres");
+        }
+    }
+    if (np) {
+        std::vector<double> s((size_t)15 * np);
+        const char *q = p;
+        for (int k = 0; k < np; ++k) {
+            std::memcpy(&s[15 * k], q, 15 * 8);
+            q += 18 * 8 + 4;
+        }
+        const int rc = lb_set_particle_state(h, s.data());
+        if (rc != LB_OK) return rc;
+    }
+    LB_HIP_CHECK(hipMemcpyAsync(h->f[h->cur], pops, fsz, hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipMemcpyAsync(h->dstate, dstate, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    h->step = st;
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_enable_timing(lb_handle *h, int32_t enable) {
+    if (!h) return LB_EINVAL;
+    LB_API_BEGIN
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    release_events(h);
+    h->timing = enable != 0;
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_kernel_timing(lb_handle *h, int32_t which, double *ms, int64_t *launches) {
+    if (!h || which < 0 || which > 2 || !ms || !launches) return LB_EINVAL;
+    LB_API_BEGIN
+    LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    for (auto &pr : h->ev_pairs[which]) {
+        float t = 0.f;
+        LB_HIP_CHECK(hipEventElapsedTime(&t, pr.first, pr.second));
+        tot += t;
+    }
+    *ms = tot;
+    *launches = (int64_t)h->ev_pairs[which].size();
+    return LB_OK;
+    LB_API_END
+}
+
+int lb_contact_angle_to_color(double theta_deg, double *color) {
+    if (!color || !(theta_deg >= 0.0 && theta_deg <= 180.0)) return LB_EINVAL;
+    *color = (theta_deg - 90.0) / 442.0;
+    return LB_OK;
+}
+
+int lb_footprint_bytes(const lb_params *p, int32_t n_particles, double max_radius, size_t *bytes) {
+    if (!p || !bytes || n_particles < 0) return LB_EINVAL;
+    std::string msg;
+    const int rc = validate_params(p, msg);
+    if (rc != LB_OK) return rc;
+    *bytes = fluid_bytes(p) + (n_particles ? particle_bytes(n_particles, max_radius) : 0);
+    return LB_OK;
+}
+
+}  // extern "C"

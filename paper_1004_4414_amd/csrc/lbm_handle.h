@@ -1,0 +1,97 @@
+// Host-side state of one lattice and the launchers of its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+
+struct lb_handle {
+    lb_params prm{};
+    lbm::DevParams dp{};
+    hipStream_t stream = nullptr;
+    lb_allocator alloc{};
+    bool have_alloc = false;
+    std::string err;
+    long long N = 0;
+    size_t tsize = 4;  // bytes per stored population
+
+    // fluid
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    void *rho = nullptr;  // T [2][N]: densities (fluid), virtual densities (shell)
+    void *fsc = nullptr;  // T [3][N]: Shan-Chen force on virtual-fluid sites
+    uint32_t *info = nullptr;
+    int32_t *owner = nullptr;
+    int32_t *stage = nullptr;
+    double *partial = nullptr;  // per-block partial sums
+    int n_partial = 0;
+    lbm::DevState *dstate = nullptr;
+    double *fields = nullptr;  // lazily allocated output staging of lb_get_fields
+
+    // particles
+    int np = 0;
+    lbm::DevParticles dpart{};
+    std::vector<void *> part_allocs;
+    std::vector<double> h_rad, h_dens, h_color;
+    std::vector<int32_t> h_prescribed;
+
+    int kernel = LB_KERNEL_TWOPASS;
+    int tile[3] = {0, 0, 0};
+    long long step = 0;
+    std::vector<void *> owned;  // every device allocation, freed by lb_destroy
+
+    // event timing (measurement only): per kind, pairs of recorded events
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs[3];
+    hipEvent_t timing_begin(int kind);
+    void timing_end(int kind, hipEvent_t start);
+};
+
+namespace lbm {
+
+void *dev_alloc(lb_handle *h, size_t bytes);
+void dev_free(lb_handle *h, void *p);
+
+// fluid (lbm_fluid.hip)
+void launch_init_fluid(lb_handle *h);
+void launch_density(lb_handle *h, const void *f, bool partial_sums);
+void launch_finalize_mass(lb_handle *h);
+void launch_shell_fill(lb_handle *h);
+void launch_collide_stream(lb_handle *h, const void *fin, void *fout);
+void launch_fields(lb_handle *h, const void *f, double *out);
+void launch_sums(lb_handle *h, const void *f);
+void launch_fill_int(lb_handle *h, int32_t *p, long long n, int32_t v);
+void launch_zero_solid(lb_handle *h, void *f);
+void launch_info_dense(lb_handle *h);
+void launch_owner_reset(lb_handle *h);
+
+// particles (lbm_particles.hip)
+void launch_particle_fluid_force(lb_handle *h, const void *fout);
+void launch_pair_forces(lb_handle *h);
+void launch_integrate(lb_handle *h);
+void launch_map_mark(lb_handle *h, bool use_prev);
+void launch_map_events(lb_handle *h);
+void launch_cover_refill(lb_handle *h, void *fout);
+void launch_map_commit(lb_handle *h);
+void launch_map_info(lb_handle *h);
+void launch_build_lists(lb_handle *h);
+
+}  // namespace lbm
+
+#define LB_HIP_CHECK(expr)                                                            \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) throw lbm::HipFailure(#expr, hipGetErrorString(e_));    \
+    } while (0)
+
+namespace lbm {
+struct HipFailure {
+    std::string what;
+    HipFailure(const char *expr, const char *msg) : what(std::string(expr) + ": " + msg) {}
+};
+}  // namespace lbm

@@ -1,0 +1,501 @@
+// Particle kernels for gfx950 (Secs. III, IV of Jansen & Harting): the
+// momentum exchanged on bounce-back links and the Shan-Chen force on the
+// virtual fluid summed per sphere, Hertz and lubrication pair forces, the
+// leap-frog integration, and the update of the solid map with the covering
+// and refilling of sites.
+//
+// Every per-sphere sum is a fixed-order FP64 block reduction and every list
+// is compacted in scan order with wavefront ballots, so results are bitwise
+// reproducible.  One block handles one sphere; the only atomics are integer
+// (the lowest-index owner of a site, event counters).
+#include "lbm_handle.h"
+
+#pragma clang fp contract(off)
+
+namespace lbm {
+
+__device__ __forceinline__ void load3(const double *a, int p, double v[3]) {
+    v[0] = a[3 * p];
+    v[1] = a[3 * p + 1];
+    v[2] = a[3 * p + 2];
+}
+
+__device__ __forceinline__ void box_site(int k, const int lo[3], const int ext[3], const DevParams &P, int &x, int &y,
+                                         int &z) {
+    const int dx = k % ext[0];
+    const int t = k / ext[0];
+    const int dy = t % ext[1];
+    const int dz = t / ext[1];
+    x = wrapany(lo[0] + dx, P.nx);
+    y = wrapany(lo[1] + dy, P.ny);
+    z = wrapany(lo[2] + dz, P.nz);
+}
+
+// box holding the sphere at its previous and its new position (the new one
+// unwrapped next to the previous), optionally grown by g sites
+__device__ __forceinline__ void union_box(const DevParams &P, const DevParticles &D, int p, int g, int lo[3],
+                                          int ext[3]) {
+    double Rp[3], Rn[3];
+    load3(D.Rprev, p, Rp);
+    load3(D.R, p, Rn);
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    for (int a = 0; a < 3; ++a) Rn[a] = Rp[a] + minimg(Rn[a] - Rp[a], L[a]);
+    int lo0[3], hi0[3], lo1[3], hi1[3];
+    sphere_box(Rp, D.rad[p], lo0, hi0);
+    sphere_box(Rn, D.rad[p], lo1, hi1);
+    const int Lb[3] = {P.nx, P.ny, P.nz};
+    const bool empty = hi0[0] < lo0[0] || hi1[0] < lo1[0];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = min(lo0[a], lo1[a]) - g;
+        ext[a] = empty ? 0 : min(max(hi0[a], hi1[a]) + g - lo[a] + 1, Lb[a] + 2 * g + 8);
+    }
+}
+
+__device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &D, int p, int lo[3], int ext[3]) {
+    double R[3];
+    load3(D.R, p, R);
+    int hi[3];
+    sphere_box(R, D.rad[p], lo, hi);
+    const int Lb[3] = {P.nx, P.ny, P.nz};
+    for (int a = 0; a < 3; ++a) ext[a] = hi[a] < lo[a] ? 0 : min(hi[a] - lo[a] + 1, Lb[a] + 8);
+}
+
+// ---------------------------------------------------------------------------
+// fluid force and torque on each sphere: bounce-back links, Eqs. (13)-(17),
+// and the Shan-Chen force on its virtual fluid, Eq. (28).
+// A link (x, i) has x fluid and x + c_i inside the sphere.  The kernel that
+// streamed wrote f_opp(i)(x) = f*_i(x) - w^c with w^c = 6 zeta_i rho^c(x)
+// (c_i . u_b), so the momentum given to the sphere is
+// c_i sum_c (2 f*_i - w^c) = c_i sum_c (2 f_opp(i)(x) + w^c).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, const T *__restrict__ fout,
+                                                                const T *__restrict__ rho, const T *__restrict__ fsc) {
+    __shared__ double lds[6 * BLOCK];
+    const int p = blockIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    double R[3];
+    load3(D.R, p, R);
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    const int nl = min(D.link_cnt[p], D.link_cap[p]), loff = D.link_off[p];
+    for (int k = threadIdx.x; k < nl; k += BLOCK) {
+        const long long e = D.links[loff + k];
+        const long long n = e >> 5;
+        const int i = (int)(e & 31);
+        int x, y, z;
+        site_xyz(n, P, x, y, z);
+        double ub[3], rb[3];
+        solid_velocity(P, D, p, x, y, z, i, ub, rb);
+        const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
+        double s = 0.0;
+        for (int c = 0; c < 2; ++c) {
+            const double w = 6.0 * zeta(i) * cub * (double)rho[c * P.N + n];
+            s += 2.0 * (double)fout[(long long)(c * Q + opp(i)) * P.N + n] + w;
+        }
+        const double dp[3] = {cx(i) * s, cy(i) * s, cz(i) * s};
+        v[0] += dp[0];
+        v[1] += dp[1];
+        v[2] += dp[2];
+        v[3] += rb[1] * dp[2] - rb[2] * dp[1];
+        v[4] += rb[2] * dp[0] - rb[0] * dp[2];
+        v[5] += rb[0] * dp[1] - rb[1] * dp[0];
+    }
+    const int ns = min(D.shell_cnt[p], D.shell_cap[p]), soff = D.shell_off[p];
+    for (int k = threadIdx.x; k < ns; k += BLOCK) {
+        const long long n = D.shell[soff + k];
+        int x, y, z;
+        site_xyz(n, P, x, y, z);
+        const double pos[3] = {(double)x, (double)y, (double)z};
+        double r[3], F[3];
+        for (int a = 0; a < 3; ++a) {
+            r[a] = minimg(pos[a] - R[a], L[a]);
+            F[a] = (double)fsc[a * P.N + n];
+        }
+        v[0] += F[0];
+        v[1] += F[1];
+        v[2] += F[2];
+        v[3] += r[1] * F[2] - r[2] * F[1];
+        v[4] += r[2] * F[0] - r[0] * F[2];
+        v[5] += r[0] * F[1] - r[1] * F[0];
+    }
+    block_sum<6>(v, lds);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) {
+            D.Ffl[3 * p + a] = v[a];
+            D.Tfl[3 * p + a] = v[3 + a];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// pair forces, Eqs. (21) and (22), then the total force and torque: Hertz
+// repulsion (5/2) K (r_a + r_b - d)^(3/2) along the centre line, lubrication
+// -6 pi nu rho0 (r_a r_b/(r_a+r_b))^2 [n.(u_p - u_q)] (1/h - 1/h_c) n for gaps
+// h < h_c, h clamped at h_min.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_pair_forces(DevParams P, DevParticles D) {
+    __shared__ double lds[3 * BLOCK];
+    const int p = blockIdx.x;
+    double Rp[3], Up[3];
+    load3(D.R, p, Rp);
+    load3(D.U, p, Up);
+    const double rp = D.rad[p];
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    double F[3] = {0, 0, 0};
+    for (int q = threadIdx.x; q < P.np; q += BLOCK) {
+        if (q == p) continue;
+        double d[3], dist2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = minimg(D.R[3 * q + a] - Rp[a], L[a]);
+            dist2 += d[a] * d[a];
+        }
+        const double rsum = rp + D.rad[q];
+        const double reach = rsum + (P.lub_hc > 0.0 ? P.lub_hc : 0.0);
+        if (dist2 >= reach * reach) continue;
+        const double dist = sqrt(dist2);
+        if (dist <= 0.0) continue;
+        const double nh[3] = {d[0] / dist, d[1] / dist, d[2] / dist};
+        if (dist < rsum) {
+            const double fh = 2.5 * P.k_hertz * pow(rsum - dist, 1.5);
+            for (int a = 0; a < 3; ++a) F[a] -= fh * nh[a];
+        }
+        const double h = dist - rsum;
+        if (P.lub_hc > 0.0 && h < P.lub_hc) {
+            const double hh = h < P.lub_hmin ? P.lub_hmin : h;
+            const double ared = rp * D.rad[q] / rsum;
+            const double coef = 6.0 * M_PI * P.nu * P.rho0 * ared * ared;
+            double vrel = 0.0;
+            for (int a = 0; a < 3; ++a) vrel += nh[a] * (Up[a] - D.U[3 * q + a]);
+            const double fl = -coef * vrel * (1.0 / hh - 1.0 / P.lub_hc);
+            for (int a = 0; a < 3; ++a) F[a] += fl * nh[a];
+        }
+    }
+    block_sum<3>(F, lds);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) {
+            D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + F[a];
+            D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
+        }
+}
+
+// leap-frog of Eqs. (9), (10): U(t+1/2) = U(t-1/2) + F/m, R(t+1) = R(t) + U,
+// Omega(t+1/2) = Omega(t-1/2) + D/J; the pending impulses are consumed
+__global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= P.np) return;
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    double step2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        D.Rprev[3 * p + a] = D.R[3 * p + a];
+        if (!D.prescribed[p]) {
+            D.U[3 * p + a] += D.Ftot[3 * p + a] / D.mass[p];
+            D.W[3 * p + a] += D.Ttot[3 * p + a] / D.inertia[p];
+        }
+        double r = D.R[3 * p + a] + D.U[3 * p + a];
+        if (r >= L[a]) r -= L[a];
+        if (r < 0.0) r += L[a];
+        D.R[3 * p + a] = r;
+        D.P[3 * p + a] = 0.0;
+        D.PT[3 * p + a] = 0.0;
+        step2 += D.U[3 * p + a] * D.U[3 * p + a];
+    }
+    if (!(step2 < 1.0)) atomicOr(&st->overflow, 8);
+}
+
+// ---------------------------------------------------------------------------
+// solid map: every site inside sphere p (at its current position) proposes p;
+// the lowest index wins.  stage[] holds STAGE_NONE everywhere else.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage) {
+    const int p = blockIdx.x;
+    int lo[3], ext[3];
+    new_box(P, D, p, lo, ext);
+    long long cq[3];
+    for (int a = 0; a < 3; ++a) cq[a] = fixed20(D.R[3 * p + a]);
+    const long long rq = fixed20(D.rad[p]);
+    const long long r2q = rq * rq;
+    const int V = ext[0] * ext[1] * ext[2];
+    for (int k = threadIdx.x; k < V; k += BLOCK) {
+        int x, y, z;
+        box_site(k, lo, ext, P, x, y, z);
+        if (inside_sphere(x, y, z, cq, r2q, P.nx, P.ny, P.nz)) atomicMin(&stage[site_of(x, y, z, P)], p);
+    }
+}
+
+// covered (fluid -> inside p) and uncovered (inside p -> fluid) sites of
+// sphere p, listed in scan order of its box
+__global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                      const int32_t *__restrict__ stage, DevState *st) {
+    __shared__ int lds[8];
+    const int p = blockIdx.x;
+    int lo[3], ext[3];
+    union_box(P, D, p, 0, lo, ext);
+    const int V = ext[0] * ext[1] * ext[2];
+    const int off = D.ev_off[p], cap = D.ev_cap[p];
+    int ncov = 0, nunc = 0;
+    for (int start = 0; start < V; start += BLOCK) {
+        const int k = start + threadIdx.x;
+        bool cov = false, unc = false;
+        long long n = 0;
+        if (k < V) {
+            int x, y, z;
+            box_site(k, lo, ext, P, x, y, z);
+            n = site_of(x, y, z, P);
+            const int32_t o = owner[n], s = stage[n];
+            cov = (o == OWN_FLUID && s == p);
+            unc = (o == p && s == STAGE_NONE);
+        }
+        int slot = block_compact(cov, ncov, lds);
+        if (cov && slot < cap) D.cov[off + slot] = (int32_t)n;
+        slot = block_compact(unc, nunc, lds);
+        if (unc && slot < cap) D.unc[off + slot] = (int32_t)n;
+    }
+    if (threadIdx.x == 0) {
+        D.cov_cnt[p] = ncov;
+        D.unc_cnt[p] = nunc;
+        if (ncov > cap || nunc > cap) atomicOr(&st->overflow, 4);
+    }
+}
+
+// Covering, Eq. (18): the fluid of a covered site is removed and its momentum
+// goes to the sphere.  Refilling, Eqs. (23)-(26), (31): an uncovered site gets
+// f^eq(rho_new, u_surf) with rho_new^c the mean of rho^c(t+1) over its
+// neighbours that are fluid before and after the move, scaled by the mass
+// correction; the sphere loses the created momentum.  Both impulses are
+// applied in the next step's integration.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticles D, T *__restrict__ f,
+                                                        const int32_t *__restrict__ owner,
+                                                        const int32_t *__restrict__ stage, DevState *st) {
+    __shared__ double lds[6 * BLOCK];
+    const int p = blockIdx.x;
+    const long long N = P.N;
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    double R[3], U[3], W[3];
+    load3(D.R, p, R);
+    load3(D.U, p, U);
+    load3(D.W, p, W);
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    const int off = D.ev_off[p], cap = D.ev_cap[p];
+    const int nc = min(D.cov_cnt[p], cap), nu = min(D.unc_cnt[p], cap);
+    for (int k = threadIdx.x; k < nc; k += BLOCK) {
+        const long long n = D.cov[off + k];
+        int x, y, z;
+        site_xyz(n, P, x, y, z);
+        double mom[3] = {0, 0, 0};
+        for (int c = 0; c < 2; ++c)
+            for (int i = 0; i < Q; ++i) {
+                T *fp = &f[(long long)(c * Q + i) * N + n];
+                const double fi = (double)*fp;
+                mom[0] += fi * cx(i);
+                mom[1] += fi * cy(i);
+                mom[2] += fi * cz(i);
+                *fp = (T)0;
+            }
+        const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
+        for (int a = 0; a < 3; ++a) v[a] += mom[a];
+        v[3] += r[1] * mom[2] - r[2] * mom[1];
+        v[4] += r[2] * mom[0] - r[0] * mom[2];
+        v[5] += r[0] * mom[1] - r[1] * mom[0];
+    }
+    const double sumrinit = P.rho_init[0] + P.rho_init[1];
+    int fallback = 0;
+    for (int k = threadIdx.x; k < nu; k += BLOCK) {
+        const long long n = D.unc[off + k];
+        int x, y, z;
+        site_xyz(n, P, x, y, z);
+        double rbar[2] = {0.0, 0.0};
+        int cnt = 0;
+        for (int i = 1; i < Q; ++i) {
+            const long long m = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
+            if (owner[m] != OWN_FLUID || stage[m] != STAGE_NONE) continue;
+            ++cnt;
+            for (int c = 0; c < 2; ++c) {
+                double r = 0.0;
+                for (int q = 0; q < Q; ++q) r += (double)f[(long long)(c * Q + q) * N + m];
+                rbar[c] += r;
+            }
+        }
+        double rnew[2];
+        for (int c = 0; c < 2; ++c) {
+            rnew[c] = cnt > 0 ? rbar[c] / cnt : P.rho_init[c];
+            if (P.c0 != 0.0 && P.rho_init[c] > 0.0) {
+                const double dM = st->Mstep[c] - st->M0[c];
+                rnew[c] *= 1.0 - P.c0 * (sumrinit / P.rho_init[c]) * dM / (double)N;
+            }
+        }
+        if (cnt == 0) ++fallback;
+        const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
+        const double us[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]), U[1] + (W[2] * r[0] - W[0] * r[2]),
+                              U[2] + (W[0] * r[1] - W[1] * r[0])};
+        const double u2 = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+        for (int c = 0; c < 2; ++c)
+            for (int i = 0; i < Q; ++i)
+                f[(long long)(c * Q + i) * N + n] = (T)feq_dir<double>(i, rnew[c], us[0], us[1], us[2], u2, P.eq_order);
+        double mom[3];
+        for (int a = 0; a < 3; ++a) mom[a] = (rnew[0] + rnew[1]) * us[a];
+        for (int a = 0; a < 3; ++a) v[a] -= mom[a];
+        v[3] -= r[1] * mom[2] - r[2] * mom[1];
+        v[4] -= r[2] * mom[0] - r[0] * mom[2];
+        v[5] -= r[0] * mom[1] - r[1] * mom[0];
+    }
+    if (fallback) atomicAdd(&st->refill_fallback, (unsigned long long)fallback);
+    block_sum<6>(v, lds);
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            D.P[3 * p + a] += v[a];
+            D.PT[3 * p + a] += v[3 + a];
+        }
+        atomicAdd(&st->covered_total, (unsigned long long)nc);
+        atomicAdd(&st->uncovered_total, (unsigned long long)nu);
+    }
+}
+
+// new owners of the sites in the box (identical values from every block)
+__global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles D, int32_t *__restrict__ owner,
+                                                      const int32_t *__restrict__ stage) {
+    const int p = blockIdx.x;
+    int lo[3], ext[3];
+    union_box(P, D, p, 0, lo, ext);
+    const int V = ext[0] * ext[1] * ext[2];
+    for (int k = threadIdx.x; k < V; k += BLOCK) {
+        int x, y, z;
+        box_site(k, lo, ext, P, x, y, z);
+        const long long n = site_of(x, y, z, P);
+        const int32_t s = stage[n];
+        owner[n] = s == STAGE_NONE ? OWN_FLUID : s;
+    }
+}
+
+// class words around the moved sphere; clears its marks in stage[]
+__global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                    uint32_t *__restrict__ info, int32_t *__restrict__ stage) {
+    const int p = blockIdx.x;
+    int lo[3], ext[3];
+    union_box(P, D, p, 1, lo, ext);
+    int V = ext[0] * ext[1] * ext[2];
+    for (int k = threadIdx.x; k < V; k += BLOCK) {
+        int x, y, z;
+        box_site(k, lo, ext, P, x, y, z);
+        const long long n = site_of(x, y, z, P);
+        info[n] = compute_info(n, P, owner);
+    }
+    new_box(P, D, p, lo, ext);
+    V = ext[0] * ext[1] * ext[2];
+    for (int k = threadIdx.x; k < V; k += BLOCK) {
+        int x, y, z;
+        box_site(k, lo, ext, P, x, y, z);
+        stage[site_of(x, y, z, P)] = STAGE_NONE;
+    }
+}
+
+// virtual-fluid sites and bounce-back links of sphere p on the new map
+__global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                       const uint32_t *__restrict__ info, DevState *st) {
+    __shared__ int lds[8];
+    const int p = blockIdx.x;
+    int lo[3], ext[3];
+    new_box(P, D, p, lo, ext);
+    const int V = ext[0] * ext[1] * ext[2];
+    const int soff = D.shell_off[p], scap = D.shell_cap[p];
+    const int loff = D.link_off[p], lcap = D.link_cap[p];
+    int nshell = 0, nlink = 0;
+    for (int start = 0; start < V; start += BLOCK) {
+        const int k = start + threadIdx.x;
+        bool mine = false;
+        int x = 0, y = 0, z = 0;
+        long long n = 0;
+        if (k < V) {
+            box_site(k, lo, ext, P, x, y, z);
+            n = site_of(x, y, z, P);
+            mine = owner[n] == p;
+        }
+        const bool sh = mine && site_class(info[n]) == CLS_SHELL;
+        int slot = block_compact(sh, nshell, lds);
+        if (sh && slot < scap) D.shell[soff + slot] = (int32_t)n;
+        for (int i = 1; i < Q; ++i) {
+            bool lk = false;
+            long long m = 0;
+            if (mine) {
+                m = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
+                lk = owner[m] == OWN_FLUID;
+            }
+            slot = block_compact(lk, nlink, lds);
+            if (lk && slot < lcap) D.links[loff + slot] = (m << 5) | i;
+        }
+    }
+    if (threadIdx.x == 0) {
+        D.shell_cnt[p] = nshell;
+        D.link_cnt[p] = nlink;
+        if (nlink > lcap) atomicOr(&st->overflow, 1);
+        if (nshell > scap) atomicOr(&st->overflow, 2);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers (one block per sphere unless noted)
+// ---------------------------------------------------------------------------
+void launch_particle_fluid_force(lb_handle *h, const void *fout) {
+    if (!h->np) return;
+    if (h->prm.precision == LB_FP64)
+        k_particle_fluid_force<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (const double *)fout,
+                                                                       (const double *)h->rho, (const double *)h->fsc);
+    else
+        k_particle_fluid_force<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (const float *)fout,
+                                                                      (const float *)h->rho, (const float *)h->fsc);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_pair_forces(lb_handle *h) {
+    if (!h->np) return;
+    k_pair_forces<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_integrate(lb_handle *h) {
+    if (!h->np) return;
+    k_integrate<<<(h->np + BLOCK - 1) / BLOCK, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->dstate);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_map_mark(lb_handle *h, bool) {
+    if (!h->np) return;
+    k_map_mark<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->stage);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_map_events(lb_handle *h) {
+    if (!h->np) return;
+    k_map_events<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage, h->dstate);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_cover_refill(lb_handle *h, void *fout) {
+    if (!h->np) return;
+    if (h->prm.precision == LB_FP64)
+        k_cover_refill<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (double *)fout, h->owner, h->stage,
+                                                               h->dstate);
+    else
+        k_cover_refill<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (float *)fout, h->owner, h->stage,
+                                                              h->dstate);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_map_commit(lb_handle *h) {
+    if (!h->np) return;
+    k_map_commit<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_map_info(lb_handle *h) {
+    if (!h->np) return;
+    k_map_info<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->info, h->stage);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_build_lists(lb_handle *h) {
+    if (!h->np) return;
+    k_build_lists<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->info, h->dstate);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace lbm
