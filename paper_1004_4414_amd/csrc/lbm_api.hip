@@ -86,6 +86,10 @@ void set_dev_params(lb_handle *h) {
     for (int c = 0; c < 2; ++c) {
         d.tau[c] = p.tau[c];
         d.rho_init[c] = p.rho_init[c];
+        // FP32 keeps deviations from the rest state of the mean density, which
+        // carries the small flow signal with ~50x finer resolution; FP64 keeps f
+        d.rho_ref[c] = p.precision == LB_FP32 ? p.rho_init[c] : 0.0;
+        d.psi_e[c] = p.rho0 * std::exp(-d.rho_ref[c] / p.rho0);
     }
     d.g = p.g_br;
     d.rho0 = p.rho0;
@@ -161,6 +165,7 @@ void free_particles(lb_handle *h) {
     h->np = 0;
 }
 
+// stored value of (component c, direction i) <-> population f: f = stored + zeta_i rho_ref^c
 template <typename T>
 void to_host_populations(lb_handle *h, double *out) {
     const long long N = h->N;
@@ -169,7 +174,11 @@ void to_host_populations(lb_handle *h, double *out) {
     LB_HIP_CHECK(hipMemcpyAsync(buf.data(), h->f[h->cur], buf.size() * sizeof(T), hipMemcpyDeviceToHost, h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(own.data(), h->owner, own.size() * 4, hipMemcpyDeviceToHost, h->stream));
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
-    for (size_t k = 0; k < buf.size(); ++k) out[k] = own[k % N] == OWN_FLUID ? (double)buf[k] : 0.0;
+    for (size_t k = 0; k < buf.size(); ++k) {
+        const size_t ci = k / N;
+        const double w = zeta((int)(ci % Q)) * h->dp.rho_ref[ci / Q];
+        out[k] = own[k % N] == OWN_FLUID ? (double)buf[k] + w : 0.0;
+    }
 }
 
 template <typename T>
@@ -179,7 +188,11 @@ void from_host_populations(lb_handle *h, const double *in) {
     std::vector<int32_t> own((size_t)N);
     LB_HIP_CHECK(hipMemcpyAsync(own.data(), h->owner, own.size() * 4, hipMemcpyDeviceToHost, h->stream));
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
-    for (size_t k = 0; k < buf.size(); ++k) buf[k] = own[k % N] == OWN_FLUID ? (T)in[k] : (T)0;
+    for (size_t k = 0; k < buf.size(); ++k) {
+        const size_t ci = k / N;
+        const double w = zeta((int)(ci % Q)) * h->dp.rho_ref[ci / Q];
+        buf[k] = own[k % N] == OWN_FLUID ? (T)(in[k] - w) : (T)0;
+    }
     LB_HIP_CHECK(hipMemcpyAsync(h->f[h->cur], buf.data(), buf.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
 }
@@ -395,6 +408,8 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
         double rmax = *std::max_element(rad.begin(), rad.end());
         int nc[3];
         for (int a = 0; a < 3; ++a) nc[a] = std::max(1, (int)(L[a] / (2 * rmax)));
+        // fewer than 3 cells along an axis: one cell holds everything (brute force)
+        if (nc[0] < 3 || nc[1] < 3 || nc[2] < 3) nc[0] = nc[1] = nc[2] = 1;
         std::vector<std::vector<int>> cells((size_t)nc[0] * nc[1] * nc[2]);
         auto cell_of = [&](int p, int a) { return std::min(nc[a] - 1, (int)(pos[3 * p + a] / L[a] * nc[a])); };
         for (int p = 0; p < tot; ++p)
@@ -404,7 +419,7 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
             for (int dz = -1; dz <= 1; ++dz)
                 for (int dy = -1; dy <= 1; ++dy)
                     for (int dx = -1; dx <= 1; ++dx) {
-                        if ((nc[0] < 3 && dx) || (nc[1] < 3 && dy) || (nc[2] < 3 && dz)) continue;
+                        if (nc[0] == 1 && (dx || dy || dz)) continue;
                         const size_t ci = ((size_t)((c2 + dz + nc[2]) % nc[2]) * nc[1] + (c1 + dy + nc[1]) % nc[1]) *
                                               nc[0] + (c0 + dx + nc[0]) % nc[0];
                         for (int q : cells[ci]) {

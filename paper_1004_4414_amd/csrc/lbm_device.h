@@ -50,6 +50,8 @@ struct DevParams {
     double g, rho0, w_face, w_edge;
     int velocity_mode, eq_order, wall_axis, pad;
     double rho_init[2];
+    double rho_ref[2];  // populations are stored as f_i - zeta_i rho_ref^c
+    double psi_e[2];    // rho0 exp(-rho_ref^c / rho0): Psi(rho_ref + d) - Psi(rho_ref) = -psi_e expm1(-d/rho0)
     double body[3];
     double wall_vel[2][3];
     double c0;
@@ -94,8 +96,23 @@ __device__ __forceinline__ C feq_dir(int i, C rho, C ux, C uy, C uz, C u2, int o
     return C(zeta(i)) * rho * b;
 }
 
+// f^eq_i - zeta_i rho_ref = zeta_i [ (rho - rho_ref) + rho (bracket - 1) ]: the
+// equilibrium as a deviation from the stored reference, all terms small
+template <typename C>
+__device__ __forceinline__ C feq_dev_dir(int i, C drho, C rho, C ux, C uy, C uz, C u2, int order) {
+    const C cu = C(cx(i)) * ux + C(cy(i)) * uy + C(cz(i)) * uz;
+    C b = C(3) * cu + C(4.5) * cu * cu - C(1.5) * u2;
+    if (order >= 3) b += C(4.5) * cu * cu * cu - C(4.5) * u2 * cu;
+    return C(zeta(i)) * (drho + rho * b);
+}
+
 template <typename C>
 __device__ __forceinline__ C psi_of(C rho, C rho0) { return rho0 * (C(1) - exp(-rho / rho0)); }
+
+// Psi(rho_ref + d) - Psi(rho_ref) from the density deviation d; the neighbour
+// sum of Eq. (4) only sees differences of Psi because sum_i W_i c_i = 0
+template <typename C>
+__device__ __forceinline__ C psi_dev(C d, C e, C rho0) { return -e * expm1(-d / rho0); }
 
 // ---------------------------------------------------------------------------
 // Sphere discretisation: site inside iff |x - R|^2 < r^2, evaluated on the

@@ -38,10 +38,12 @@ __global__ void k_init_owner(DevParams P, int32_t *owner) {
     owner[n] = o;
 }
 
-// initial densities rho^c = rho_init^c + noise (2U - 1), f = zeta_i rho^c
+// initial densities rho^c = rho_init^c + noise (2U - 1), f = zeta_i rho^c,
+// stored as f - zeta_i rho_ref^c
 template <typename T>
 __global__ void k_init_fluid(DevParams P, uint64_t seed, double noise, const int32_t *__restrict__ owner,
                              T *__restrict__ f) {
+#pragma clang fp contract(off)
     const long long n = (long long)blockIdx.x * BLOCK + threadIdx.x;
     if (n >= P.N) return;
     const bool fluid = owner[n] == OWN_FLUID;
@@ -51,7 +53,8 @@ __global__ void k_init_fluid(DevParams P, uint64_t seed, double noise, const int
                          (1.0 / 9007199254740992.0);
         const double r = P.rho_init[c] + noise * (2.0 * U - 1.0);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[(long long)(c * Q + i) * P.N + n] = fluid ? (T)(zeta(i) * r) : (T)0;
+        for (int i = 0; i < Q; ++i)
+            f[(long long)(c * Q + i) * P.N + n] = fluid ? (T)(zeta(i) * r - zeta(i) * P.rho_ref[c]) : (T)0;
     }
 }
 
@@ -80,8 +83,9 @@ __global__ void k_zero_solid(DevParams P, const int32_t *__restrict__ owner, T *
 }
 
 // ---------------------------------------------------------------------------
-// densities rho^c = sum_i f_i^c on fluid sites (0 elsewhere), optionally with
-// per-block FP64 partial sums of the fluid mass
+// density deviations rho^c - rho_ref^c = sum_i d_i^c on fluid sites (and
+// -rho_ref^c, i.e. rho = 0, elsewhere), optionally with per-block FP64 partial
+// sums of the fluid mass
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const T *__restrict__ f,
@@ -94,13 +98,14 @@ __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const T *__restr
         const bool fluid = site_class(info[n]) == CLS_FLUID;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            T r = 0;
+            T dr = -(T)P.rho_ref[c];
             if (fluid) {
+                dr = 0;
 #pragma unroll
-                for (int i = 0; i < Q; ++i) r += f[(long long)(c * Q + i) * P.N + n];
+                for (int i = 0; i < Q; ++i) dr += f[(long long)(c * Q + i) * P.N + n];
+                m[c] = (double)dr + P.rho_ref[c];
             }
-            rho[c * P.N + n] = r;
-            m[c] = (double)r;
+            rho[c * P.N + n] = dr;
         }
     }
     if (partial) {
@@ -136,7 +141,7 @@ __global__ void k_finalize_mass(const double *__restrict__ partial, int nb, DevS
 // ---------------------------------------------------------------------------
 // virtual fluid (Sec. IV): on every shell site of particle p, rho^c is the mean
 // of rho^c over its fluid 18-neighbours plus |colour| on the preferred
-// component; written into the density array in place.
+// component; written into the (deviation) density array in place.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_shell_fill(DevParams P, DevParticles D, const uint32_t *__restrict__ info,
@@ -167,11 +172,13 @@ __global__ __launch_bounds__(BLOCK) void k_shell_fill(DevParams P, DevParticles 
     }
 }
 
-// acc[c][a] = sum_{i=1..18} W_i Psi^c(x + c_i) c_ia from the density array
+// acc[c][a] = sum_{i=1..18} W_i Psi^c(x + c_i) c_ia from the density-deviation
+// array, with Psi^c(x + c_i) - Psi^c(rho_ref) in place of Psi^c (same sum)
 template <typename T>
 __device__ __forceinline__ void neighbour_psi_sum(const T *__restrict__ rho, const DevParams &P, int x, int y, int z,
                                                   T acc[2][3]) {
     const T rho0 = (T)P.rho0;
+    const T e[2] = {(T)P.psi_e[0], (T)P.psi_e[1]};
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc[c][0] = acc[c][1] = acc[c][2] = 0;
 #pragma unroll
@@ -180,7 +187,7 @@ __device__ __forceinline__ void neighbour_psi_sum(const T *__restrict__ rho, con
         const T w = norm2(i) == 1 ? (T)P.w_face : (T)P.w_edge;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const T wp = w * psi_of(rho[c * P.N + m], rho0);
+            const T wp = w * psi_dev(rho[c * P.N + m], e[c], rho0);
             if (cx(i)) acc[c][0] += cx(i) > 0 ? wp : -wp;
             if (cy(i)) acc[c][1] += cy(i) > 0 ? wp : -wp;
             if (cz(i)) acc[c][2] += cz(i) > 0 ? wp : -wp;
@@ -188,12 +195,15 @@ __device__ __forceinline__ void neighbour_psi_sum(const T *__restrict__ rho, con
     }
 }
 
-// moments of one component: rho, and j summed over opposite pairs
+// moments of one component from its stored values d_i = f_i - zeta_i rho_ref:
+// dr = sum_i d_i, rho = dr + rho_ref, and j summed over opposite pairs (the
+// reference part cancels exactly)
 template <typename T>
-__device__ __forceinline__ void moments(const T (&f)[Q], T &r, T &jx, T &jy, T &jz) {
-    r = 0;
+__device__ __forceinline__ void moments(const T (&f)[Q], T ref, T &dr, T &r, T &jx, T &jy, T &jz) {
+    dr = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) r += f[i];
+    for (int i = 0; i < Q; ++i) dr += f[i];
+    r = dr + ref;
     jx = jy = jz = 0;
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
@@ -255,7 +265,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide_stream(DevParams P, DevPartic
     T acc[2][3];
     neighbour_psi_sum(rho, P, x, y, z, acc);
     if (cls == CLS_SHELL) {
-        const T ps0 = psi_of(rho[n], rho0), ps1 = psi_of(rho[P.N + n], rho0);
+        const T ps0 = psi_of(rho[n] + (T)P.rho_ref[0], rho0), ps1 = psi_of(rho[P.N + n] + (T)P.rho_ref[1], rho0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) fsc[a * P.N + n] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
         return;
@@ -265,9 +275,9 @@ __global__ __launch_bounds__(BLOCK) void k_collide_stream(DevParams P, DevPartic
     for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[c][i] = fin[(long long)(c * Q + i) * P.N + n];
-    T r[2], j[2][3], F[2][3];
+    T dr[2], r[2], j[2][3], F[2][3];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) moments(f[c], r[c], j[c][0], j[c][1], j[c][2]);
+    for (int c = 0; c < 2; ++c) moments(f[c], (T)P.rho_ref[c], dr[c], r[c], j[c][0], j[c][1], j[c][2]);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const T ps = psi_of(r[c], rho0);
@@ -283,7 +293,8 @@ __global__ __launch_bounds__(BLOCK) void k_collide_stream(DevParams P, DevPartic
         const T ux = ueq[c][0], uy = ueq[c][1], uz = ueq[c][2];
         const T u2 = ux * ux + uy * uy + uz * uz;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[c][i] = f[c][i] - (f[c][i] - feq_dir<T>(i, r[c], ux, uy, uz, u2, order)) * omega;
+        for (int i = 0; i < Q; ++i)
+            f[c][i] = f[c][i] - (f[c][i] - feq_dev_dir<T>(i, dr[c], r[c], ux, uy, uz, u2, order)) * omega;
     }
     // push: f*_i(x) -> f_i(x + c_i), or bounced back into f_opp(i)(x)
 #pragma unroll
@@ -333,7 +344,7 @@ __global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const T *__restri
     T acc[2][3];
     neighbour_psi_sum(rho, P, x, y, z, acc);
     if (cls == CLS_SHELL) {
-        const T ps0 = psi_of(rho[n], rho0), ps1 = psi_of(rho[N + n], rho0);
+        const T ps0 = psi_of(rho[n] + (T)P.rho_ref[0], rho0), ps1 = psi_of(rho[N + n] + (T)P.rho_ref[1], rho0);
         for (int a = 0; a < 3; ++a) {
             oF[(0 * N + n) * 3 + a] = (double)(-ps0 * g * acc[1][a]);
             oF[(1 * N + n) * 3 + a] = (double)(-ps1 * g * acc[0][a]);
@@ -345,9 +356,9 @@ __global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const T *__restri
     for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[c][i] = fin[(long long)(c * Q + i) * N + n];
-    T r[2], j[2][3], F[2][3];
+    T dr[2], r[2], j[2][3], F[2][3];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) moments(f[c], r[c], j[c][0], j[c][1], j[c][2]);
+    for (int c = 0; c < 2; ++c) moments(f[c], (T)P.rho_ref[c], dr[c], r[c], j[c][0], j[c][1], j[c][2]);
     for (int c = 0; c < 2; ++c) {
         const T ps = psi_of(r[c], rho0);
         for (int a = 0; a < 3; ++a) F[c][a] = -ps * g * acc[1 - c][a] + r[c] * (T)P.body[a];
@@ -373,15 +384,18 @@ __global__ __launch_bounds__(BLOCK) void k_sums(DevParams P, const T *__restrict
     double v[5] = {0, 0, 0, 0, 0};
     if (n < P.N && site_class(info[n]) == CLS_FLUID) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < 2; ++c) {
+            double m = P.rho_ref[c];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const double fi = (double)f[(long long)(c * Q + i) * P.N + n];
-                v[c] += fi;
-                v[2] += fi * cx(i);
-                v[3] += fi * cy(i);
-                v[4] += fi * cz(i);
+                const double di = (double)f[(long long)(c * Q + i) * P.N + n];
+                m += di;
+                v[2] += di * cx(i);
+                v[3] += di * cy(i);
+                v[4] += di * cz(i);
             }
+            v[c] += m;
+        }
     }
     block_sum<5>(v, lds);
     if (threadIdx.x == 0)

@@ -89,8 +89,9 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
         const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
         double s = 0.0;
         for (int c = 0; c < 2; ++c) {
-            const double w = 6.0 * zeta(i) * cub * (double)rho[c * P.N + n];
-            s += 2.0 * (double)fout[(long long)(c * Q + opp(i)) * P.N + n] + w;
+            const double w = 6.0 * zeta(i) * cub * ((double)rho[c * P.N + n] + P.rho_ref[c]);
+            const double fo = (double)fout[(long long)(c * Q + opp(i)) * P.N + n] + zeta(i) * P.rho_ref[c];
+            s += 2.0 * fo + w;
         }
         const double dp[3] = {cx(i) * s, cy(i) * s, cz(i) * s};
         v[0] += dp[0];
@@ -281,14 +282,14 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
         const long long n = D.cov[off + k];
         int x, y, z;
         site_xyz(n, P, x, y, z);
-        double mom[3] = {0, 0, 0};
+        double mom[3] = {0, 0, 0};  // the reference part of the stored values has no momentum
         for (int c = 0; c < 2; ++c)
             for (int i = 0; i < Q; ++i) {
                 T *fp = &f[(long long)(c * Q + i) * N + n];
-                const double fi = (double)*fp;
-                mom[0] += fi * cx(i);
-                mom[1] += fi * cy(i);
-                mom[2] += fi * cz(i);
+                const double di = (double)*fp;
+                mom[0] += di * cx(i);
+                mom[1] += di * cy(i);
+                mom[2] += di * cz(i);
                 *fp = (T)0;
             }
         const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
             for (int c = 0; c < 2; ++c) {
                 double r = 0.0;
                 for (int q = 0; q < Q; ++q) r += (double)f[(long long)(c * Q + q) * N + m];
-                rbar[c] += r;
+                rbar[c] += r + P.rho_ref[c];
             }
         }
         double rnew[2];
@@ -330,7 +331,8 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
         const double u2 = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
         for (int c = 0; c < 2; ++c)
             for (int i = 0; i < Q; ++i)
-                f[(long long)(c * Q + i) * N + n] = (T)feq_dir<double>(i, rnew[c], us[0], us[1], us[2], u2, P.eq_order);
+                f[(long long)(c * Q + i) * N + n] =
+                    (T)(feq_dir<double>(i, rnew[c], us[0], us[1], us[2], u2, P.eq_order) - zeta(i) * P.rho_ref[c]);
         double mom[3];
         for (int a = 0; a < 3; ++a) mom[a] = (rnew[0] + rnew[1]) * us[a];
         for (int a = 0; a < 3; ++a) v[a] -= mom[a];

@@ -80,8 +80,10 @@ def test_initial_state_matches_the_oracle():
     ref = Oracle(p).populations()
     g64 = lbm().Lattice(p, precision="fp64").populations()
     assert np.array_equal(g64, ref)
+    # FP32 stores f - zeta_i rho_init^c: the round trip is exact to the
+    # resolution of that deviation (|d| <= zeta_0 * noise)
     g32 = lbm().Lattice(p, precision="fp32").populations()
-    assert np.array_equal(g32, ref.astype(np.float32).astype(np.float64))
+    assert np.abs(g32 - ref).max() < 1e-9
 
 
 @pytest.mark.parametrize("kernel", ["twopass"])
