@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--workload", default="bijel256")
+    ap.add_argument("--tile", default="0,0,0", help="fused-kernel tile TX,TY,TZ (0 = automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -77,7 +78,8 @@ def main():
 
     p, parts, _, precision = W.config(args.workload)
     N = p["nx"] * p["ny"] * p["nz"]
-    lat = lbm.Lattice(p, precision=precision, kernel=args.kernel)
+    tile = tuple(int(v) for v in args.tile.split(","))
+    lat = lbm.Lattice(p, precision=precision, kernel=args.kernel, tile=tile)
     lat.add_particles(parts)
     print(f"# workload {args.workload}: {p['nx']}x{p['ny']}x{p['nz']}, {len(parts['radius'])} spheres, "
           f"{precision}, kernel {args.kernel}", file=sys.stderr, flush=True)
@@ -121,6 +123,7 @@ def main():
             "sites": N,
             "spheres": len(parts["radius"]),
             "kernel": args.kernel,
+            "tile": args.tile,
         },
         "roofline": {
             "bound": "hbm",

@@ -90,7 +90,11 @@ void set_dev_params(lb_handle *h) {
         // carries the small flow signal with ~50x finer resolution; FP64 keeps f
         d.rho_ref[c] = p.precision == LB_FP32 ? p.rho_init[c] : 0.0;
         d.psi_e[c] = p.rho0 * std::exp(-d.rho_ref[c] / p.rho0);
+        d.inv_tau[c] = 1.0 / p.tau[c];
     }
+    d.inv_rho0 = 1.0 / p.rho0;
+    d.div_nx = make_fastdiv((uint32_t)p.nx);
+    d.div_nxy = make_fastdiv((uint32_t)p.nx * (uint32_t)p.ny);
     d.g = p.g_br;
     d.rho0 = p.rho0;
     d.w_face = p.w_face;
@@ -130,8 +134,9 @@ size_t fluid_bytes(const lb_params *p) {
     const long long N = (long long)p->nx * p->ny * p->nz;
     const size_t ts = p->precision == LB_FP64 ? 8 : 4;
     size_t b = 0;
-    b += 2 * (size_t)(2 * Q) * N * ts;  // two population buffers
-    b += 5 * (size_t)N * ts;            // densities, shell force
+    const size_t Np = padded_sites(N);
+    b += 2 * (size_t)(2 * Q) * Np * ts;  // two population buffers
+    b += 7 * Np * ts;                    // densities, Psi, shell force
     b += 3 * (size_t)N * 4;             // info, owner, stage
     b += 5 * (size_t)nblk(N) * 8 + 4096;
     return b;
@@ -169,30 +174,49 @@ void free_particles(lb_handle *h) {
 template <typename T>
 void to_host_populations(lb_handle *h, double *out) {
     const long long N = h->N;
-    std::vector<T> buf((size_t)2 * Q * N);
+    std::vector<T> buf((size_t)2 * Q * padded_sites(N));
     std::vector<int32_t> own((size_t)N);
     LB_HIP_CHECK(hipMemcpyAsync(buf.data(), h->f[h->cur], buf.size() * sizeof(T), hipMemcpyDeviceToHost, h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(own.data(), h->owner, own.size() * 4, hipMemcpyDeviceToHost, h->stream));
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
-    for (size_t k = 0; k < buf.size(); ++k) {
-        const size_t ci = k / N;
-        const double w = zeta((int)(ci % Q)) * h->dp.rho_ref[ci / Q];
-        out[k] = own[k % N] == OWN_FLUID ? (double)buf[k] + w : 0.0;
-    }
+    const int nx = h->prm.nx, ny = h->prm.ny, nz = h->prm.nz;
+    for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < Q; ++i) {
+            const double w = zeta(i) * h->dp.rho_ref[c];
+            double *dst = out + (size_t)(c * Q + i) * N;
+            for (int z = 0; z < nz; ++z)
+                for (int y = 0; y < ny; ++y)
+                    for (int x = 0; x < nx; ++x) {
+                        const long long n = ((long long)z * ny + y) * nx + x;
+                        const long long src = ((long long)((z - cz(i) + nz) % nz) * ny + (y - cy(i) + ny) % ny) * nx +
+                                              (x - cx(i) + nx) % nx;  // f_i(x) = slot (i, x - c_i)
+                        dst[n] = own[n] == OWN_FLUID ? (double)buf[pidx(c, i, (unsigned)src)] + w : 0.0;
+                    }
+        }
 }
 
 template <typename T>
 void from_host_populations(lb_handle *h, const double *in) {
     const long long N = h->N;
-    std::vector<T> buf((size_t)2 * Q * N);
+    std::vector<T> buf((size_t)2 * Q * padded_sites(N));
     std::vector<int32_t> own((size_t)N);
     LB_HIP_CHECK(hipMemcpyAsync(own.data(), h->owner, own.size() * 4, hipMemcpyDeviceToHost, h->stream));
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
-    for (size_t k = 0; k < buf.size(); ++k) {
-        const size_t ci = k / N;
-        const double w = zeta((int)(ci % Q)) * h->dp.rho_ref[ci / Q];
-        buf[k] = own[k % N] == OWN_FLUID ? (T)(in[k] - w) : (T)0;
-    }
+    const int nx = h->prm.nx, ny = h->prm.ny, nz = h->prm.nz;
+    for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < Q; ++i) {
+            const double w = zeta(i) * h->dp.rho_ref[c];
+            const double *src = in + (size_t)(c * Q + i) * N;
+            for (int z = 0; z < nz; ++z)
+                for (int y = 0; y < ny; ++y)
+                    for (int x = 0; x < nx; ++x) {
+                        const long long n = ((long long)z * ny + y) * nx + x;
+                        if (own[n] != OWN_FLUID) continue;
+                        const long long dst = ((long long)((z - cz(i) + nz) % nz) * ny + (y - cy(i) + ny) % ny) * nx +
+                                              (x - cx(i) + nx) % nx;
+                        buf[pidx(c, i, (unsigned)dst)] = (T)(src[n] - w);
+                    }
+        }
     LB_HIP_CHECK(hipMemcpyAsync(h->f[h->cur], buf.data(), buf.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
 }
@@ -207,17 +231,48 @@ int check_device_state(lb_handle *h) {
     return LB_OK;
 }
 
+// fused-kernel tile: explicit request, else the widest of the compiled shapes
+// that fits the box in x
+void choose_fused_tile(lb_handle *h) {
+    const lb_params &p = h->prm;
+    int tx = p.tile[0], ty = p.tile[1], tz = p.tile[2];
+    // compiled shapes; a tile must satisfy tx <= nx - 2, ty <= ny - 2
+    auto fits = [&](int a, int b) { return a <= p.nx - 2 && b <= p.ny - 2; };
+    bool known;
+    if (p.precision == LB_FP64)
+        known = (tx == 32 && ty == 4) || (tx == 64 && ty == 4) || (tx == 16 && ty == 8);
+    else
+        known = (tx == 64 && ty == 4) || (tx == 64 && ty == 8) || (tx == 32 && ty == 8) || (tx == 32 && ty == 4) ||
+                (tx == 128 && ty == 2) || (tx == 16 && ty == 8);
+    if (!known || !fits(tx, ty)) {
+        if (p.precision != LB_FP64 && fits(64, 4)) tx = 64, ty = 4;
+        else if (fits(32, 4)) tx = 32, ty = 4;
+        else tx = 16, ty = 8;
+    }
+    if (tz <= 0) tz = 32;
+    h->fused_tx = tx;
+    h->fused_ty = ty;
+    h->fused_tz = std::max(1, std::min(tz, p.nz - 1));
+}
+
 void one_step(lb_handle *h) {
     void *fin = h->f[h->cur], *fout = h->f[1 - h->cur];
     hipEvent_t t_step = h->timing_begin(2);
-    hipEvent_t t_den = h->timing_begin(1);
-    launch_density(h, fin, true);
-    h->timing_end(1, t_den);
-    launch_finalize_mass(h);
-    launch_shell_fill(h);
-    hipEvent_t t_col = h->timing_begin(0);
-    launch_collide_stream(h, fin, fout);
-    h->timing_end(0, t_col);
+    if (h->kernel == LB_KERNEL_FUSED) {
+        hipEvent_t t_col = h->timing_begin(0);
+        launch_fused(h, fin, fout);
+        h->timing_end(0, t_col);
+        launch_finalize_mass_n(h, h->n_fused_blocks);
+    } else {
+        hipEvent_t t_den = h->timing_begin(1);
+        launch_density(h, fin, true);
+        h->timing_end(1, t_den);
+        launch_finalize_mass(h);
+        launch_shell_fill(h);
+        hipEvent_t t_col = h->timing_begin(0);
+        launch_collide_stream(h, fin, fout);
+        h->timing_end(0, t_col);
+    }
     if (h->np) {
         launch_particle_fluid_force(h, fout);
         launch_pair_forces(h);
@@ -313,20 +368,29 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
     }
     h->N = (long long)p->nx * p->ny * p->nz;
     h->tsize = p->precision == LB_FP64 ? 8 : 4;
-    h->kernel = p->kernel == LB_KERNEL_AUTO ? LB_KERNEL_TWOPASS : p->kernel;
+    if (p->kernel == LB_KERNEL_FUSED && !fused_supported(*p)) {
+        delete h;
+        return LB_EINVAL;
+    }
+    h->kernel = p->kernel == LB_KERNEL_AUTO ? (fused_supported(*p) ? LB_KERNEL_FUSED : LB_KERNEL_TWOPASS) : p->kernel;
     for (int a = 0; a < 3; ++a) h->tile[a] = p->tile[a];
+    choose_fused_tile(h);
     set_dev_params(h);
     try {
-        const size_t fsz = (size_t)2 * Q * h->N * h->tsize;
+        const size_t Np = padded_sites(h->N);
+        const size_t fsz = (size_t)2 * Q * Np * h->tsize;
         h->f[0] = dev_alloc(h, fsz);
         h->f[1] = dev_alloc(h, fsz);
-        h->rho = dev_alloc(h, (size_t)2 * h->N * h->tsize);
-        h->fsc = dev_alloc(h, (size_t)3 * h->N * h->tsize);
+        h->rho = dev_alloc(h, (size_t)2 * Np * h->tsize);
+        h->psi = dev_alloc(h, (size_t)2 * Np * h->tsize);
+        h->fsc = dev_alloc(h, (size_t)3 * Np * h->tsize);
         h->info = (uint32_t *)dev_alloc(h, (size_t)h->N * 4);
         h->owner = (int32_t *)dev_alloc(h, (size_t)h->N * 4);
         h->stage = (int32_t *)dev_alloc(h, (size_t)h->N * 4);
         h->n_partial = (int)nblk(h->N);
-        h->partial = (double *)dev_alloc(h, (size_t)5 * h->n_partial * 8);
+        const long long nfused = (long long)((p->nx + h->fused_tx - 1) / h->fused_tx) *
+                                 ((p->ny + h->fused_ty - 1) / h->fused_ty) * ((p->nz + h->fused_tz - 1) / h->fused_tz);
+        h->partial = (double *)dev_alloc(h, (size_t)std::max(5LL * h->n_partial, 2 * nfused + 16) * 8);
         h->dstate = (DevState *)dev_alloc(h, sizeof(DevState));
         LB_HIP_CHECK(hipMemsetAsync(h->dstate, 0, sizeof(DevState), h->stream));
         LB_HIP_CHECK(hipMemsetAsync(h->f[1], 0, fsz, h->stream));
@@ -523,8 +587,7 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     h->h_color = col;
     h->h_prescribed = pre;
     set_dev_params(h);
-    rebuild_map(h);
-    launch_zero_solid(h, h->f[h->cur]);  // the fluid inside the spheres is removed
+    rebuild_map(h);  // the fluid inside the spheres is no longer read: it is removed
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
     return check_device_state(h);
     LB_API_END
@@ -687,7 +750,6 @@ int lb_set_particle_state(lb_handle *h, const double *state) {
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.W, W.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.P, P.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.PT, PT.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
-    launch_zero_solid(h, h->f[h->cur]);
     rebuild_map(h);
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
     return check_device_state(h);
@@ -712,7 +774,7 @@ int lb_particle_counts(lb_handle *h, int32_t *links, int32_t *shell) {
 // R U W P PT (15 doubles) radius density colour (3 doubles) prescribed (i32)
 int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
     if (!h || !bytes) return LB_EINVAL;
-    const size_t fsz = (size_t)2 * Q * h->N * h->tsize;
+    const size_t fsz = (size_t)2 * Q * padded_sites(h->N) * h->tsize;
     const size_t need = 8 + 6 * 4 + 8 + sizeof(DevState) + fsz + (size_t)h->np * (18 * 8 + 4);
     if (!buf) {
         *bytes = need;
@@ -771,7 +833,7 @@ int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
         (int)hdr[3] != h->prm.ny || (int)hdr[4] != h->prm.nz)
         return fail(h, LB_EINVAL, "checkpoint of a different lattice");
     const int np = (int)hdr[5];
-    const size_t fsz = (size_t)2 * Q * h->N * h->tsize;
+    const size_t fsz = (size_t)2 * Q * padded_sites(h->N) * h->tsize;
     if (bytes < 8 + 24 + 8 + sizeof(DevState) + fsz + (size_t)np * (18 * 8 + 4))
         return fail(h, LB_EINVAL, "truncated checkpoint");
     LB_API_BEGIN

@@ -8,7 +8,25 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
+
+// compile-time loop: f(integral_constant<int, 0>) ... f(integral_constant<int, I-1>),
+// so that arrays indexed by the loop variable stay in registers
+template <int I>
+struct Unroll {
+    template <class F>
+    __device__ __forceinline__ static void run(F &&f) {
+        Unroll<I - 1>::run(f);
+        f(std::integral_constant<int, I - 1>{});
+    }
+};
+template <>
+struct Unroll<0> {
+    template <class F>
+    __device__ __forceinline__ static void run(F &&) {}
+};
 
 constexpr int Q = 19;
 constexpr int BLOCK = 256;  // threads per block of the generic kernels (4 wave64)
@@ -34,6 +52,50 @@ __host__ __device__ constexpr double zeta(int i) {
     return norm2(i) == 0 ? 1.0 / 3.0 : (norm2(i) == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
+// ---------------------------------------------------------------------------
+// Memory layout.  Sites are grouped in storage blocks of VB = 64 consecutive
+// linear indices (one wavefront).  A block keeps all its values together, one
+// run of 64 sites per value: population (c, i) of site n lives at
+//   (n / 64) * (2*19*64) + (c*19 + i) * 64 + n % 64,
+// so a wavefront's load of one direction is a single aligned 256-byte run and
+// the whole block spans a few pages (a plane-per-direction layout would make
+// every wavefront touch ~80 pages and thrash the L1 TLB).  Two-component
+// scalar fields and 3-vectors use the same blocking.
+// ---------------------------------------------------------------------------
+constexpr unsigned VB = 64;
+__host__ __device__ __forceinline__ size_t pidx(int c, int i, unsigned n) {
+    return (size_t)(n / VB) * (2 * Q * VB) + (size_t)(c * Q + i) * VB + (n % VB);
+}
+__host__ __device__ __forceinline__ size_t sidx(int c, unsigned n) {
+    return (size_t)(n / VB) * (2 * VB) + (size_t)c * VB + (n % VB);
+}
+__host__ __device__ __forceinline__ size_t vidx(int a, unsigned n) {
+    return (size_t)(n / VB) * (3 * VB) + (size_t)a * VB + (n % VB);
+}
+__host__ __device__ __forceinline__ size_t padded_sites(long long N) { return (size_t)((N + VB - 1) / VB) * VB; }
+
+// division of 32-bit unsigned integers by an invariant divisor d via a
+// multiply-high (Granlund & Montgomery 1994, round-up method):
+// n / d = (t + ((n - t) >> s1)) >> s2 with t = mulhi(n, m)
+struct FastDiv {
+    uint32_t d, m;
+    int s1, s2;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    FastDiv f;
+    f.d = d;
+    f.m = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 1 ? l - 1 : 0;
+    return f;
+}
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv &f) {
+    const uint32_t t = __umulhi(n, f.m);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 // per-site classification word: bits 1..18 flag the directions i whose
 // neighbour x + c_i is solid (bounce-back), bits 29..30 hold the class
 enum : uint32_t { CLS_FLUID = 0, CLS_SHELL = 1, CLS_SOLID = 2, CLS_WALL = 3 };
@@ -52,6 +114,9 @@ struct DevParams {
     double rho_init[2];
     double rho_ref[2];  // populations are stored as f_i - zeta_i rho_ref^c
     double psi_e[2];    // rho0 exp(-rho_ref^c / rho0): Psi(rho_ref + d) - Psi(rho_ref) = -psi_e expm1(-d/rho0)
+    double inv_tau[2];  // 1 / tau^c
+    double inv_rho0;    // 1 / rho0
+    FastDiv div_nx, div_nxy;
     double body[3];
     double wall_vel[2][3];
     double c0;
@@ -85,6 +150,21 @@ struct DevParticles {
 };
 
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+__device__ __forceinline__ bool dense_site(const DevParams &P, unsigned &n, int &x, int &y, int &z) {
+    const unsigned nb = gridDim.x;
+    unsigned b = blockIdx.x;
+    if (nb % 8u == 0) b = (b % 8u) * (nb / 8u) + b / 8u;
+    n = b * 256u + threadIdx.x;
+    if (n >= (unsigned)P.N) return false;
+    const unsigned zq = fast_div(n, P.div_nxy);
+    const unsigned r = n - zq * P.div_nxy.d;
+    const unsigned yq = fast_div(r, P.div_nx);
+    x = (int)(r - yq * P.div_nx.d);
+    y = (int)yq;
+    z = (int)zq;
+    return true;
+}
 __device__ __forceinline__ int wrapany(int a, int n) { a %= n; return a < 0 ? a + n : a; }
 
 // equilibrium of Eq. (3) with c_s^2 = 1/3 for one direction
@@ -106,13 +186,29 @@ __device__ __forceinline__ C feq_dev_dir(int i, C drho, C rho, C ux, C uy, C uz,
     return C(zeta(i)) * (drho + rho * b);
 }
 
-template <typename C>
-__device__ __forceinline__ C psi_of(C rho, C rho0) { return rho0 * (C(1) - exp(-rho / rho0)); }
+// exp(x) - 1 in FP32: Taylor polynomial to x^6 for |x| < 1/4 (truncation
+// below 1.3e-8 relative), the hardware exponential elsewhere
+__device__ __forceinline__ float fast_expm1(float x) {
+    if (fabsf(x) < 0.25f)
+        return x * (1.0f + x * (0.5f + x * (1.0f / 6 + x * (1.0f / 24 + x * (1.0f / 120 + x * (1.0f / 720))))));
+    return __expf(x) - 1.0f;
+}
+
+// Eq. (5): Psi = rho0 (1 - exp(-rho/rho0)); FP32 uses the hardware exponential
+__device__ __forceinline__ float psi_of(float rho, float rho0, float irho0) { return rho0 * (1.0f - __expf(-rho * irho0)); }
+__device__ __forceinline__ double psi_of(double rho, double rho0, double irho0) {
+    return rho0 * (1.0 - exp(-rho * irho0));
+}
 
 // Psi(rho_ref + d) - Psi(rho_ref) from the density deviation d; the neighbour
 // sum of Eq. (4) only sees differences of Psi because sum_i W_i c_i = 0
-template <typename C>
-__device__ __forceinline__ C psi_dev(C d, C e, C rho0) { return -e * expm1(-d / rho0); }
+__device__ __forceinline__ float psi_dev(float d, float e, float irho0) { return -e * fast_expm1(-d * irho0); }
+__device__ __forceinline__ double psi_dev(double d, double e, double irho0) { return -e * expm1(-d * irho0); }
+
+// dense launch geometry: one thread per site in linear order (a wavefront is
+// one storage block), block ids remapped so that each XCD (the hardware deals
+// block b to XCD b % 8) walks a contiguous slab of the box
+__device__ __forceinline__ bool dense_site(const struct DevParams &P, unsigned &n, int &x, int &y, int &z);
 
 // ---------------------------------------------------------------------------
 // Sphere discretisation: site inside iff |x - R|^2 < r^2, evaluated on the
@@ -158,11 +254,13 @@ __device__ __forceinline__ double minimg(double d, double L) {
 }
 
 __device__ __forceinline__ void site_xyz(long long n, const DevParams &P, int &x, int &y, int &z) {
-    const long long nxy = (long long)P.nx * P.ny;
-    z = (int)(n / nxy);
-    const int r = (int)(n - (long long)z * nxy);
-    y = r / P.nx;
-    x = r - y * P.nx;
+    const unsigned u = (unsigned)n;
+    const unsigned zq = fast_div(u, P.div_nxy);
+    const unsigned r = u - zq * P.div_nxy.d;
+    const unsigned yq = fast_div(r, P.div_nx);
+    x = (int)(r - yq * P.div_nx.d);
+    y = (int)yq;
+    z = (int)zq;
 }
 
 __device__ __forceinline__ long long site_of(int x, int y, int z, const DevParams &P) {
@@ -203,11 +301,181 @@ __device__ __forceinline__ void solid_velocity(const DevParams &P, const DevPart
         ub[1] = U[1] + (W[2] * rb[0] - W[0] * rb[2]);
         ub[2] = U[2] + (W[0] * rb[1] - W[1] * rb[0]);
     } else {
-        const int wi = own == OWN_WALL_LO ? 0 : 1;
+        const bool lo = own == OWN_WALL_LO;  // select, not a runtime index into the parameter block
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ub[a] = P.wall_vel[wi][a];
+            ub[a] = lo ? P.wall_vel[0][a] : P.wall_vel[1][a];
             rb[a] = 0.0;
+        }
+    }
+}
+
+// moments of one component from its stored values d_i = f_i - zeta_i rho_ref:
+// dr = sum_i d_i, rho = dr + rho_ref, and j summed over opposite pairs (the
+// reference part cancels exactly)
+template <typename T>
+__device__ __forceinline__ void moments(const T (&f)[Q], T ref, T &dr, T &r, T &jx, T &jy, T &jz) {
+    dr = 0;
+    Unroll<Q>::run([&](auto ic) { dr += f[decltype(ic)::value]; });
+    r = dr + ref;
+    jx = jy = jz = 0;
+    Unroll<Q / 2>::run([&](auto ic) {
+        constexpr int i = 2 * decltype(ic)::value + 1;
+        const T d = f[i] - f[i + 1];
+        if (cx(i)) jx += cx(i) > 0 ? d : -d;
+        if (cy(i)) jy += cy(i) > 0 ? d : -d;
+        if (cz(i)) jz += cz(i) > 0 ? d : -d;
+    });
+}
+
+// equilibrium velocities of both components (Sec. II, Eq. (6))
+template <typename T>
+__device__ __forceinline__ void eq_velocity(const DevParams &P, const T r[2], const T j[2][3], const T F[2][3],
+                                            T ueq[2][3]) {
+    T ubar[3] = {0, 0, 0};
+    if (P.velocity_mode == 0) {
+        const T it0 = (T)P.inv_tau[0], it1 = (T)P.inv_tau[1];
+        const T den = r[0] * it0 + r[1] * it1;
+        if (den != (T)0) {
+            const T iden = (T)1 / den;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ubar[a] = (j[0][a] * it0 + j[1][a] * it1) * iden;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T tau = (T)P.tau[c];
+        const bool live = r[c] != (T)0;
+        const T ir = live ? (T)1 / r[c] : (T)0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // zero density: the component is inert (no velocity, no shift)
+            const T base = P.velocity_mode == 1 ? j[c][a] * ir : ubar[a];
+            ueq[c][a] = base + tau * F[c][a] * ir;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Population storage (pull form).  Slot (c, i, z) of a buffer holds the value
+// that site z + c_i receives in direction i: the post-streaming population of
+// a fluid site x is f_i(x) = slot (i, x - c_i).  A step reads those slots,
+// collides and writes its own slots (i, x) with aligned, full-line stores;
+// when x + c_i is solid the bounced population is written once more into the
+// unused slot (opp(i), x + c_i), which is exactly where x reads direction
+// opp(i) at the next step.
+// ---------------------------------------------------------------------------
+
+// signed offsets from a site to its 18 neighbours with the periodic wrap folded
+// into per-axis corrections (32-bit site indices)
+struct NbrOffsets {
+    int nx, nxy, xm, xp, ym, yp, zm, zp;
+    __device__ __forceinline__ NbrOffsets(const DevParams &P, int xs, int ys, int zs) {
+        nx = P.nx;
+        nxy = P.nx * P.ny;
+        const int N = (int)P.N;
+        xm = xs == 0 ? nx : 0;
+        xp = xs == P.nx - 1 ? -nx : 0;
+        ym = ys == 0 ? nxy : 0;
+        yp = ys == P.ny - 1 ? -nxy : 0;
+        zm = zs == 0 ? N : 0;
+        zp = zs == P.nz - 1 ? -N : 0;
+    }
+    template <int i>
+    __device__ __forceinline__ int off() const {
+        return cx(i) + cy(i) * nx + cz(i) * nxy + (cx(i) < 0 ? xm : (cx(i) > 0 ? xp : 0)) +
+               (cy(i) < 0 ? ym : (cy(i) > 0 ? yp : 0)) + (cz(i) < 0 ? zm : (cz(i) > 0 ? zp : 0));
+    }
+};
+
+// f_i(x) = slot (i, x - c_i) for both components
+template <typename T>
+__device__ __forceinline__ void pull_load(const T *__restrict__ fin, unsigned n, const NbrOffsets &o, T (&f)[2][Q]) {
+    Unroll<Q>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const unsigned src = i == 0 ? n : (unsigned)((int)n + o.template off<opp(i)>());
+        f[0][i] = fin[pidx(0, i, src)];
+        f[1][i] = fin[pidx(1, i, src)];
+    });
+}
+
+// sum_i f_i(x) of component c (pull form)
+template <typename T>
+__device__ __forceinline__ T pull_sum(const T *__restrict__ fin, int c, unsigned n, const NbrOffsets &o) {
+    T s = 0;
+    Unroll<Q>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const unsigned src = i == 0 ? n : (unsigned)((int)n + o.template off<opp(i)>());
+        s += fin[pidx(c, i, src)];
+    });
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// The site update shared by both fluid kernels: BGK collision with the
+// velocity shift, Eqs. (2), (3), (6), and streaming with bounce-back, Eqs.
+// (11), (12), (16), for a fluid site x (linear index n) whose populations are
+// in f and whose neighbour sum of Eq. (4) is acc.  The moving-wall term of
+// Eq. (16) is subtracted afterwards on the rare bounce-back links.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void collide_and_store(const DevParams &P, const DevParticles &D, T (&f)[2][Q],
+                                                  const T (&acc)[2][3], uint32_t inf, int xs, int ys, int zs,
+                                                  unsigned n, const NbrOffsets &o, T *__restrict__ fout,
+                                                  const int32_t *__restrict__ owner, T *__restrict__ rho_out,
+                                                  double &mass0, double &mass1) {
+    const T rho0 = (T)P.rho0, irho0 = (T)P.inv_rho0, g = (T)P.g;
+    const unsigned N = (unsigned)P.N;
+    T dr[2], r[2], j[2][3], F[2][3];
+    moments(f[0], (T)P.rho_ref[0], dr[0], r[0], j[0][0], j[0][1], j[0][2]);
+    moments(f[1], (T)P.rho_ref[1], dr[1], r[1], j[1][0], j[1][1], j[1][2]);
+    mass0 += (double)dr[0] + P.rho_ref[0];
+    mass1 += (double)dr[1] + P.rho_ref[1];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T ps = psi_of(r[c], rho0, irho0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) F[c][a] = -ps * g * acc[1 - c][a] + r[c] * (T)P.body[a];
+    }
+    T ueq[2][3];
+    eq_velocity(P, r, j, F, ueq);
+    if (rho_out && (inf & 0x7fffeu)) {  // density of a boundary site, read back by the link sums
+        rho_out[sidx(0, n)] = dr[0];
+        rho_out[sidx(1, n)] = dr[1];
+    }
+    const int order = P.eq_order;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T omega = (T)P.inv_tau[c];
+        const T ux = ueq[c][0], uy = ueq[c][1], uz = ueq[c][2];
+        const T u2 = ux * ux + uy * uy + uz * uz;
+        Unroll<Q>::run([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const T fs = f[c][i] - (f[c][i] - feq_dev_dir<T>(i, dr[c], r[c], ux, uy, uz, u2, order)) * omega;
+            fout[pidx(c, i, n)] = fs;
+            if (i != 0 && (inf & (1u << i))) fout[pidx(c, opp(i), (unsigned)((int)n + o.template off<i>()))] = fs;
+        });
+    }
+    if (inf & 0x7fffeu) {
+        // moving-wall term on the bounce-back links: slot (opp(i), x + c_i) -= 6 zeta_i rho (c_i . u_b)
+        uint32_t bits = inf & 0x7fffeu;
+        while (bits) {
+            const int i = __ffs(bits) - 1;
+            bits &= bits - 1;
+            const int ci[3] = {cx(i), cy(i), cz(i)};
+            const int xn = wrapc(xs + ci[0], P.nx), yn = wrapc(ys + ci[1], P.ny), zn = wrapc(zs + ci[2], P.nz);
+            const unsigned m = ((unsigned)zn * P.ny + yn) * P.nx + xn;
+            double ub[3], rb[3];
+            solid_velocity(P, D, owner[m], xs, ys, zs, i, ub, rb);
+            const double cub = ci[0] * ub[0] + ci[1] * ub[1] + ci[2] * ub[2];
+            if (cub != 0.0) {
+                const double wz = 6.0 * zeta(i) * cub;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    T *p = fout + pidx(c, opp(i), m);
+                    *p = *p - (T)wz * r[c];
+                }
+            }
         }
     }
 }

@@ -23,6 +23,7 @@ struct lb_handle {
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
     void *rho = nullptr;  // T [2][N]: densities (fluid), virtual densities (shell)
+    void *psi = nullptr;  // T [2][N]: Psi - Psi(rho_ref) of the two-pass variant
     void *fsc = nullptr;  // T [3][N]: Shan-Chen force on virtual-fluid sites
     uint32_t *info = nullptr;
     int32_t *owner = nullptr;
@@ -41,6 +42,8 @@ struct lb_handle {
 
     int kernel = LB_KERNEL_TWOPASS;
     int tile[3] = {0, 0, 0};
+    int fused_tx = 64, fused_ty = 4, fused_tz = 32;  // fused-kernel tile
+    int n_fused_blocks = 0;
     long long step = 0;
     std::vector<void *> owned;  // every device allocation, freed by lb_destroy
 
@@ -65,8 +68,12 @@ void launch_shell_fill(lb_handle *h);
 void launch_collide_stream(lb_handle *h, const void *fin, void *fout);
 void launch_fields(lb_handle *h, const void *f, double *out);
 void launch_sums(lb_handle *h, const void *f);
+void launch_finalize_mass_n(lb_handle *h, int nblocks);
+
+// fused single sweep (lbm_fused.hip)
+bool fused_supported(const lb_params &p);
+void launch_fused(lb_handle *h, const void *fin, void *fout);
 void launch_fill_int(lb_handle *h, int32_t *p, long long n, int32_t v);
-void launch_zero_solid(lb_handle *h, void *f);
 void launch_info_dense(lb_handle *h);
 void launch_owner_reset(lb_handle *h);
 

@@ -63,10 +63,11 @@ __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &
 // ---------------------------------------------------------------------------
 // fluid force and torque on each sphere: bounce-back links, Eqs. (13)-(17),
 // and the Shan-Chen force on its virtual fluid, Eq. (28).
-// A link (x, i) has x fluid and x + c_i inside the sphere.  The kernel that
-// streamed wrote f_opp(i)(x) = f*_i(x) - w^c with w^c = 6 zeta_i rho^c(x)
-// (c_i . u_b), so the momentum given to the sphere is
-// c_i sum_c (2 f*_i - w^c) = c_i sum_c (2 f_opp(i)(x) + w^c).
+// A link (x, i) has x fluid and x + c_i inside the sphere.  The streaming
+// kernel wrote the bounced population f_opp(i)(x) = f*_i(x) - w^c, with
+// w^c = 6 zeta_i rho^c(x) (c_i . u_b), into slot (opp(i), x + c_i), so the
+// momentum given to the sphere is c_i sum_c (2 f*_i - w^c)
+// = c_i sum_c (2 f_opp(i)(x) + w^c).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, const T *__restrict__ fout,
@@ -87,10 +88,11 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
         double ub[3], rb[3];
         solid_velocity(P, D, p, x, y, z, i, ub, rb);
         const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
+        const long long m = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
         double s = 0.0;
         for (int c = 0; c < 2; ++c) {
-            const double w = 6.0 * zeta(i) * cub * ((double)rho[c * P.N + n] + P.rho_ref[c]);
-            const double fo = (double)fout[(long long)(c * Q + opp(i)) * P.N + n] + zeta(i) * P.rho_ref[c];
+            const double w = 6.0 * zeta(i) * cub * ((double)rho[sidx(c, (unsigned)n)] + P.rho_ref[c]);
+            const double fo = (double)fout[pidx(c, opp(i), (unsigned)m)] + zeta(i) * P.rho_ref[c];
             s += 2.0 * fo + w;
         }
         const double dp[3] = {cx(i) * s, cy(i) * s, cz(i) * s};
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
         double r[3], F[3];
         for (int a = 0; a < 3; ++a) {
             r[a] = minimg(pos[a] - R[a], L[a]);
-            F[a] = (double)fsc[a * P.N + n];
+            F[a] = (double)fsc[vidx(a, (unsigned)n)];
         }
         v[0] += F[0];
         v[1] += F[1];
@@ -282,15 +284,16 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
         const long long n = D.cov[off + k];
         int x, y, z;
         site_xyz(n, P, x, y, z);
-        double mom[3] = {0, 0, 0};  // the reference part of the stored values has no momentum
+        // f_i(y) = slot (i, y - c_i); the reference part of the stored values
+        // has no momentum.  Nothing reads those slots once y is solid.
+        double mom[3] = {0, 0, 0};
         for (int c = 0; c < 2; ++c)
             for (int i = 0; i < Q; ++i) {
-                T *fp = &f[(long long)(c * Q + i) * N + n];
-                const double di = (double)*fp;
+                const long long src = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
+                const double di = (double)f[pidx(c, i, (unsigned)src)];
                 mom[0] += di * cx(i);
                 mom[1] += di * cy(i);
                 mom[2] += di * cz(i);
-                *fp = (T)0;
             }
         const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
         for (int a = 0; a < 3; ++a) v[a] += mom[a];
@@ -310,9 +313,15 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
             const long long m = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
             if (owner[m] != OWN_FLUID || stage[m] != STAGE_NONE) continue;
             ++cnt;
+            int mx, my, mz;
+            site_xyz(m, P, mx, my, mz);
             for (int c = 0; c < 2; ++c) {
                 double r = 0.0;
-                for (int q = 0; q < Q; ++q) r += (double)f[(long long)(c * Q + q) * N + m];
+                for (int q = 0; q < Q; ++q) {
+                    const long long src =
+                        site_of(wrapc(mx - cx(q), P.nx), wrapc(my - cy(q), P.ny), wrapc(mz - cz(q), P.nz), P);
+                    r += (double)f[pidx(c, q, (unsigned)src)];
+                }
                 rbar[c] += r + P.rho_ref[c];
             }
         }
@@ -330,9 +339,12 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
                               U[2] + (W[0] * r[1] - W[1] * r[0])};
         const double u2 = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
         for (int c = 0; c < 2; ++c)
-            for (int i = 0; i < Q; ++i)
-                f[(long long)(c * Q + i) * N + n] =
+            for (int i = 0; i < Q; ++i) {
+                // written where the site reads it: slot (i, y - c_i), read by nobody else
+                const long long dst = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
+                f[pidx(c, i, (unsigned)dst)] =
                     (T)(feq_dir<double>(i, rnew[c], us[0], us[1], us[2], u2, P.eq_order) - zeta(i) * P.rho_ref[c]);
+            }
         double mom[3];
         for (int a = 0; a < 3; ++a) mom[a] = (rnew[0] + rnew[1]) * us[a];
         for (int a = 0; a < 3; ++a) v[a] -= mom[a];

@@ -86,7 +86,7 @@ def test_initial_state_matches_the_oracle():
     assert np.abs(g32 - ref).max() < 1e-9
 
 
-@pytest.mark.parametrize("kernel", ["twopass"])
+@pytest.mark.parametrize("kernel", ["fused", "twopass"])
 def test_spinodal32_fp64_end_to_end(kernel):
     """32^3, 0.7 +- 0.01 each, g = 0.1, no particles, FP64, 200 steps."""
     p, parts, steps, prec = W.config("spinodal32")
@@ -102,7 +102,7 @@ def test_spinodal32_fp64_end_to_end(kernel):
     assert np.abs(rho[0] - rho[1]).mean() > 0.5
 
 
-@pytest.mark.parametrize("kernel", ["twopass"])
+@pytest.mark.parametrize("kernel", ["fused", "twopass"])
 def test_spinodal32_fp32_shadowing(kernel):
     p, _, _, _ = W.config("spinodal32")
     gpu = lbm().Lattice(p, precision="fp32", kernel=kernel)
@@ -117,7 +117,7 @@ def test_spinodal32_fp32_shadowing(kernel):
         compare_fields(gpu, ref, p)
 
 
-@pytest.mark.parametrize("kernel", ["twopass"])
+@pytest.mark.parametrize("kernel", ["fused", "twopass"])
 def test_spheres64_fp32_shadowing(kernel):
     """64^3, 50:50, g = 0.08, 100 spheres of radius 4, FP32: shadowed at
     steps 0 and 60 for 1 and 5 steps, bookkeeping exact."""
@@ -149,6 +149,31 @@ def _prescribed_boxes(n=48, count=20, seed=5):
     vel = rng.uniform(-0.04, 0.04, (count, 3))
     om = rng.uniform(-0.01, 0.01, (count, 3))
     return p, W.make_particles(pos, 4.0, vel=vel, omega=om, prescribed=1, color=rng.uniform(-0.05, 0.05, count))
+
+
+@pytest.mark.parametrize("shape", [(64, 48, 40), (40, 36, 33), (20, 12, 11)])
+def test_fused_and_twopass_agree(shape):
+    """The single-sweep kernel computes the same step as the two-pass one
+    (ragged tiles, periodic wrap of the halos, spheres near the box edges)."""
+    nx, ny, nz = shape
+    p = W.params(nx=nx, ny=ny, nz=nz, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.07, seed=13)
+    r = float(min(4, (min(nx, ny, nz) - 7) // 2))  # the library needs 2 ceil(r) + 7 <= every edge
+    pos = W.random_sphere_positions((nx, ny, nz), 3 if nz > 12 else 1, r, seed=13, min_gap=1.5)
+    rng = np.random.default_rng(13)
+    parts = W.make_particles(pos, r, vel=rng.uniform(-0.03, 0.03, (len(pos), 3)),
+                             color=rng.uniform(-0.05, 0.05, len(pos)))
+    runs = {}
+    for kernel in ("fused", "twopass"):
+        g = lbm().Lattice(p, precision="fp32", kernel=kernel)
+        g.add_particles(parts)
+        g.step(12)
+        runs[kernel] = (g.populations(), g.particles(), g.owner())
+    fa, pa, oa = runs["fused"]
+    fb, pb, ob = runs["twopass"]
+    assert np.array_equal(oa, ob)
+    assert np.abs(fa - fb).max() < 1e-6
+    for k in ("Ffluid", "Tfluid", "R", "U"):
+        assert np.abs(pa[k] - pb[k]).max() < 1e-6 * max(1.0, np.abs(pb[k]).max()), k
 
 
 def test_prescribed_motion_bookkeeping_is_exact():
