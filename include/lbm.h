@@ -84,7 +84,7 @@ typedef struct {
     double noise_amp;        /* initial density = rho_init + noise_amp*(2U-1), U uniform */
     uint64_t seed;           /* key of the SplitMix64 draws U (draw index 2n + c) */
     double body_accel[3];    /* uniform acceleration of the fluid (channel-flow tests) */
-    int32_t wall_axis;       /* -1: none; 0..2: the planes 0 and n-1 of that axis are walls */
+    int32_t wall_axis;       /* -1: none; 0..2: the planes 0 and n-1 of that axis are walls (n >= 3) */
     double wall_vel[2][3];   /* velocities of the low and the high wall */
     double c0_mass_corr;     /* C_0 of the mass correction, Eq. (31); 0 switches it off */
     double k_hertz;          /* K_Hertz of Eq. (21) */

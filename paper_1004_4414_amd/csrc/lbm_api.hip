@@ -125,6 +125,8 @@ int validate_params(const lb_params *p, std::string &msg) {
     if (p->velocity_mode != 0 && p->velocity_mode != 1) return msg = "velocity_mode must be 0 or 1", LB_EINVAL;
     if (p->eq_order != 2 && p->eq_order != 3) return msg = "eq_order must be 2 or 3", LB_EINVAL;
     if (p->wall_axis < -1 || p->wall_axis > 2) return msg = "wall_axis must be -1, 0, 1 or 2", LB_EINVAL;
+    if (p->wall_axis >= 0 && (p->wall_axis == 0 ? p->nx : (p->wall_axis == 1 ? p->ny : p->nz)) < 3)
+        return msg = "a box with walls needs at least 3 sites along the wall axis", LB_EINVAL;
     if (p->kernel < LB_KERNEL_AUTO || p->kernel > LB_KERNEL_TWOPASS) return msg = "unknown kernel", LB_EINVAL;
     if (!std::isfinite(p->g_br) || !std::isfinite(p->noise_amp)) return msg = "non-finite parameter", LB_EINVAL;
     return LB_OK;
@@ -273,6 +275,7 @@ void one_step(lb_handle *h) {
         launch_collide_stream(h, fin, fout);
         h->timing_end(0, t_col);
     }
+    launch_wall_links(h, fout);
     if (h->np) {
         launch_particle_fluid_force(h, fout);
         launch_pair_forces(h);

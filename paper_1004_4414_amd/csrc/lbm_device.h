@@ -399,6 +399,40 @@ __device__ __forceinline__ void pull_load(const T *__restrict__ fin, unsigned n,
     });
 }
 
+// Tuning macros of the sweep kernels (compile-time):
+//   LBM_COLLIDE_WAVES  minimum wavefronts per SIMD the collide sweep is
+//                      register-limited to (0: compiler's choice)
+//   LBM_NT_STORE       1: populations are written with non-temporal stores
+#ifndef LBM_COLLIDE_WAVES
+#define LBM_COLLIDE_WAVES 0
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 0
+#endif
+#if LBM_COLLIDE_WAVES > 0
+#define LBM_COLLIDE_ATTR __attribute__((amdgpu_waves_per_eu(LBM_COLLIDE_WAVES)))
+#else
+#define LBM_COLLIDE_ATTR
+#endif
+
+template <typename T>
+__device__ __forceinline__ void store_pop(T *p, T v) {
+#if LBM_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// An empty asm statement that takes the values as inputs: loads issued
+// before it complete before it, and the compiler cannot sink them into the
+// branches that follow, so all of a wavefront's loads are in flight together.
+template <typename T, int K>
+__device__ __forceinline__ void hold_loads(const T (&v)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) asm volatile("" ::"v"(v[k]));
+}
+
 // sum_i f_i(x) of component c (pull form)
 template <typename T>
 __device__ __forceinline__ T pull_sum(const T *__restrict__ fin, int c, unsigned n, const NbrOffsets &o) {
@@ -415,17 +449,18 @@ __device__ __forceinline__ T pull_sum(const T *__restrict__ fin, int c, unsigned
 // The site update shared by both fluid kernels: BGK collision with the
 // velocity shift, Eqs. (2), (3), (6), and streaming with bounce-back, Eqs.
 // (11), (12), (16), for a fluid site x (linear index n) whose populations are
-// in f and whose neighbour sum of Eq. (4) is acc.  The moving-wall term of
-// Eq. (16) is subtracted afterwards on the rare bounce-back links.
+// in f and whose neighbour sum of Eq. (4) is acc.  A population bounced at a
+// solid neighbour x + c_i is stored as f*_i(x) in slot (opp(i), x + c_i); the
+// moving-wall term of Eq. (16) is subtracted from it by the link kernels
+// (spheres: the link force sum; walls: the wall-plane kernel), which need
+// the density of x and therefore find it in rho_out at boundary sites.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void collide_and_store(const DevParams &P, const DevParticles &D, T (&f)[2][Q],
-                                                  const T (&acc)[2][3], uint32_t inf, int xs, int ys, int zs,
-                                                  unsigned n, const NbrOffsets &o, T *__restrict__ fout,
-                                                  const int32_t *__restrict__ owner, T *__restrict__ rho_out,
-                                                  double &mass0, double &mass1) {
+__device__ __forceinline__ void collide_and_store(const DevParams &P, T (&f)[2][Q], const T (&acc)[2][3],
+                                                  uint32_t inf, unsigned n, const NbrOffsets &o,
+                                                  T *__restrict__ fout, T *__restrict__ rho_out, double &mass0,
+                                                  double &mass1) {
     const T rho0 = (T)P.rho0, irho0 = (T)P.inv_rho0, g = (T)P.g;
-    const unsigned N = (unsigned)P.N;
     T dr[2], r[2], j[2][3], F[2][3];
     moments(f[0], (T)P.rho_ref[0], dr[0], r[0], j[0][0], j[0][1], j[0][2]);
     moments(f[1], (T)P.rho_ref[1], dr[1], r[1], j[1][0], j[1][1], j[1][2]);
@@ -439,7 +474,7 @@ __device__ __forceinline__ void collide_and_store(const DevParams &P, const DevP
     }
     T ueq[2][3];
     eq_velocity(P, r, j, F, ueq);
-    if (rho_out && (inf & 0x7fffeu)) {  // density of a boundary site, read back by the link sums
+    if (rho_out && (inf & 0x7fffeu)) {  // density of a boundary site, read back by the link kernels
         rho_out[sidx(0, n)] = dr[0];
         rho_out[sidx(1, n)] = dr[1];
     }
@@ -452,31 +487,9 @@ __device__ __forceinline__ void collide_and_store(const DevParams &P, const DevP
         Unroll<Q>::run([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             const T fs = f[c][i] - (f[c][i] - feq_dev_dir<T>(i, dr[c], r[c], ux, uy, uz, u2, order)) * omega;
-            fout[pidx(c, i, n)] = fs;
+            store_pop(fout + pidx(c, i, n), fs);
             if (i != 0 && (inf & (1u << i))) fout[pidx(c, opp(i), (unsigned)((int)n + o.template off<i>()))] = fs;
         });
-    }
-    if (inf & 0x7fffeu) {
-        // moving-wall term on the bounce-back links: slot (opp(i), x + c_i) -= 6 zeta_i rho (c_i . u_b)
-        uint32_t bits = inf & 0x7fffeu;
-        while (bits) {
-            const int i = __ffs(bits) - 1;
-            bits &= bits - 1;
-            const int ci[3] = {cx(i), cy(i), cz(i)};
-            const int xn = wrapc(xs + ci[0], P.nx), yn = wrapc(ys + ci[1], P.ny), zn = wrapc(zs + ci[2], P.nz);
-            const unsigned m = ((unsigned)zn * P.ny + yn) * P.nx + xn;
-            double ub[3], rb[3];
-            solid_velocity(P, D, owner[m], xs, ys, zs, i, ub, rb);
-            const double cub = ci[0] * ub[0] + ci[1] * ub[1] + ci[2] * ub[2];
-            if (cub != 0.0) {
-                const double wz = 6.0 * zeta(i) * cub;
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    T *p = fout + pidx(c, opp(i), m);
-                    *p = *p - (T)wz * r[c];
-                }
-            }
-        }
     }
 }
 

@@ -174,20 +174,30 @@ __global__ __launch_bounds__(BLOCK) void k_shell_fill(DevParams P, DevParticles 
     }
 }
 
+// Psi^c(x + c_i) - Psi^c(rho_ref) of the 18 neighbours (pn[c][i-1])
+template <typename T>
+__device__ __forceinline__ void load_psi_neighbours(const T *__restrict__ psi, unsigned n, const NbrOffsets &o,
+                                                    T (&pn)[2][Q - 1]) {
+    Unroll<Q - 1>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value + 1;
+        const unsigned m = (unsigned)((int)n + o.template off<i>());
+        pn[0][i - 1] = psi[sidx(0, m)];
+        pn[1][i - 1] = psi[sidx(1, m)];
+    });
+}
+
 // acc[c][a] = sum_{i=1..18} W_i (Psi^c(x + c_i) - Psi^c(rho_ref)) c_ia
 template <typename T>
-__device__ __forceinline__ void neighbour_psi_sum(const T *__restrict__ psi, const DevParams &P, unsigned n,
-                                                  const NbrOffsets &o, T (&acc)[2][3]) {
+__device__ __forceinline__ void psi_force_sum(const DevParams &P, const T (&pn)[2][Q - 1], T (&acc)[2][3]) {
     const T wf = (T)P.w_face, we = (T)P.w_edge;
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc[c][0] = acc[c][1] = acc[c][2] = 0;
     Unroll<Q - 1>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value + 1;
-        const unsigned m = (unsigned)((int)n + o.template off<i>());
         const T w = norm2(i) == 1 ? wf : we;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const T wp = w * psi[sidx(c, m)];
+            const T wp = w * pn[c][i - 1];
             if (cx(i)) acc[c][0] += cx(i) > 0 ? wp : -wp;
             if (cy(i)) acc[c][1] += cy(i) > 0 ? wp : -wp;
             if (cz(i)) acc[c][2] += cz(i) > 0 ? wp : -wp;
@@ -198,22 +208,33 @@ __device__ __forceinline__ void neighbour_psi_sum(const T *__restrict__ psi, con
 // ---------------------------------------------------------------------------
 // collide and stream (two-pass variant, second sweep): populations of the
 // site, Psi of the neighbours from the Psi array.  On shell sites it stores
-// the Shan-Chen force for the particle sums.
+// the Shan-Chen force for the particle sums.  Every load of a site is issued
+// before its classification is known (all addresses lie in the box), so a
+// wavefront has its whole working set in flight at once.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_collide_stream(DevParams P, DevParticles D, const T *__restrict__ fin,
-                                                          T *__restrict__ fout, const T *__restrict__ rho,
-                                                          const T *__restrict__ psi, const uint32_t *__restrict__ info,
-                                                          const int32_t *__restrict__ owner, T *__restrict__ fsc) {
+__global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevParams P, const T *__restrict__ fin,
+                                                                          T *__restrict__ fout, const T *__restrict__ rho,
+                                                                          const T *__restrict__ psi,
+                                                                          const uint32_t *__restrict__ info,
+                                                                          T *__restrict__ fsc) {
     unsigned n;
     int x, y, z;
     if (!dense_site(P, n, x, y, z)) return;
+    const NbrOffsets o(P, x, y, z);
+    T f[2][Q];
+    pull_load(fin, n, o, f);
+    T pn[2][Q - 1];
+    load_psi_neighbours(psi, n, o, pn);
     const uint32_t inf = info[n];
+    hold_loads(f[0]);
+    hold_loads(f[1]);
+    hold_loads(pn[0]);
+    hold_loads(pn[1]);
     const uint32_t cls = site_class(inf);
     if (cls == CLS_SOLID || cls == CLS_WALL) return;
-    const NbrOffsets o(P, x, y, z);
     T acc[2][3];
-    neighbour_psi_sum(psi, P, n, o, acc);
+    psi_force_sum(P, pn, acc);
     if (cls == CLS_SHELL) {
         const T g = (T)P.g, rho0 = (T)P.rho0, irho0 = (T)P.inv_rho0;
         const T ps0 = psi_of(rho[sidx(0, n)] + (T)P.rho_ref[0], rho0, irho0);
@@ -222,10 +243,57 @@ __global__ __launch_bounds__(BLOCK) void k_collide_stream(DevParams P, DevPartic
         for (int a = 0; a < 3; ++a) fsc[vidx(a, n)] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
         return;
     }
-    T f[2][Q];
-    pull_load(fin, n, o, f);
     double m0 = 0.0, m1 = 0.0;
-    collide_and_store(P, D, f, acc, inf, x, y, z, n, o, fout, owner, (T *)nullptr, m0, m1);
+    collide_and_store(P, f, acc, inf, n, o, fout, (T *)nullptr, m0, m1);
+}
+
+// ---------------------------------------------------------------------------
+// moving-wall term of Eq. (16) on the links into the two walls: for a fluid
+// site x next to a wall and a direction i with x + c_i in the wall, the
+// bounced population in slot (opp(i), x + c_i) loses 6 zeta_i rho^c(x)
+// (c_i . u_wall).  Only the planes next to the walls hold such links; the
+// grid covers both (one thread per site of the two planes).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_wall_links(DevParams P, T *__restrict__ fout, const T *__restrict__ rho,
+                                                      const uint32_t *__restrict__ info,
+                                                      const int32_t *__restrict__ owner) {
+    const int ax = P.wall_axis;
+    const int L = ax == 0 ? P.nx : (ax == 1 ? P.ny : P.nz);
+    const int ua = ax == 0 ? P.ny : P.nx;  // the two in-plane axes, u fastest
+    const int va = ax == 2 ? P.ny : P.nz;
+    const long long plane = (long long)ua * va;
+    const long long k = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= 2 * plane) return;
+    const int pos = k < plane ? 1 : L - 2;
+    if (k >= plane && L - 2 == 1) return;  // one plane touches both walls
+    const int u = (int)((k % plane) % ua), v = (int)((k % plane) / ua);
+    const int x = ax == 0 ? pos : u, y = ax == 1 ? pos : (ax == 0 ? u : v), z = ax == 2 ? pos : v;
+    const unsigned n = (unsigned)(((long long)z * P.ny + y) * P.nx + x);
+    const uint32_t inf = info[n];
+    if (site_class(inf) != CLS_FLUID && site_class(inf) != CLS_SHELL) return;
+    uint32_t bits = inf & 0x7fffeu;
+    while (bits) {
+        const int i = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const int xn = wrapc(x + cx(i), P.nx), yn = wrapc(y + cy(i), P.ny), zn = wrapc(z + cz(i), P.nz);
+        const unsigned m = (unsigned)(((long long)zn * P.ny + yn) * P.nx + xn);
+        const int32_t own = owner[m];
+        if (own != OWN_WALL_LO && own != OWN_WALL_HI) continue;
+        const bool lo = own == OWN_WALL_LO;
+        double cub = 0.0;
+        if (cx(i)) cub += cx(i) * (lo ? P.wall_vel[0][0] : P.wall_vel[1][0]);
+        if (cy(i)) cub += cy(i) * (lo ? P.wall_vel[0][1] : P.wall_vel[1][1]);
+        if (cz(i)) cub += cz(i) * (lo ? P.wall_vel[0][2] : P.wall_vel[1][2]);
+        if (cub == 0.0) continue;
+        const double wz = 6.0 * zeta(i) * cub;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const T rc = rho[sidx(c, n)] + (T)P.rho_ref[c];
+            T *p = fout + pidx(c, opp(i), m);
+            *p = *p - (T)wz * rc;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -253,8 +321,9 @@ __global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const T *__restri
     if (cls == CLS_SOLID || cls == CLS_WALL) return;
     const NbrOffsets o(P, x, y, z);
     const T g = (T)P.g, rho0 = (T)P.rho0, irho0 = (T)P.inv_rho0;
-    T acc[2][3];
-    neighbour_psi_sum(psi, P, n, o, acc);
+    T acc[2][3], pn[2][Q - 1];
+    load_psi_neighbours(psi, n, o, pn);
+    psi_force_sum(P, pn, acc);
     if (cls == CLS_SHELL) {
         const T ps0 = psi_of(rho[sidx(0, n)] + (T)P.rho_ref[0], rho0, irho0);
         const T ps1 = psi_of(rho[sidx(1, n)] + (T)P.rho_ref[1], rho0, irho0);
@@ -391,12 +460,26 @@ void launch_shell_fill(lb_handle *h) {
 void launch_collide_stream(lb_handle *h, const void *fin, void *fout) {
     const unsigned nb = dense_blocks(h);
     LB_DISPATCH(h,
-                (k_collide_stream<float><<<nb, BLOCK, 0, h->stream>>>(
-                    h->dp, h->dpart, (const float *)fin, (float *)fout, (const float *)h->rho, (const float *)h->psi,
-                    h->info, h->owner, (float *)h->fsc)),
-                (k_collide_stream<double><<<nb, BLOCK, 0, h->stream>>>(
-                    h->dp, h->dpart, (const double *)fin, (double *)fout, (const double *)h->rho,
-                    (const double *)h->psi, h->info, h->owner, (double *)h->fsc)));
+                (k_collide_stream<float><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const float *)fin, (float *)fout,
+                                                                       (const float *)h->rho, (const float *)h->psi,
+                                                                       h->info, (float *)h->fsc)),
+                (k_collide_stream<double><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const double *)fin, (double *)fout,
+                                                                        (const double *)h->rho, (const double *)h->psi,
+                                                                        h->info, (double *)h->fsc)));
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_wall_links(lb_handle *h, void *fout) {
+    const int ax = h->prm.wall_axis;
+    if (ax < 0) return;
+    const long long plane = ax == 0 ? (long long)h->prm.ny * h->prm.nz
+                                    : (ax == 1 ? (long long)h->prm.nx * h->prm.nz : (long long)h->prm.nx * h->prm.ny);
+    const unsigned nb = nblocks(2 * plane);
+    LB_DISPATCH(h,
+                (k_wall_links<float><<<nb, BLOCK, 0, h->stream>>>(h->dp, (float *)fout, (const float *)h->rho, h->info,
+                                                                   h->owner)),
+                (k_wall_links<double><<<nb, BLOCK, 0, h->stream>>>(h->dp, (double *)fout, (const double *)h->rho,
+                                                                    h->info, h->owner)));
     LB_HIP_CHECK(hipGetLastError());
 }
 

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles
                     const NbrOffsets o(P, xs, ys, zc);
                     T f[2][Q];
                     pull_load(fin, (unsigned)n, o, f);
-                    collide_and_store(P, D, f, acc, inf, xs, ys, zc, (unsigned)n, o, fout, owner, rho, mass0, mass1);
+                    collide_and_store(P, f, acc, inf, (unsigned)n, o, fout, rho, mass0, mass1);
                 }
             }
         }

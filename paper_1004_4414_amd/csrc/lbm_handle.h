@@ -66,6 +66,7 @@ void launch_density(lb_handle *h, const void *f, bool partial_sums);
 void launch_finalize_mass(lb_handle *h);
 void launch_shell_fill(lb_handle *h);
 void launch_collide_stream(lb_handle *h, const void *fin, void *fout);
+void launch_wall_links(lb_handle *h, void *fout);
 void launch_fields(lb_handle *h, const void *f, double *out);
 void launch_sums(lb_handle *h, const void *f);
 void launch_finalize_mass_n(lb_handle *h, int nblocks);
@@ -78,7 +79,7 @@ void launch_info_dense(lb_handle *h);
 void launch_owner_reset(lb_handle *h);
 
 // particles (lbm_particles.hip)
-void launch_particle_fluid_force(lb_handle *h, const void *fout);
+void launch_particle_fluid_force(lb_handle *h, void *fout);
 void launch_pair_forces(lb_handle *h);
 void launch_integrate(lb_handle *h);
 void launch_map_mark(lb_handle *h, bool use_prev);

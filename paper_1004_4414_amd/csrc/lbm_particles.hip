@@ -64,13 +64,14 @@ __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &
 // fluid force and torque on each sphere: bounce-back links, Eqs. (13)-(17),
 // and the Shan-Chen force on its virtual fluid, Eq. (28).
 // A link (x, i) has x fluid and x + c_i inside the sphere.  The streaming
-// kernel wrote the bounced population f_opp(i)(x) = f*_i(x) - w^c, with
-// w^c = 6 zeta_i rho^c(x) (c_i . u_b), into slot (opp(i), x + c_i), so the
-// momentum given to the sphere is c_i sum_c (2 f*_i - w^c)
-// = c_i sum_c (2 f_opp(i)(x) + w^c).
+// kernel stored the bounced population f*_i(x) in slot (opp(i), x + c_i);
+// this kernel completes Eq. (16) there, f_opp(i)(x) = f*_i(x) - w^c with
+// w^c = 6 zeta_i rho^c(x) (c_i . u_b) (each link is visited once, by the
+// sphere that owns x + c_i), and adds the momentum given to the sphere,
+// c_i sum_c (2 f*_i - w^c).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, const T *__restrict__ fout,
+__global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, T *__restrict__ fout,
                                                                 const T *__restrict__ rho, const T *__restrict__ fsc) {
     __shared__ double lds[6 * BLOCK];
     const int p = blockIdx.x;
@@ -91,9 +92,12 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
         const long long m = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
         double s = 0.0;
         for (int c = 0; c < 2; ++c) {
-            const double w = 6.0 * zeta(i) * cub * ((double)rho[sidx(c, (unsigned)n)] + P.rho_ref[c]);
-            const double fo = (double)fout[pidx(c, opp(i), (unsigned)m)] + zeta(i) * P.rho_ref[c];
-            s += 2.0 * fo + w;
+            const T rc = rho[sidx(c, (unsigned)n)] + (T)P.rho_ref[c];
+            T *slot = fout + pidx(c, opp(i), (unsigned)m);
+            const T raw = *slot;
+            const T w = (T)(6.0 * zeta(i) * cub) * rc;
+            *slot = raw - w;
+            s += 2.0 * ((double)raw + zeta(i) * P.rho_ref[c]) - (double)w;
         }
         const double dp[3] = {cx(i) * s, cy(i) * s, cz(i) * s};
         v[0] += dp[0];
@@ -448,13 +452,13 @@ __global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles
 // ---------------------------------------------------------------------------
 // launchers (one block per sphere unless noted)
 // ---------------------------------------------------------------------------
-void launch_particle_fluid_force(lb_handle *h, const void *fout) {
+void launch_particle_fluid_force(lb_handle *h, void *fout) {
     if (!h->np) return;
     if (h->prm.precision == LB_FP64)
-        k_particle_fluid_force<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (const double *)fout,
+        k_particle_fluid_force<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (double *)fout,
                                                                        (const double *)h->rho, (const double *)h->fsc);
     else
-        k_particle_fluid_force<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (const float *)fout,
+        k_particle_fluid_force<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (float *)fout,
                                                                       (const float *)h->rho, (const float *)h->fsc);
     LB_HIP_CHECK(hipGetLastError());
 }

@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm.so")
+# an alternative build of the same library (e.g. with other tuning macros) can
+# be selected with LBM_LIBRARY
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 Q = 19
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EOVERLAP, LB_ESTATE, LB_EUNSTABLE, LB_ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
