@@ -146,8 +146,8 @@ size_t fluid_bytes(const lb_params *p) {
 
 size_t particle_bytes(int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
-    size_t b = (size_t)np * (34 * 8 + 11 * 4);
-    b += (size_t)np * sc * (18 * 8 + 4 + 2 * 4);
+    size_t b = (size_t)np * (34 * 8 + 9 * 4);
+    b += (size_t)np * sc * (4 + 2 * 4);  // virtual-fluid sites, covered and uncovered sites
     return b + 4096;
 }
 
@@ -503,26 +503,23 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
         }
     }
     // per-sphere list capacities
-    std::vector<int32_t> link_off(tot), link_cap(tot), shell_off(tot), shell_cap(tot), ev_off(tot), ev_cap(tot);
-    long long lsum = 0, ssum = 0, esum = 0;
+    std::vector<int32_t> shell_off(tot), shell_cap(tot), ev_off(tot), ev_cap(tot);
+    long long ssum = 0, esum = 0;
     for (int p = 0; p < tot; ++p) {
         const int sc = shell_capacity(rad[p]);
         shell_off[p] = (int32_t)ssum;
         shell_cap[p] = sc;
         ssum += sc;
-        link_off[p] = (int32_t)lsum;
-        link_cap[p] = 18 * sc;
-        lsum += 18LL * sc;
         ev_off[p] = (int32_t)esum;
         ev_cap[p] = sc;
         esum += sc;
     }
-    if (lsum > 0x7fffffffLL) return fail(h, LB_EINVAL, "too many spheres for the list capacity");
+    if (ssum > 0x7fffffffLL) return fail(h, LB_EINVAL, "too many spheres for the list capacity");
     free_particles(h);
     h->np = tot;
     DevParticles &D = h->dpart;
     double *dbl = (double *)dev_alloc(h, sizeof(double) * 34 * tot);
-    int32_t *i32 = (int32_t *)dev_alloc(h, sizeof(int32_t) * 11 * tot);
+    int32_t *i32 = (int32_t *)dev_alloc(h, sizeof(int32_t) * 9 * tot);
     h->part_allocs.push_back(dbl);
     h->part_allocs.push_back(i32);
     D.R = dbl;
@@ -540,21 +537,17 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.inertia = dbl + 32 * tot;
     D.color = dbl + 33 * tot;
     D.prescribed = i32;
-    D.link_off = i32 + tot;
-    D.link_cap = i32 + 2 * tot;
-    D.link_cnt = i32 + 3 * tot;
-    D.shell_off = i32 + 4 * tot;
-    D.shell_cap = i32 + 5 * tot;
-    D.shell_cnt = i32 + 6 * tot;
-    D.ev_off = i32 + 7 * tot;
-    D.ev_cap = i32 + 8 * tot;
-    D.cov_cnt = i32 + 9 * tot;
-    D.unc_cnt = i32 + 10 * tot;
-    D.links = (int64_t *)dev_alloc(h, sizeof(int64_t) * lsum);
+    D.link_cnt = i32 + tot;
+    D.shell_off = i32 + 2 * tot;
+    D.shell_cap = i32 + 3 * tot;
+    D.shell_cnt = i32 + 4 * tot;
+    D.ev_off = i32 + 5 * tot;
+    D.ev_cap = i32 + 6 * tot;
+    D.cov_cnt = i32 + 7 * tot;
+    D.unc_cnt = i32 + 8 * tot;
     D.shell = (int32_t *)dev_alloc(h, sizeof(int32_t) * ssum);
     D.cov = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.unc = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
-    h->part_allocs.push_back(D.links);
     h->part_allocs.push_back(D.shell);
     h->part_allocs.push_back(D.cov);
     h->part_allocs.push_back(D.unc);
@@ -573,15 +566,13 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
         hd[32 * tot + p] = 0.4 * m * rad[p] * rad[p];
         hd[33 * tot + p] = col[p];
     }
-    std::vector<int32_t> hi((size_t)11 * tot, 0);
+    std::vector<int32_t> hi((size_t)9 * tot, 0);
     for (int p = 0; p < tot; ++p) {
         hi[p] = pre[p];
-        hi[tot + p] = link_off[p];
-        hi[2 * tot + p] = link_cap[p];
-        hi[4 * tot + p] = shell_off[p];
-        hi[5 * tot + p] = shell_cap[p];
-        hi[7 * tot + p] = ev_off[p];
-        hi[8 * tot + p] = ev_cap[p];
+        hi[2 * tot + p] = shell_off[p];
+        hi[3 * tot + p] = shell_cap[p];
+        hi[5 * tot + p] = ev_off[p];
+        hi[6 * tot + p] = ev_cap[p];
     }
     LB_HIP_CHECK(hipMemcpyAsync(dbl, hd.data(), hd.size() * 8, hipMemcpyHostToDevice, h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(i32, hi.data(), hi.size() * 4, hipMemcpyHostToDevice, h->stream));

@@ -33,24 +33,23 @@ constexpr int BLOCK = 256;  // threads per block of the generic kernels (4 wave6
 
 // D3Q19 velocities in the order of the public layout (rest, 6 faces, 12 edges,
 // opposite directions adjacent).
-__host__ __device__ constexpr int cx(int i) {
-    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
-         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
-}
-__host__ __device__ constexpr int cy(int i) {
-    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
-         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
-}
-__host__ __device__ constexpr int cz(int i) {
-    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
-         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
-}
+// (each component as two bit sets over the direction index, so that a
+// runtime direction costs two shifts and no branches)
+constexpr uint32_t DIRSET_PX = (1u << 1) | (1u << 7) | (1u << 9) | (1u << 11) | (1u << 13);
+constexpr uint32_t DIRSET_MX = (1u << 2) | (1u << 8) | (1u << 10) | (1u << 12) | (1u << 14);
+constexpr uint32_t DIRSET_PY = (1u << 3) | (1u << 7) | (1u << 10) | (1u << 15) | (1u << 17);
+constexpr uint32_t DIRSET_MY = (1u << 4) | (1u << 8) | (1u << 9) | (1u << 16) | (1u << 18);
+constexpr uint32_t DIRSET_PZ = (1u << 5) | (1u << 11) | (1u << 14) | (1u << 15) | (1u << 18);
+constexpr uint32_t DIRSET_MZ = (1u << 6) | (1u << 12) | (1u << 13) | (1u << 16) | (1u << 17);
+__host__ __device__ constexpr int cx(int i) { return (int)((DIRSET_PX >> i) & 1u) - (int)((DIRSET_MX >> i) & 1u); }
+__host__ __device__ constexpr int cy(int i) { return (int)((DIRSET_PY >> i) & 1u) - (int)((DIRSET_MY >> i) & 1u); }
+__host__ __device__ constexpr int cz(int i) { return (int)((DIRSET_PZ >> i) & 1u) - (int)((DIRSET_MZ >> i) & 1u); }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-__host__ __device__ constexpr int norm2(int i) { return cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i); }
+__host__ __device__ constexpr int norm2(int i) { return i == 0 ? 0 : (i <= 6 ? 1 : 2); }
 // lattice weights zeta_i (standard D3Q19: 1/3, 1/18, 1/36)
-__host__ __device__ constexpr double zeta(int i) {
-    return norm2(i) == 0 ? 1.0 / 3.0 : (norm2(i) == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
-}
+__host__ __device__ constexpr double zeta(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+static_assert(cx(7) == 1 && cy(7) == 1 && cz(7) == 0 && cx(18) == 0 && cy(18) == -1 && cz(18) == 1, "D3Q19 table");
+static_assert(cx(opp(13)) == -cx(13) && cz(opp(13)) == -cz(13) && norm2(12) == 2 && norm2(6) == 1, "D3Q19 table");
 
 // ---------------------------------------------------------------------------
 // Memory layout.  Sites are grouped in storage blocks of VB = 64 consecutive
@@ -97,7 +96,9 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv &f) {
 }
 
 // per-site classification word: bits 1..18 flag the directions i whose
-// neighbour x + c_i is solid (bounce-back), bits 29..30 hold the class
+// neighbour x + c_i is solid (on fluid sites: the bounce-back links; on
+// virtual-fluid sites: the complement of the fluid neighbours), bits 29..30
+// hold the class
 enum : uint32_t { CLS_FLUID = 0, CLS_SHELL = 1, CLS_SOLID = 2, CLS_WALL = 3 };
 constexpr int CLS_SHIFT = 29;
 __host__ __device__ inline uint32_t site_class(uint32_t info) { return (info >> CLS_SHIFT) & 3u; }
@@ -129,7 +130,7 @@ struct DevState {
     double Mstep[2];   // fluid mass at the start of the current step
     int32_t have_M0;
     int32_t unstable;
-    int32_t overflow;  // bit 0 links, bit 1 shell, bit 2 events, bit 3 a sphere moved >= 1 site
+    int32_t overflow;  // bit 1 shell list, bit 2 event lists, bit 3 a sphere moved >= 1 site
     int32_t pad;
     unsigned long long covered_total, uncovered_total, refill_fallback;
 };
@@ -140,9 +141,11 @@ struct DevParticles {
     double *Ffl, *Tfl, *Ftot, *Ttot, *P, *PT;
     double *rad, *mass, *inertia, *color;  // np each
     int32_t *prescribed;
-    // per-particle list segments (offset into the flat arrays, capacity, count)
-    int32_t *link_off, *link_cap, *link_cnt;
-    int64_t *links;  // site * 32 + direction (push view: site + c_dir is solid)
+    // per-particle list segments (offset into the flat arrays, capacity, count);
+    // the bounce-back links of a sphere are those of its virtual-fluid sites
+    // (a link (x, i) ends on the solid site x + c_i, which has the fluid
+    // neighbour x), so only their number is kept
+    int32_t *link_cnt;
     int32_t *shell_off, *shell_cap, *shell_cnt;
     int32_t *shell;
     int32_t *ev_off, *ev_cap, *cov_cnt, *unc_cnt;
@@ -284,7 +287,7 @@ __device__ __forceinline__ uint32_t compute_info(long long n, const DevParams &P
         else any_fluid = true;
     }
     if (own == OWN_FLUID) return mask;
-    return (uint32_t)(any_fluid ? CLS_SHELL : CLS_SOLID) << CLS_SHIFT;
+    return any_fluid ? ((uint32_t)CLS_SHELL << CLS_SHIFT) | mask : (uint32_t)CLS_SOLID << CLS_SHIFT;
 }
 
 // velocity of the solid at the midpoint of the link from fluid site x along

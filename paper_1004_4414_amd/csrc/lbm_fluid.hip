@@ -153,16 +153,19 @@ __global__ __launch_bounds__(BLOCK) void k_shell_fill(DevParams P, DevParticles 
         const long long s = D.shell[off + k];
         int x, y, z;
         site_xyz(s, P, x, y, z);
+        // every neighbour's density is loaded (the addresses are in the box)
+        // and masked afterwards, so the loads of a site are in flight together
         T sum0 = 0, sum1 = 0;
         int nf = 0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const long long m = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
-            if (site_class(info[m]) == CLS_FLUID) {
-                sum0 += rho[sidx(0, (unsigned)m)];
-                sum1 += rho[sidx(1, (unsigned)m)];
-                ++nf;
-            }
+            const unsigned m =
+                (unsigned)site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
+            const bool fl = site_class(info[m]) == CLS_FLUID;
+            const T a0 = rho[sidx(0, m)], a1 = rho[sidx(1, m)];
+            sum0 += fl ? a0 : (T)0;
+            sum1 += fl ? a1 : (T)0;
+            nf += fl;
         }
         T r0 = nf ? sum0 / (T)nf : (T)0, r1 = nf ? sum1 / (T)nf : (T)0;
         if (col > 0.0) r0 += (T)fabs(col);
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(BLOCK) void k_wall_links(DevParams P, T *__restrict
     const int x = ax == 0 ? pos : u, y = ax == 1 ? pos : (ax == 0 ? u : v), z = ax == 2 ? pos : v;
     const unsigned n = (unsigned)(((long long)z * P.ny + y) * P.nx + x);
     const uint32_t inf = info[n];
-    if (site_class(inf) != CLS_FLUID && site_class(inf) != CLS_SHELL) return;
+    if (site_class(inf) != CLS_FLUID) return;
     uint32_t bits = inf & 0x7fffeu;
     while (bits) {
         const int i = __ffs(bits) - 1;

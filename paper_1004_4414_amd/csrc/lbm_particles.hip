@@ -63,67 +63,73 @@ __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &
 // ---------------------------------------------------------------------------
 // fluid force and torque on each sphere: bounce-back links, Eqs. (13)-(17),
 // and the Shan-Chen force on its virtual fluid, Eq. (28).
-// A link (x, i) has x fluid and x + c_i inside the sphere.  The streaming
-// kernel stored the bounced population f*_i(x) in slot (opp(i), x + c_i);
-// this kernel completes Eq. (16) there, f_opp(i)(x) = f*_i(x) - w^c with
-// w^c = 6 zeta_i rho^c(x) (c_i . u_b) (each link is visited once, by the
-// sphere that owns x + c_i), and adds the momentum given to the sphere,
+// The links of sphere p are found from its virtual-fluid sites s: a link
+// (x, i) has x = s - c_i fluid (bit opp(i) of the class word of s clear).
+// The streaming kernel stored the bounced population f*_i(x) in slot
+// (opp(i), s); this kernel completes Eq. (16) there, f_opp(i)(x) = f*_i(x) -
+// w^c with w^c = 6 zeta_i rho^c(x) (c_i . u_b) (each link is visited once, by
+// the sphere that owns s), and adds the momentum given to the sphere,
 // c_i sum_c (2 f*_i - w^c).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, T *__restrict__ fout,
-                                                                const T *__restrict__ rho, const T *__restrict__ fsc) {
+                                                                const T *__restrict__ rho, const T *__restrict__ fsc,
+                                                                const uint32_t *__restrict__ info) {
     __shared__ double lds[6 * BLOCK];
     const int p = blockIdx.x;
     double v[6] = {0, 0, 0, 0, 0, 0};
-    double R[3];
+    double R[3], U[3], W[3];
     load3(D.R, p, R);
+    load3(D.U, p, U);
+    load3(D.W, p, W);
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
-    const int nl = min(D.link_cnt[p], D.link_cap[p]), loff = D.link_off[p];
-    for (int k = threadIdx.x; k < nl; k += BLOCK) {
-        const long long e = D.links[loff + k];
-        const long long n = e >> 5;
-        const int i = (int)(e & 31);
-        int x, y, z;
-        site_xyz(n, P, x, y, z);
-        double ub[3], rb[3];
-        solid_velocity(P, D, p, x, y, z, i, ub, rb);
-        const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
-        const long long m = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
-        double s = 0.0;
-        for (int c = 0; c < 2; ++c) {
-            const T rc = rho[sidx(c, (unsigned)n)] + (T)P.rho_ref[c];
-            T *slot = fout + pidx(c, opp(i), (unsigned)m);
-            const T raw = *slot;
-            const T w = (T)(6.0 * zeta(i) * cub) * rc;
-            *slot = raw - w;
-            s += 2.0 * ((double)raw + zeta(i) * P.rho_ref[c]) - (double)w;
-        }
-        const double dp[3] = {cx(i) * s, cy(i) * s, cz(i) * s};
-        v[0] += dp[0];
-        v[1] += dp[1];
-        v[2] += dp[2];
-        v[3] += rb[1] * dp[2] - rb[2] * dp[1];
-        v[4] += rb[2] * dp[0] - rb[0] * dp[2];
-        v[5] += rb[0] * dp[1] - rb[1] * dp[0];
-    }
     const int ns = min(D.shell_cnt[p], D.shell_cap[p]), soff = D.shell_off[p];
     for (int k = threadIdx.x; k < ns; k += BLOCK) {
-        const long long n = D.shell[soff + k];
+        const unsigned s = (unsigned)D.shell[soff + k];
+        const uint32_t inf = info[s];
+        double F[3];
+        for (int a = 0; a < 3; ++a) F[a] = (double)fsc[vidx(a, s)];
         int x, y, z;
-        site_xyz(n, P, x, y, z);
+        site_xyz(s, P, x, y, z);
         const double pos[3] = {(double)x, (double)y, (double)z};
-        double r[3], F[3];
-        for (int a = 0; a < 3; ++a) {
-            r[a] = minimg(pos[a] - R[a], L[a]);
-            F[a] = (double)fsc[vidx(a, (unsigned)n)];
-        }
+        double r[3];
+        for (int a = 0; a < 3; ++a) r[a] = minimg(pos[a] - R[a], L[a]);
+        // Shan-Chen force on the virtual fluid at s
         v[0] += F[0];
         v[1] += F[1];
         v[2] += F[2];
         v[3] += r[1] * F[2] - r[2] * F[1];
         v[4] += r[2] * F[0] - r[0] * F[2];
         v[5] += r[0] * F[1] - r[1] * F[0];
+        // links (x = s - c_i, i): fluid neighbours of s, in direction order
+        uint32_t fl = ~inf & 0x7fffeu;
+        while (fl) {
+            const int j = __ffs(fl) - 1;  // s + c_j = x is fluid, i = opp(j)
+            fl &= fl - 1;
+            const int i = opp(j);
+            const unsigned m = (unsigned)site_of(wrapc(x + cx(j), P.nx), wrapc(y + cy(j), P.ny), wrapc(z + cz(j), P.nz), P);
+            // link midpoint x + c_i / 2 = s - c_i / 2 relative to the centre
+            const double rb[3] = {r[0] - 0.5 * cx(i), r[1] - 0.5 * cy(i), r[2] - 0.5 * cz(i)};
+            const double ub[3] = {U[0] + (W[1] * rb[2] - W[2] * rb[1]), U[1] + (W[2] * rb[0] - W[0] * rb[2]),
+                                  U[2] + (W[0] * rb[1] - W[1] * rb[0])};
+            const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
+            const T r0 = rho[sidx(0, m)], r1 = rho[sidx(1, m)];
+            T *slot0 = fout + pidx(0, j, s), *slot1 = fout + pidx(1, j, s);
+            const T raw0 = *slot0, raw1 = *slot1;
+            const T wz = (T)(6.0 * zeta(i) * cub);
+            const T w0 = wz * (r0 + (T)P.rho_ref[0]), w1 = wz * (r1 + (T)P.rho_ref[1]);
+            *slot0 = raw0 - w0;
+            *slot1 = raw1 - w1;
+            const double sum = (2.0 * ((double)raw0 + zeta(i) * P.rho_ref[0]) - (double)w0) +
+                               (2.0 * ((double)raw1 + zeta(i) * P.rho_ref[1]) - (double)w1);
+            const double dp[3] = {cx(i) * sum, cy(i) * sum, cz(i) * sum};
+            v[0] += dp[0];
+            v[1] += dp[1];
+            v[2] += dp[2];
+            v[3] += rb[1] * dp[2] - rb[2] * dp[1];
+            v[4] += rb[2] * dp[0] - rb[0] * dp[2];
+            v[5] += rb[0] * dp[1] - rb[1] * dp[0];
+        }
     }
     block_sum<6>(v, lds);
     if (threadIdx.x == 0)
@@ -305,56 +311,68 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
         v[4] += r[2] * mom[0] - r[0] * mom[2];
         v[5] += r[0] * mom[1] - r[1] * mom[0];
     }
+    // one wavefront per uncovered site: lane l < 18 takes the neighbour along
+    // c_(l+1), the densities are summed over the wavefront in a fixed order,
+    // lanes 0..37 write the 2 x 19 new populations
     const double sumrinit = P.rho_init[0] + P.rho_init[1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int fallback = 0;
-    for (int k = threadIdx.x; k < nu; k += BLOCK) {
+    for (int k = wave; k < nu; k += BLOCK / 64) {
         const long long n = D.unc[off + k];
         int x, y, z;
         site_xyz(n, P, x, y, z);
-        double rbar[2] = {0.0, 0.0};
-        int cnt = 0;
-        for (int i = 1; i < Q; ++i) {
-            const long long m = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
-            if (owner[m] != OWN_FLUID || stage[m] != STAGE_NONE) continue;
-            ++cnt;
-            int mx, my, mz;
-            site_xyz(m, P, mx, my, mz);
-            for (int c = 0; c < 2; ++c) {
-                double r = 0.0;
-                for (int q = 0; q < Q; ++q) {
-                    const long long src =
-                        site_of(wrapc(mx - cx(q), P.nx), wrapc(my - cy(q), P.ny), wrapc(mz - cz(q), P.nz), P);
-                    r += (double)f[pidx(c, q, (unsigned)src)];
+        double rn[2] = {0.0, 0.0};
+        bool use = false;
+        if (lane < Q - 1) {
+            const int i = lane + 1;
+            const int mx = wrapc(x + cx(i), P.nx), my = wrapc(y + cy(i), P.ny), mz = wrapc(z + cz(i), P.nz);
+            const long long m = site_of(mx, my, mz, P);
+            use = owner[m] == OWN_FLUID && stage[m] == STAGE_NONE;
+            if (use) {
+                for (int c = 0; c < 2; ++c) {
+                    double r = 0.0;
+                    for (int q = 0; q < Q; ++q) {
+                        const long long src =
+                            site_of(wrapc(mx - cx(q), P.nx), wrapc(my - cy(q), P.ny), wrapc(mz - cz(q), P.nz), P);
+                        r += (double)f[pidx(c, q, (unsigned)src)];
+                    }
+                    rn[c] = r + P.rho_ref[c];
                 }
-                rbar[c] += r + P.rho_ref[c];
             }
+        }
+        const int cnt = __popcll(__ballot(use));
+        for (int c = 0; c < 2; ++c) {
+            for (int o = 32; o > 0; o >>= 1) rn[c] += __shfl_down(rn[c], o, 64);
+            rn[c] = __shfl(rn[c], 0, 64);
         }
         double rnew[2];
         for (int c = 0; c < 2; ++c) {
-            rnew[c] = cnt > 0 ? rbar[c] / cnt : P.rho_init[c];
+            rnew[c] = cnt > 0 ? rn[c] / cnt : P.rho_init[c];
             if (P.c0 != 0.0 && P.rho_init[c] > 0.0) {
                 const double dM = st->Mstep[c] - st->M0[c];
                 rnew[c] *= 1.0 - P.c0 * (sumrinit / P.rho_init[c]) * dM / (double)N;
             }
         }
-        if (cnt == 0) ++fallback;
         const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
         const double us[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]), U[1] + (W[2] * r[0] - W[0] * r[2]),
                               U[2] + (W[0] * r[1] - W[1] * r[0])};
         const double u2 = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
-        for (int c = 0; c < 2; ++c)
-            for (int i = 0; i < Q; ++i) {
-                // written where the site reads it: slot (i, y - c_i), read by nobody else
-                const long long dst = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
-                f[pidx(c, i, (unsigned)dst)] =
-                    (T)(feq_dir<double>(i, rnew[c], us[0], us[1], us[2], u2, P.eq_order) - zeta(i) * P.rho_ref[c]);
-            }
-        double mom[3];
-        for (int a = 0; a < 3; ++a) mom[a] = (rnew[0] + rnew[1]) * us[a];
-        for (int a = 0; a < 3; ++a) v[a] -= mom[a];
-        v[3] -= r[1] * mom[2] - r[2] * mom[1];
-        v[4] -= r[2] * mom[0] - r[0] * mom[2];
-        v[5] -= r[0] * mom[1] - r[1] * mom[0];
+        if (lane < 2 * Q) {
+            // written where the site reads it: slot (i, y - c_i), read by nobody else
+            const int c = lane / Q, i = lane % Q;
+            const long long dst = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
+            f[pidx(c, i, (unsigned)dst)] =
+                (T)(feq_dir<double>(i, rnew[c], us[0], us[1], us[2], u2, P.eq_order) - zeta(i) * P.rho_ref[c]);
+        }
+        if (lane == 0) {
+            if (cnt == 0) ++fallback;
+            double mom[3];
+            for (int a = 0; a < 3; ++a) mom[a] = (rnew[0] + rnew[1]) * us[a];
+            for (int a = 0; a < 3; ++a) v[a] -= mom[a];
+            v[3] -= r[1] * mom[2] - r[2] * mom[1];
+            v[4] -= r[2] * mom[0] - r[0] * mom[2];
+            v[5] -= r[0] * mom[1] - r[1] * mom[0];
+        }
     }
     if (fallback) atomicAdd(&st->refill_fallback, (unsigned long long)fallback);
     block_sum<6>(v, lds);
@@ -406,45 +424,39 @@ __global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D,
     }
 }
 
-// virtual-fluid sites and bounce-back links of sphere p on the new map
+// virtual-fluid sites of sphere p on the new map, in scan order of its box,
+// and the number of its bounce-back links (fluid neighbours of those sites)
 __global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
                                                        const uint32_t *__restrict__ info, DevState *st) {
     __shared__ int lds[8];
+    __shared__ int nlink_block;
     const int p = blockIdx.x;
+    if (threadIdx.x == 0) nlink_block = 0;
     int lo[3], ext[3];
     new_box(P, D, p, lo, ext);
     const int V = ext[0] * ext[1] * ext[2];
     const int soff = D.shell_off[p], scap = D.shell_cap[p];
-    const int loff = D.link_off[p], lcap = D.link_cap[p];
     int nshell = 0, nlink = 0;
     for (int start = 0; start < V; start += BLOCK) {
         const int k = start + threadIdx.x;
-        bool mine = false;
-        int x = 0, y = 0, z = 0;
+        bool sh = false;
         long long n = 0;
         if (k < V) {
+            int x, y, z;
             box_site(k, lo, ext, P, x, y, z);
             n = site_of(x, y, z, P);
-            mine = owner[n] == p;
+            const uint32_t inf = info[n];
+            sh = owner[n] == p && site_class(inf) == CLS_SHELL;
+            if (sh) nlink += __popc(~inf & 0x7fffeu);
         }
-        const bool sh = mine && site_class(info[n]) == CLS_SHELL;
-        int slot = block_compact(sh, nshell, lds);
+        const int slot = block_compact(sh, nshell, lds);
         if (sh && slot < scap) D.shell[soff + slot] = (int32_t)n;
-        for (int i = 1; i < Q; ++i) {
-            bool lk = false;
-            long long m = 0;
-            if (mine) {
-                m = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
-                lk = owner[m] == OWN_FLUID;
-            }
-            slot = block_compact(lk, nlink, lds);
-            if (lk && slot < lcap) D.links[loff + slot] = (m << 5) | i;
-        }
     }
+    atomicAdd(&nlink_block, nlink);  // integer sum: order does not matter
+    __syncthreads();
     if (threadIdx.x == 0) {
         D.shell_cnt[p] = nshell;
-        D.link_cnt[p] = nlink;
-        if (nlink > lcap) atomicOr(&st->overflow, 1);
+        D.link_cnt[p] = nlink_block;
         if (nshell > scap) atomicOr(&st->overflow, 2);
     }
 }
@@ -455,11 +467,11 @@ __global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles
 void launch_particle_fluid_force(lb_handle *h, void *fout) {
     if (!h->np) return;
     if (h->prm.precision == LB_FP64)
-        k_particle_fluid_force<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (double *)fout,
-                                                                       (const double *)h->rho, (const double *)h->fsc);
+        k_particle_fluid_force<double><<<h->np, BLOCK, 0, h->stream>>>(
+            h->dp, h->dpart, (double *)fout, (const double *)h->rho, (const double *)h->fsc, h->info);
     else
-        k_particle_fluid_force<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (float *)fout,
-                                                                      (const float *)h->rho, (const float *)h->fsc);
+        k_particle_fluid_force<float><<<h->np, BLOCK, 0, h->stream>>>(
+            h->dp, h->dpart, (float *)fout, (const float *)h->rho, (const float *)h->fsc, h->info);
     LB_HIP_CHECK(hipGetLastError());
 }
 
