@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--workload", default="bijel256")
     ap.add_argument("--tile", default="0,0,0", help="fused-kernel tile TX,TY,TZ (0 = automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="before the run, copy a buffer of this many MiB device to device three times "
+                         "(a kernel of known traffic that calibrates rocprofv3's FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs one GPU "
@@ -75,6 +78,16 @@ def main():
 
     import torch
     from paper_1004_4414_amd import lbm, workloads as W
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"# calibration copy: 3 x {args.copy_mib} MiB read + {args.copy_mib} MiB written", file=sys.stderr,
+              flush=True)
 
     p, parts, _, precision = W.config(args.workload)
     N = p["nx"] * p["ny"] * p["nz"]

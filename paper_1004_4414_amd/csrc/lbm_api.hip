@@ -138,15 +138,16 @@ size_t fluid_bytes(const lb_params *p) {
     size_t b = 0;
     const size_t Np = padded_sites(N);
     b += 2 * (size_t)(2 * Q) * Np * ts;  // two population buffers
-    b += 7 * Np * ts;                    // densities, Psi, shell force
+    b += 8 * Np * ts;                    // densities, Psi, shell force (padded to 4)
     b += 3 * (size_t)N * 4;             // info, owner, stage
     b += 5 * (size_t)nblk(N) * 8 + 4096;
     return b;
 }
 
-size_t particle_bytes(int np, double max_r) {
+size_t particle_bytes(const lb_params *p, int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
-    size_t b = (size_t)np * (34 * 8 + 9 * 4);
+    const size_t cells = (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
+    size_t b = (size_t)np * (34 * 8 + 16 * 4) + 4 * cells;
     b += (size_t)np * sc * (4 + 2 * 4);  // virtual-fluid sites, covered and uncovered sites
     return b + 4096;
 }
@@ -159,10 +160,10 @@ void rebuild_map(lb_handle *h) {
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.Rprev, h->dpart.R, sizeof(double) * 3 * h->np, hipMemcpyDeviceToDevice,
                                 h->stream));
     launch_map_mark(h, false);
-    launch_map_commit(h);
+    launch_map_commit(h, true);
     launch_info_dense(h);
     launch_fill_int(h, h->stage, h->N, STAGE_NONE);
-    launch_build_lists(h);
+    launch_build_lists(h, true);
 }
 
 void free_particles(lb_handle *h) {
@@ -280,12 +281,13 @@ void one_step(lb_handle *h) {
         launch_particle_fluid_force(h, fout);
         launch_pair_forces(h);
         launch_integrate(h);
+        launch_fill_int(h, h->dpart.dirty, (long long)h->dpart.cgx * h->dpart.cgy * h->dpart.cgz, 0);
         launch_map_mark(h, true);
         launch_map_events(h);
         launch_cover_refill(h, fout);
-        launch_map_commit(h);
+        launch_map_commit(h, false);
         launch_map_info(h);
-        launch_build_lists(h);
+        launch_build_lists(h, false);
     }
     h->timing_end(2, t_step);
     h->cur = 1 - h->cur;
@@ -386,7 +388,7 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         h->f[1] = dev_alloc(h, fsz);
         h->rho = dev_alloc(h, (size_t)2 * Np * h->tsize);
         h->psi = dev_alloc(h, (size_t)2 * Np * h->tsize);
-        h->fsc = dev_alloc(h, (size_t)3 * Np * h->tsize);
+        h->fsc = dev_alloc(h, (size_t)4 * Np * h->tsize);
         h->info = (uint32_t *)dev_alloc(h, (size_t)h->N * 4);
         h->owner = (int32_t *)dev_alloc(h, (size_t)h->N * 4);
         h->stage = (int32_t *)dev_alloc(h, (size_t)h->N * 4);
@@ -519,7 +521,7 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     h->np = tot;
     DevParticles &D = h->dpart;
     double *dbl = (double *)dev_alloc(h, sizeof(double) * 34 * tot);
-    int32_t *i32 = (int32_t *)dev_alloc(h, sizeof(int32_t) * 9 * tot);
+    int32_t *i32 = (int32_t *)dev_alloc(h, sizeof(int32_t) * 10 * tot);
     h->part_allocs.push_back(dbl);
     h->part_allocs.push_back(i32);
     D.R = dbl;
@@ -545,6 +547,14 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.ev_cap = i32 + 6 * tot;
     D.cov_cnt = i32 + 7 * tot;
     D.unc_cnt = i32 + 8 * tot;
+    D.changed = i32 + 9 * tot;
+    D.cgx = (h->prm.nx + (1 << CELL_SHIFT) - 1) >> CELL_SHIFT;
+    D.cgy = (h->prm.ny + (1 << CELL_SHIFT) - 1) >> CELL_SHIFT;
+    D.cgz = (h->prm.nz + (1 << CELL_SHIFT) - 1) >> CELL_SHIFT;
+    D.dirty = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)D.cgx * D.cgy * D.cgz);
+    D.lbox = (int32_t *)dev_alloc(h, sizeof(int32_t) * 6 * (size_t)tot);
+    h->part_allocs.push_back(D.dirty);
+    h->part_allocs.push_back(D.lbox);
     D.shell = (int32_t *)dev_alloc(h, sizeof(int32_t) * ssum);
     D.cov = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.unc = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
@@ -566,7 +576,7 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
         hd[32 * tot + p] = 0.4 * m * rad[p] * rad[p];
         hd[33 * tot + p] = col[p];
     }
-    std::vector<int32_t> hi((size_t)9 * tot, 0);
+    std::vector<int32_t> hi((size_t)10 * tot, 0);
     for (int p = 0; p < tot; ++p) {
         hi[p] = pre[p];
         hi[2 * tot + p] = shell_off[p];
@@ -922,7 +932,7 @@ int lb_footprint_bytes(const lb_params *p, int32_t n_particles, double max_radiu
     std::string msg;
     const int rc = validate_params(p, msg);
     if (rc != LB_OK) return rc;
-    *bytes = fluid_bytes(p) + (n_particles ? particle_bytes(n_particles, max_radius) : 0);
+    *bytes = fluid_bytes(p) + (n_particles ? particle_bytes(p, n_particles, max_radius) : 0);
     return LB_OK;
 }
 

@@ -53,23 +53,47 @@ static_assert(cx(opp(13)) == -cx(13) && cz(opp(13)) == -cz(13) && norm2(12) == 2
 
 // ---------------------------------------------------------------------------
 // Memory layout.  Sites are grouped in storage blocks of VB = 64 consecutive
-// linear indices (one wavefront).  A block keeps all its values together, one
-// run of 64 sites per value: population (c, i) of site n lives at
-//   (n / 64) * (2*19*64) + (c*19 + i) * 64 + n % 64,
-// so a wavefront's load of one direction is a single aligned 256-byte run and
-// the whole block spans a few pages (a plane-per-direction layout would make
+// linear indices (one wavefront).  A block keeps all its populations
+// together, one run of 64 sites per direction, the two components of a site
+// side by side: population (c, i) of site n lives at
+//   (n / 64) * (2*19*64) + i * 128 + 2 * (n % 64) + c,
+// so a wavefront's load of one direction (both components) is a single
+// aligned 512-byte run, and one bounce-back link touches one 8-byte pair.
+// The whole block spans a few pages (a plane-per-direction layout would make
 // every wavefront touch ~80 pages and thrash the L1 TLB).  Two-component
-// scalar fields and 3-vectors use the same blocking.
+// fields are stored as pairs per site, 3-vectors padded to four.
 // ---------------------------------------------------------------------------
 constexpr unsigned VB = 64;
 __host__ __device__ __forceinline__ size_t pidx(int c, int i, unsigned n) {
-    return (size_t)(n / VB) * (2 * Q * VB) + (size_t)(c * Q + i) * VB + (n % VB);
+    return (size_t)(n / VB) * (2 * Q * VB) + (size_t)i * (2 * VB) + 2 * (size_t)(n % VB) + c;
 }
-__host__ __device__ __forceinline__ size_t sidx(int c, unsigned n) {
-    return (size_t)(n / VB) * (2 * VB) + (size_t)c * VB + (n % VB);
+__host__ __device__ __forceinline__ size_t sidx(int c, unsigned n) { return 2 * (size_t)n + c; }
+__host__ __device__ __forceinline__ size_t vidx(int a, unsigned n) { return 4 * (size_t)n + a; }
+
+// component pairs as one vector access
+template <typename T>
+struct PairOf;
+template <>
+struct PairOf<float> {
+    using type = float2;
+};
+template <>
+struct PairOf<double> {
+    using type = double2;
+};
+template <typename T>
+using Pair = typename PairOf<T>::type;
+// the pair at element index k (even)
+template <typename T>
+__device__ __forceinline__ Pair<T> load_pair(const T *__restrict__ a, size_t k) {
+    return *reinterpret_cast<const Pair<T> *>(a + k);
 }
-__host__ __device__ __forceinline__ size_t vidx(int a, unsigned n) {
-    return (size_t)(n / VB) * (3 * VB) + (size_t)a * VB + (n % VB);
+template <typename T>
+__device__ __forceinline__ void store_pair(T *__restrict__ a, size_t k, T v0, T v1) {
+    Pair<T> v;
+    v.x = v0;
+    v.y = v1;
+    *reinterpret_cast<Pair<T> *>(a + k) = v;
 }
 __host__ __device__ __forceinline__ size_t padded_sites(long long N) { return (size_t)((N + VB - 1) / VB) * VB; }
 
@@ -150,7 +174,14 @@ struct DevParticles {
     int32_t *shell;
     int32_t *ev_off, *ev_cap, *cov_cnt, *unc_cnt;
     int32_t *cov, *unc;
+    // map-update bookkeeping: changed[p] = the discrete sphere p changed this
+    // step; dirty[] = coarse cells (CELL^3 sites) whose class words changed
+    int32_t *changed;
+    int32_t *dirty;
+    int32_t *lbox;  // np x 6: box (lo, ext) of the last list build
+    int cgx, cgy, cgz;
 };
+constexpr int CELL_SHIFT = 3;  // coarse cells of 8^3 sites
 
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
@@ -397,8 +428,9 @@ __device__ __forceinline__ void pull_load(const T *__restrict__ fin, unsigned n,
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const unsigned src = i == 0 ? n : (unsigned)((int)n + o.template off<opp(i)>());
-        f[0][i] = fin[pidx(0, i, src)];
-        f[1][i] = fin[pidx(1, i, src)];
+        const Pair<T> v = load_pair(fin, pidx(0, i, src));
+        f[0][i] = v.x;
+        f[1][i] = v.y;
     });
 }
 
@@ -419,11 +451,14 @@ __device__ __forceinline__ void pull_load(const T *__restrict__ fin, unsigned n,
 #endif
 
 template <typename T>
-__device__ __forceinline__ void store_pop(T *p, T v) {
+__device__ __forceinline__ void store_pop_pair(T *p, T v0, T v1) {
+    Pair<T> v;
+    v.x = v0;
+    v.y = v1;
 #if LBM_NT_STORE
-    __builtin_nontemporal_store(v, p);
+    __builtin_nontemporal_store(v, reinterpret_cast<Pair<T> *>(p));
 #else
-    *p = v;
+    *reinterpret_cast<Pair<T> *>(p) = v;
 #endif
 }
 
@@ -436,16 +471,18 @@ __device__ __forceinline__ void hold_loads(const T (&v)[K]) {
     for (int k = 0; k < K; ++k) asm volatile("" ::"v"(v[k]));
 }
 
-// sum_i f_i(x) of component c (pull form)
+// sum_i f_i(x) of both components (pull form)
 template <typename T>
-__device__ __forceinline__ T pull_sum(const T *__restrict__ fin, int c, unsigned n, const NbrOffsets &o) {
-    T s = 0;
+__device__ __forceinline__ void pull_sum(const T *__restrict__ fin, unsigned n, const NbrOffsets &o, T &s0, T &s1) {
+    s0 = 0;
+    s1 = 0;
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const unsigned src = i == 0 ? n : (unsigned)((int)n + o.template off<opp(i)>());
-        s += fin[pidx(c, i, src)];
+        const Pair<T> v = load_pair(fin, pidx(0, i, src));
+        s0 += v.x;
+        s1 += v.y;
     });
-    return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -477,43 +514,42 @@ __device__ __forceinline__ void collide_and_store(const DevParams &P, T (&f)[2][
     }
     T ueq[2][3];
     eq_velocity(P, r, j, F, ueq);
-    if (rho_out && (inf & 0x7fffeu)) {  // density of a boundary site, read back by the link kernels
-        rho_out[sidx(0, n)] = dr[0];
-        rho_out[sidx(1, n)] = dr[1];
-    }
+    if (rho_out && (inf & 0x7fffeu))  // density of a boundary site, read back by the link kernels
+        store_pair(rho_out, sidx(0, n), dr[0], dr[1]);
     const int order = P.eq_order;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const T omega = (T)P.inv_tau[c];
-        const T ux = ueq[c][0], uy = ueq[c][1], uz = ueq[c][2];
-        const T u2 = ux * ux + uy * uy + uz * uz;
-        Unroll<Q>::run([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const T fs = f[c][i] - (f[c][i] - feq_dev_dir<T>(i, dr[c], r[c], ux, uy, uz, u2, order)) * omega;
-            store_pop(fout + pidx(c, i, n), fs);
-            if (i != 0 && (inf & (1u << i))) fout[pidx(c, opp(i), (unsigned)((int)n + o.template off<i>()))] = fs;
-        });
-    }
+    const T om0 = (T)P.inv_tau[0], om1 = (T)P.inv_tau[1];
+    const T u20 = ueq[0][0] * ueq[0][0] + ueq[0][1] * ueq[0][1] + ueq[0][2] * ueq[0][2];
+    const T u21 = ueq[1][0] * ueq[1][0] + ueq[1][1] * ueq[1][1] + ueq[1][2] * ueq[1][2];
+    Unroll<Q>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const T fs0 = f[0][i] - (f[0][i] - feq_dev_dir<T>(i, dr[0], r[0], ueq[0][0], ueq[0][1], ueq[0][2], u20, order)) * om0;
+        const T fs1 = f[1][i] - (f[1][i] - feq_dev_dir<T>(i, dr[1], r[1], ueq[1][0], ueq[1][1], ueq[1][2], u21, order)) * om1;
+        store_pop_pair(fout + pidx(0, i, n), fs0, fs1);
+        if (i != 0 && (inf & (1u << i)))
+            store_pair(fout, pidx(0, opp(i), (unsigned)((int)n + o.template off<i>())), fs0, fs1);
+    });
 }
 
 // ---------------------------------------------------------------------------
 // deterministic block reductions (blockDim.x == BLOCK)
 // ---------------------------------------------------------------------------
 template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double *lds /* K*BLOCK */) {
-    const int t = threadIdx.x;
+__device__ __forceinline__ void block_sum(double (&v)[K], double *lds /* >= K * BLOCK / 64 */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = BLOCK / 64;
 #pragma unroll
-    for (int k = 0; k < K; ++k) lds[k * BLOCK + t] = v[k];
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[k * NW + wave] = v[k];
     __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (t < s) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) lds[k * BLOCK + t] += lds[k * BLOCK + t + s];
-        }
-        __syncthreads();
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += lds[k * NW + w];
+        v[k] = t;
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = lds[k * BLOCK];
     __syncthreads();
 }
 

@@ -88,7 +88,7 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const T *__restrict__ f,
                                                    const uint32_t *__restrict__ info, T *__restrict__ rho,
                                                    T *__restrict__ psi, double *__restrict__ partial) {
-    __shared__ double lds[2 * BLOCK];
+    __shared__ double lds[2 * (BLOCK / 64)];
     double m[2] = {0.0, 0.0};
     unsigned n;
     int x, y, z;
@@ -96,16 +96,14 @@ __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const T *__restr
         const bool fluid = site_class(info[n]) == CLS_FLUID;
         const NbrOffsets o(P, x, y, z);
         const T irho0 = (T)P.inv_rho0;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            T dr = -(T)P.rho_ref[c];
-            if (fluid) {
-                dr = pull_sum(f, c, n, o);
-                m[c] = (double)dr + P.rho_ref[c];
-            }
-            rho[sidx(c, n)] = dr;
-            psi[sidx(c, n)] = psi_dev(dr, (T)P.psi_e[c], irho0);
+        T dr[2] = {-(T)P.rho_ref[0], -(T)P.rho_ref[1]};
+        if (fluid) {
+            pull_sum(f, n, o, dr[0], dr[1]);
+            m[0] = (double)dr[0] + P.rho_ref[0];
+            m[1] = (double)dr[1] + P.rho_ref[1];
         }
+        store_pair(rho, sidx(0, n), dr[0], dr[1]);
+        store_pair(psi, sidx(0, n), psi_dev(dr[0], (T)P.psi_e[0], irho0), psi_dev(dr[1], (T)P.psi_e[1], irho0));
     }
     if (partial) {
         block_sum<2>(m, lds);
@@ -116,24 +114,48 @@ __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const T *__restr
     }
 }
 
-// fixed-order sum of the per-block masses: M(t), baseline M(0), sentinel
-__global__ void k_finalize_mass(const double *__restrict__ partial, int nb, DevState *st) {
-    __shared__ double lds[2 * BLOCK];
-    double m[2] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < nb; b += BLOCK) {
-        m[0] += partial[2 * b];
-        m[1] += partial[2 * b + 1];
+// fixed-order sum of the per-block masses: M(t), baseline M(0), sentinel.
+// One block of FIN_THREADS; each thread keeps 8 independent partial sums so
+// that its loads are in flight together, then a fixed tree combines them.
+constexpr int FIN_THREADS = 1024;
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__restrict__ partial, int nb,
+                                                               DevState *st) {
+    __shared__ double lds[2][FIN_THREADS];
+    const int t = threadIdx.x;
+    double a[2][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[0][j] = a[1][j] = 0.0;
+    for (int b0 = t; b0 < nb; b0 += 8 * FIN_THREADS) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int b = b0 + j * FIN_THREADS;
+            if (b < nb) {
+                a[0][j] += partial[2 * b];
+                a[1][j] += partial[2 * b + 1];
+            }
+        }
     }
-    block_sum<2>(m, lds);
-    if (threadIdx.x == 0) {
-        st->Mstep[0] = m[0];
-        st->Mstep[1] = m[1];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+        lds[c][t] = ((a[c][0] + a[c][1]) + (a[c][2] + a[c][3])) + ((a[c][4] + a[c][5]) + (a[c][6] + a[c][7]));
+    __syncthreads();
+    for (int s = FIN_THREADS / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            lds[0][t] += lds[0][t + s];
+            lds[1][t] += lds[1][t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double m0 = lds[0][0], m1 = lds[1][0];
+        st->Mstep[0] = m0;
+        st->Mstep[1] = m1;
         if (!st->have_M0) {
-            st->M0[0] = m[0];
-            st->M0[1] = m[1];
+            st->M0[0] = m0;
+            st->M0[1] = m1;
             st->have_M0 = 1;
         }
-        if (!isfinite(m[0]) || !isfinite(m[1])) st->unstable = 1;
+        if (!isfinite(m0) || !isfinite(m1)) st->unstable = 1;
     }
 }
 
@@ -162,7 +184,8 @@ __global__ __launch_bounds__(BLOCK) void k_shell_fill(DevParams P, DevParticles 
             const unsigned m =
                 (unsigned)site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
             const bool fl = site_class(info[m]) == CLS_FLUID;
-            const T a0 = rho[sidx(0, m)], a1 = rho[sidx(1, m)];
+            const Pair<T> a = load_pair(rho, sidx(0, m));
+            const T a0 = a.x, a1 = a.y;
             sum0 += fl ? a0 : (T)0;
             sum1 += fl ? a1 : (T)0;
             nf += fl;
@@ -170,10 +193,8 @@ __global__ __launch_bounds__(BLOCK) void k_shell_fill(DevParams P, DevParticles 
         T r0 = nf ? sum0 / (T)nf : (T)0, r1 = nf ? sum1 / (T)nf : (T)0;
         if (col > 0.0) r0 += (T)fabs(col);
         if (col < 0.0) r1 += (T)fabs(col);
-        rho[sidx(0, (unsigned)s)] = r0;
-        rho[sidx(1, (unsigned)s)] = r1;
-        psi[sidx(0, (unsigned)s)] = psi_dev(r0, (T)P.psi_e[0], irho0);
-        psi[sidx(1, (unsigned)s)] = psi_dev(r1, (T)P.psi_e[1], irho0);
+        store_pair(rho, sidx(0, (unsigned)s), r0, r1);
+        store_pair(psi, sidx(0, (unsigned)s), psi_dev(r0, (T)P.psi_e[0], irho0), psi_dev(r1, (T)P.psi_e[1], irho0));
     }
 }
 
@@ -184,8 +205,9 @@ __device__ __forceinline__ void load_psi_neighbours(const T *__restrict__ psi, u
     Unroll<Q - 1>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value + 1;
         const unsigned m = (unsigned)((int)n + o.template off<i>());
-        pn[0][i - 1] = psi[sidx(0, m)];
-        pn[1][i - 1] = psi[sidx(1, m)];
+        const Pair<T> v = load_pair(psi, sidx(0, m));
+        pn[0][i - 1] = v.x;
+        pn[1][i - 1] = v.y;
     });
 }
 
@@ -361,7 +383,7 @@ __global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const T *__restri
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_sums(DevParams P, const T *__restrict__ fin,
                                                 const uint32_t *__restrict__ info, double *__restrict__ partial) {
-    __shared__ double lds[5 * BLOCK];
+    __shared__ double lds[5 * (BLOCK / 64)];
     double v[5] = {0, 0, 0, 0, 0};
     unsigned n;
     int x, y, z;
@@ -446,7 +468,7 @@ void launch_density(lb_handle *h, const void *f, bool partial_sums) {
 void launch_finalize_mass(lb_handle *h) { launch_finalize_mass_n(h, (int)dense_blocks(h)); }
 
 void launch_finalize_mass_n(lb_handle *h, int nb) {
-    k_finalize_mass<<<1, BLOCK, 0, h->stream>>>(h->partial, nb, h->dstate);
+    k_finalize_mass<<<1, FIN_THREADS, 0, h->stream>>>(h->partial, nb, h->dstate);
     LB_HIP_CHECK(hipGetLastError());
 }
 

@@ -91,8 +91,7 @@ __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles
                 T d0 = 0, d1 = 0;
                 if (site_class(inf) == CLS_FLUID && (!ring2 || (inf & 0x7fffeu))) {
                     const NbrOffsets o(P, x, y, za);
-                    d0 = pull_sum(fin, 0, (unsigned)n, o);
-                    d1 = pull_sum(fin, 1, (unsigned)n, o);
+                    pull_sum(fin, (unsigned)n, o, d0, d1);
                 }
                 sm.drho[slot][0][s] = d0;
                 sm.drho[slot][1][s] = d1;

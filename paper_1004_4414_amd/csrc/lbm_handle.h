@@ -85,9 +85,9 @@ void launch_integrate(lb_handle *h);
 void launch_map_mark(lb_handle *h, bool use_prev);
 void launch_map_events(lb_handle *h);
 void launch_cover_refill(lb_handle *h, void *fout);
-void launch_map_commit(lb_handle *h);
+void launch_map_commit(lb_handle *h, bool full);
 void launch_map_info(lb_handle *h);
-void launch_build_lists(lb_handle *h);
+void launch_build_lists(lb_handle *h, bool full);
 
 }  // namespace lbm
 

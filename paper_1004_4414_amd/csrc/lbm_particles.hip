@@ -51,6 +51,69 @@ __device__ __forceinline__ void union_box(const DevParams &P, const DevParticles
     }
 }
 
+// coarse cells touched by the box lo..lo+ext-1 grown by one site, per axis
+// (cells[a][0..n[a]), consecutive duplicates removed; a box wider than the
+// axis repeats cells, which is harmless); computed by thread 0 into LDS.
+// A box spanning more than MAX_AXIS_CELLS cells on an axis sets `wide`.
+constexpr int MAX_AXIS_CELLS = 64;
+struct AxisCells {
+    int n[3];
+    int wide;
+    int lo[3], ext[3];
+    int c[3][MAX_AXIS_CELLS];
+};
+__device__ __forceinline__ void axis_cells(const DevParams &P, const int lo[3], const int ext[3], AxisCells &ac) {
+    const int L[3] = {P.nx, P.ny, P.nz};
+    ac.wide = 0;
+    for (int a = 0; a < 3; ++a) {
+        ac.lo[a] = lo[a] - 1;
+        ac.ext[a] = ext[a] > 0 ? ext[a] + 2 : 0;
+        int k = 0, last = -1;
+        for (int u = lo[a] - 1; ext[a] > 0 && u <= lo[a] + ext[a]; ++u) {
+            const int cell = wrapany(u, L[a]) >> CELL_SHIFT;
+            if (cell != last) {
+                if (k == MAX_AXIS_CELLS) {
+                    ac.wide = 1;
+                    break;
+                }
+                ac.c[a][k++] = cell;
+            }
+            last = cell;
+        }
+        ac.n[a] = k;
+    }
+}
+__device__ __forceinline__ long long cell_of(const DevParticles &D, int x, int y, int z) {
+    return ((long long)(z >> CELL_SHIFT) * D.cgy + (y >> CELL_SHIFT)) * D.cgx + (x >> CELL_SHIFT);
+}
+// true in every thread when one of the cells is dirty (block-wide)
+__device__ __forceinline__ bool any_dirty(const DevParticles &D, const AxisCells &ac) {
+    if (ac.wide) return true;
+    const int tot = ac.n[0] * ac.n[1] * ac.n[2];
+    int hit = 0;
+    for (int k = threadIdx.x; k < tot; k += BLOCK) {
+        const int ca = ac.c[0][k % ac.n[0]], cb = ac.c[1][(k / ac.n[0]) % ac.n[1]], cc = ac.c[2][k / (ac.n[0] * ac.n[1])];
+        hit |= D.dirty[((long long)cc * D.cgy + cb) * D.cgx + ca] != 0;
+    }
+    return __syncthreads_or(hit) != 0;
+}
+__device__ __forceinline__ void mark_dirty(const DevParams &P, const DevParticles &D, const AxisCells &ac) {
+    if (ac.wide) {  // site by site over the grown box
+        const int V = ac.ext[0] * ac.ext[1] * ac.ext[2];
+        for (int k = threadIdx.x; k < V; k += BLOCK) {
+            int x, y, z;
+            box_site(k, ac.lo, ac.ext, P, x, y, z);
+            D.dirty[cell_of(D, x, y, z)] = 1;
+        }
+        return;
+    }
+    const int tot = ac.n[0] * ac.n[1] * ac.n[2];
+    for (int k = threadIdx.x; k < tot; k += BLOCK) {
+        const int ca = ac.c[0][k % ac.n[0]], cb = ac.c[1][(k / ac.n[0]) % ac.n[1]], cc = ac.c[2][k / (ac.n[0] * ac.n[1])];
+        D.dirty[((long long)cc * D.cgy + cb) * D.cgx + ca] = 1;
+    }
+}
+
 __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &D, int p, int lo[3], int ext[3]) {
     double R[3];
     load3(D.R, p, R);
@@ -71,68 +134,141 @@ __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &
 // the sphere that owns s), and adds the momentum given to the sphere,
 // c_i sum_c (2 f*_i - w^c).
 // ---------------------------------------------------------------------------
+// The virtual-fluid sites are taken in chunks of BLOCK, one per thread; the
+// links of a chunk are numbered by a block scan of their counts and then
+// handled LINKS_PER_PASS per thread with all their loads issued together.
+constexpr int LINKS_PER_PASS = 4;
+
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, T *__restrict__ fout,
                                                                 const T *__restrict__ rho, const T *__restrict__ fsc,
                                                                 const uint32_t *__restrict__ info) {
-    __shared__ double lds[6 * BLOCK];
-    const int p = blockIdx.x;
+    __shared__ double lds[6 * (BLOCK / 64)];
+    __shared__ int pre[BLOCK + 1];     // exclusive prefix of the link counts of the chunk's sites
+    __shared__ uint32_t fmask[BLOCK];  // fluid-neighbour masks of the chunk's sites
+    __shared__ unsigned sites[BLOCK];
+    __shared__ int wtot[BLOCK / 64];
+    const int p = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double v[6] = {0, 0, 0, 0, 0, 0};
     double R[3], U[3], W[3];
     load3(D.R, p, R);
     load3(D.U, p, U);
     load3(D.W, p, W);
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    const T ref0 = (T)P.rho_ref[0], ref1 = (T)P.rho_ref[1];
     const int ns = min(D.shell_cnt[p], D.shell_cap[p]), soff = D.shell_off[p];
-    for (int k = threadIdx.x; k < ns; k += BLOCK) {
-        const unsigned s = (unsigned)D.shell[soff + k];
-        const uint32_t inf = info[s];
-        double F[3];
-        for (int a = 0; a < 3; ++a) F[a] = (double)fsc[vidx(a, s)];
-        int x, y, z;
-        site_xyz(s, P, x, y, z);
-        const double pos[3] = {(double)x, (double)y, (double)z};
-        double r[3];
-        for (int a = 0; a < 3; ++a) r[a] = minimg(pos[a] - R[a], L[a]);
-        // Shan-Chen force on the virtual fluid at s
-        v[0] += F[0];
-        v[1] += F[1];
-        v[2] += F[2];
-        v[3] += r[1] * F[2] - r[2] * F[1];
-        v[4] += r[2] * F[0] - r[0] * F[2];
-        v[5] += r[0] * F[1] - r[1] * F[0];
-        // links (x = s - c_i, i): fluid neighbours of s, in direction order
-        uint32_t fl = ~inf & 0x7fffeu;
-        while (fl) {
-            const int j = __ffs(fl) - 1;  // s + c_j = x is fluid, i = opp(j)
-            fl &= fl - 1;
-            const int i = opp(j);
-            const unsigned m = (unsigned)site_of(wrapc(x + cx(j), P.nx), wrapc(y + cy(j), P.ny), wrapc(z + cz(j), P.nz), P);
-            // link midpoint x + c_i / 2 = s - c_i / 2 relative to the centre
-            const double rb[3] = {r[0] - 0.5 * cx(i), r[1] - 0.5 * cy(i), r[2] - 0.5 * cz(i)};
-            const double ub[3] = {U[0] + (W[1] * rb[2] - W[2] * rb[1]), U[1] + (W[2] * rb[0] - W[0] * rb[2]),
-                                  U[2] + (W[0] * rb[1] - W[1] * rb[0])};
-            const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
-            const T r0 = rho[sidx(0, m)], r1 = rho[sidx(1, m)];
-            T *slot0 = fout + pidx(0, j, s), *slot1 = fout + pidx(1, j, s);
-            const T raw0 = *slot0, raw1 = *slot1;
-            const T wz = (T)(6.0 * zeta(i) * cub);
-            const T w0 = wz * (r0 + (T)P.rho_ref[0]), w1 = wz * (r1 + (T)P.rho_ref[1]);
-            *slot0 = raw0 - w0;
-            *slot1 = raw1 - w1;
-            const double sum = (2.0 * ((double)raw0 + zeta(i) * P.rho_ref[0]) - (double)w0) +
-                               (2.0 * ((double)raw1 + zeta(i) * P.rho_ref[1]) - (double)w1);
-            const double dp[3] = {cx(i) * sum, cy(i) * sum, cz(i) * sum};
-            v[0] += dp[0];
-            v[1] += dp[1];
-            v[2] += dp[2];
-            v[3] += rb[1] * dp[2] - rb[2] * dp[1];
-            v[4] += rb[2] * dp[0] - rb[0] * dp[2];
-            v[5] += rb[0] * dp[1] - rb[1] * dp[0];
+    for (int c0 = 0; c0 < ns; c0 += BLOCK) {
+        // ---- one virtual-fluid site per thread: Shan-Chen force, link mask
+        const int k = c0 + t;
+        uint32_t fl = 0;
+        unsigned s = 0;
+        if (k < ns) {
+            s = (unsigned)D.shell[soff + k];
+            const uint32_t inf = info[s];
+            double F[3];
+            for (int a = 0; a < 3; ++a) F[a] = (double)fsc[vidx(a, s)];
+            int x, y, z;
+            site_xyz(s, P, x, y, z);
+            const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
+            v[0] += F[0];
+            v[1] += F[1];
+            v[2] += F[2];
+            v[3] += r[1] * F[2] - r[2] * F[1];
+            v[4] += r[2] * F[0] - r[0] * F[2];
+            v[5] += r[0] * F[1] - r[1] * F[0];
+            fl = ~inf & 0x7fffeu;  // s + c_j fluid: a link (s + c_j, opp(j))
         }
+        // ---- exclusive scan of the link counts (wave shuffles, then waves)
+        const int cnt = __popc(fl);
+        int inc = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
+        }
+        if (lane == 63) wtot[wave] = inc;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            if (w < wave) before += wtot[w];
+            total += wtot[w];
+        }
+        pre[t] = before + inc - cnt;
+        fmask[t] = fl;
+        sites[t] = s;
+        __syncthreads();
+        // ---- the chunk's links, LINKS_PER_PASS per thread per pass
+        for (int l0 = t; l0 < total; l0 += LINKS_PER_PASS * BLOCK) {
+            unsigned sl[LINKS_PER_PASS], ml[LINKS_PER_PASS];
+            int jl[LINKS_PER_PASS];
+            bool ok[LINKS_PER_PASS];
+            T r0[LINKS_PER_PASS], r1[LINKS_PER_PASS], raw0[LINKS_PER_PASS], raw1[LINKS_PER_PASS];
+#pragma unroll
+            for (int u = 0; u < LINKS_PER_PASS; ++u) {
+                const int l = l0 + u * BLOCK;
+                ok[u] = l < total;
+                sl[u] = 0;
+                ml[u] = 0;
+                jl[u] = 1;
+                if (ok[u]) {
+                    // the site: the largest chunk index whose prefix is <= l
+                    int lo = 0, hi = BLOCK - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (pre[mid] <= l) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    uint32_t m = fmask[lo];
+                    for (int q = l - pre[lo]; q > 0; --q) m &= m - 1;
+                    const int j = __ffs(m) - 1;
+                    const unsigned ss = sites[lo];
+                    int x, y, z;
+                    site_xyz(ss, P, x, y, z);
+                    sl[u] = ss;
+                    jl[u] = j;
+                    ml[u] = (unsigned)site_of(wrapc(x + cx(j), P.nx), wrapc(y + cy(j), P.ny), wrapc(z + cz(j), P.nz), P);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < LINKS_PER_PASS; ++u) {
+                const Pair<T> rr = load_pair(rho, sidx(0, ml[u]));
+                const Pair<T> ff = load_pair(fout, pidx(0, jl[u], sl[u]));
+                r0[u] = rr.x;
+                r1[u] = rr.y;
+                raw0[u] = ff.x;
+                raw1[u] = ff.y;
+            }
+#pragma unroll
+            for (int u = 0; u < LINKS_PER_PASS; ++u) {
+                if (!ok[u]) continue;
+                // link (x, i) with x = s + c_j fluid, i = opp(j); the stored f*_i(x) sits in slot (j, s)
+                const int j = jl[u], i = opp(j);
+                const unsigned ss = sl[u];
+                int x, y, z;
+                site_xyz(ss, P, x, y, z);
+                // lever arm at the link midpoint s - c_i/2 = s + c_j/2
+                const double rb[3] = {minimg(x + 0.5 * cx(j) - R[0], L[0]), minimg(y + 0.5 * cy(j) - R[1], L[1]),
+                                      minimg(z + 0.5 * cz(j) - R[2], L[2])};
+                const double ub[3] = {U[0] + (W[1] * rb[2] - W[2] * rb[1]), U[1] + (W[2] * rb[0] - W[0] * rb[2]),
+                                      U[2] + (W[0] * rb[1] - W[1] * rb[0])};
+                const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
+                const T wz = (T)(6.0 * zeta(i) * cub);
+                const T w0 = wz * (r0[u] + ref0), w1 = wz * (r1[u] + ref1);
+                store_pair(fout, pidx(0, j, ss), raw0[u] - w0, raw1[u] - w1);
+                const double sum = (2.0 * ((double)raw0[u] + zeta(i) * P.rho_ref[0]) - (double)w0) +
+                                   (2.0 * ((double)raw1[u] + zeta(i) * P.rho_ref[1]) - (double)w1);
+                const double dp[3] = {cx(i) * sum, cy(i) * sum, cz(i) * sum};
+                v[0] += dp[0];
+                v[1] += dp[1];
+                v[2] += dp[2];
+                v[3] += rb[1] * dp[2] - rb[2] * dp[1];
+                v[4] += rb[2] * dp[0] - rb[0] * dp[2];
+                v[5] += rb[0] * dp[1] - rb[1] * dp[0];
+            }
+        }
+        __syncthreads();  // the next chunk rewrites pre, fmask, sites and wtot
     }
     block_sum<6>(v, lds);
-    if (threadIdx.x == 0)
+    if (t == 0)
         for (int a = 0; a < 3; ++a) {
             D.Ffl[3 * p + a] = v[a];
             D.Tfl[3 * p + a] = v[3 + a];
@@ -146,7 +282,7 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
 // h < h_c, h clamped at h_min.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_pair_forces(DevParams P, DevParticles D) {
-    __shared__ double lds[3 * BLOCK];
+    __shared__ double lds[3 * (BLOCK / 64)];
     const int p = blockIdx.x;
     double Rp[3], Up[3];
     load3(D.R, p, Rp);
@@ -262,9 +398,26 @@ __global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles 
         slot = block_compact(unc, nunc, lds);
         if (unc && slot < cap) D.unc[off + slot] = (int32_t)n;
     }
+    // a site passing between two spheres is no event but changes both maps
+    int moved = 0;
+    for (int k = threadIdx.x; k < V; k += BLOCK) {
+        int x, y, z;
+        box_site(k, lo, ext, P, x, y, z);
+        const long long n = site_of(x, y, z, P);
+        const int32_t o = owner[n], s = stage[n];
+        moved |= (o >= 0 && o != p && s == p) || (o == p && s != STAGE_NONE && s != p);
+    }
+    const bool changed = __syncthreads_or(moved) != 0 || ncov > 0 || nunc > 0;
+    if (changed) {
+        __shared__ AxisCells ac;
+        if (threadIdx.x == 0) axis_cells(P, lo, ext, ac);
+        __syncthreads();
+        mark_dirty(P, D, ac);
+    }
     if (threadIdx.x == 0) {
         D.cov_cnt[p] = ncov;
         D.unc_cnt[p] = nunc;
+        D.changed[p] = changed ? 1 : 0;
         if (ncov > cap || nunc > cap) atomicOr(&st->overflow, 4);
     }
 }
@@ -279,7 +432,7 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticles D, T *__restrict__ f,
                                                         const int32_t *__restrict__ owner,
                                                         const int32_t *__restrict__ stage, DevState *st) {
-    __shared__ double lds[6 * BLOCK];
+    __shared__ double lds[6 * (BLOCK / 64)];
     const int p = blockIdx.x;
     const long long N = P.N;
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
@@ -290,6 +443,7 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
     double v[6] = {0, 0, 0, 0, 0, 0};
     const int off = D.ev_off[p], cap = D.ev_cap[p];
     const int nc = min(D.cov_cnt[p], cap), nu = min(D.unc_cnt[p], cap);
+    if (nc == 0 && nu == 0) return;  // uniform over the block
     for (int k = threadIdx.x; k < nc; k += BLOCK) {
         const long long n = D.cov[off + k];
         int x, y, z;
@@ -388,8 +542,11 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
 
 // new owners of the sites in the box (identical values from every block)
 __global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles D, int32_t *__restrict__ owner,
-                                                      const int32_t *__restrict__ stage) {
+                                                      const int32_t *__restrict__ stage, int full) {
     const int p = blockIdx.x;
+    // an unchanged sphere's box holds no change of its own; changes of other
+    // spheres inside it are written by their blocks
+    if (!full && !D.changed[p]) return;
     int lo[3], ext[3];
     union_box(P, D, p, 0, lo, ext);
     const int V = ext[0] * ext[1] * ext[2];
@@ -407,13 +564,16 @@ __global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D,
                                                     uint32_t *__restrict__ info, int32_t *__restrict__ stage) {
     const int p = blockIdx.x;
     int lo[3], ext[3];
-    union_box(P, D, p, 1, lo, ext);
-    int V = ext[0] * ext[1] * ext[2];
-    for (int k = threadIdx.x; k < V; k += BLOCK) {
-        int x, y, z;
-        box_site(k, lo, ext, P, x, y, z);
-        const long long n = site_of(x, y, z, P);
-        info[n] = compute_info(n, P, owner);
+    int V;
+    if (D.changed[p]) {
+        union_box(P, D, p, 1, lo, ext);
+        V = ext[0] * ext[1] * ext[2];
+        for (int k = threadIdx.x; k < V; k += BLOCK) {
+            int x, y, z;
+            box_site(k, lo, ext, P, x, y, z);
+            const long long n = site_of(x, y, z, P);
+            info[n] = compute_info(n, P, owner);
+        }
     }
     new_box(P, D, p, lo, ext);
     V = ext[0] * ext[1] * ext[2];
@@ -427,13 +587,29 @@ __global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D,
 // virtual-fluid sites of sphere p on the new map, in scan order of its box,
 // and the number of its bounce-back links (fluid neighbours of those sites)
 __global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                                       const uint32_t *__restrict__ info, DevState *st) {
+                                                       const uint32_t *__restrict__ info, DevState *st, int full) {
     __shared__ int lds[8];
     __shared__ int nlink_block;
+    __shared__ AxisCells ac;
     const int p = blockIdx.x;
     if (threadIdx.x == 0) nlink_block = 0;
     int lo[3], ext[3];
     new_box(P, D, p, lo, ext);
+    int32_t *lb = D.lbox + 6 * p;
+    if (!full) {
+        // the lists are the box scan of the class words within one site of the
+        // box; when none of them changed this step and the box is the one of
+        // the last build, the lists stand (and equal a rebuild)
+        const bool same = lo[0] == lb[0] && lo[1] == lb[1] && lo[2] == lb[2] && ext[0] == lb[3] &&
+                          ext[1] == lb[4] && ext[2] == lb[5];
+        if (threadIdx.x == 0) axis_cells(P, lo, ext, ac);
+        __syncthreads();
+        if (!any_dirty(D, ac) && same) return;  // `same` is uniform over the block
+    }
+    if (threadIdx.x < 3) {
+        lb[threadIdx.x] = lo[threadIdx.x];
+        lb[3 + threadIdx.x] = ext[threadIdx.x];
+    }
     const int V = ext[0] * ext[1] * ext[2];
     const int soff = D.shell_off[p], scap = D.shell_cap[p];
     int nshell = 0, nlink = 0;
@@ -510,9 +686,9 @@ void launch_cover_refill(lb_handle *h, void *fout) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
-void launch_map_commit(lb_handle *h) {
+void launch_map_commit(lb_handle *h, bool full) {
     if (!h->np) return;
-    k_map_commit<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage);
+    k_map_commit<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage, full ? 1 : 0);
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -522,9 +698,9 @@ void launch_map_info(lb_handle *h) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
-void launch_build_lists(lb_handle *h) {
+void launch_build_lists(lb_handle *h, bool full) {
     if (!h->np) return;
-    k_build_lists<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->info, h->dstate);
+    k_build_lists<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->info, h->dstate, full ? 1 : 0);
     LB_HIP_CHECK(hipGetLastError());
 }
 
