@@ -27,9 +27,9 @@ METRIC = "MLUPS (2-comp D3Q19 + spheres) at 256^3 vs HBM roofline; jobs/hour + p
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes_per_site(precision, kernel):
-    """Populations read once and written once: 2 components x 19 x (4 or 8) B x 2."""
-    ts = 8 if precision == "fp64" else 4
+def algorithmic_bytes_per_site(precision):
+    """Populations read once and written once: 2 components x 19 x (2, 4 or 8) B x 2."""
+    ts = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[precision]
     return 2 * 19 * ts * 2
 
 
@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--workload", default="bijel256")
     ap.add_argument("--tile", default="0,0,0", help="fused-kernel tile TX,TY,TZ (0 = automatic)")
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp16", "bf16"],
+                    help="population storage (default: the workload's); fp16/bf16 store deviations and compute in FP32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the run, copy a buffer of this many MiB device to device three times "
@@ -90,6 +92,8 @@ def main():
               flush=True)
 
     p, parts, _, precision = W.config(args.workload)
+    if args.precision:
+        precision = args.precision
     N = p["nx"] * p["ny"] * p["nz"]
     tile = tuple(int(v) for v in args.tile.split(","))
     lat = lbm.Lattice(p, precision=precision, kernel=args.kernel, tile=tile)
@@ -113,7 +117,7 @@ def main():
           f"step (events) {s_ms / max(s_n, 1):.3f} ms; links {obs['n_links']}", file=sys.stderr, flush=True)
 
     mlups = N * args.steps / elapsed / 1e6
-    bps = algorithmic_bytes_per_site(precision, args.kernel)
+    bps = algorithmic_bytes_per_site(precision)
     sweep_s = k_ms / 1e3 / max(k_n, 1)
     achieved = bps * N / sweep_s / 1e9
     line = {
@@ -127,16 +131,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if precision == "fp32" else "f64",
+        "dtype": "f64" if precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {
             "workload": "bijel256: 256^3 periodic, 50:50 at 0.35+-0.01, g=0.08, tau=1, "
-                        "4806 spheres r=5 (volume fraction 0.15), neutral wettability, FP32 populations"
+                        f"4806 spheres r=5 (volume fraction 0.15), neutral wettability, {precision.upper()} populations"
             if args.workload == "bijel256" else args.workload,
             "sites": N,
             "spheres": len(parts["radius"]),
             "kernel": args.kernel,
             "tile": args.tile,
+            "storage": precision,
         },
         "roofline": {
             "bound": "hbm",

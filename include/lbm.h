@@ -52,7 +52,12 @@ enum {
     LB_ECAPACITY = -7  /* a per-particle list overflowed (a sphere moved too far in one step) */
 };
 
-enum { LB_FP64 = 0, LB_FP32 = 1 };
+/* Precision of the fluid. LB_FP64 and LB_FP32 store and compute in that type
+ * (FP32 stores f_i - zeta_i rho_init to keep rounding relative to the
+ * deviations). LB_FP16 and LB_BF16 store those deviations in 16 bits (round to
+ * nearest) and compute every update in FP32; densities, forces and all
+ * global and per-sphere sums stay FP32 / FP64. */
+enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP16 = 2, LB_BF16 = 3 };
 
 /* Fluid kernel variants. LB_KERNEL_FUSED: one sweep per step that computes
  * densities, virtual fluid, Shan-Chen force, collision and streaming with
@@ -72,7 +77,7 @@ typedef struct {
 
 typedef struct {
     int32_t nx, ny, nz;      /* periodic box, each >= 4 */
-    int32_t precision;       /* LB_FP64 or LB_FP32: storage and arithmetic of the fluid */
+    int32_t precision;       /* LB_FP64, LB_FP32, LB_FP16 or LB_BF16 (storage of the populations) */
     double tau[2];           /* BGK relaxation time per component, Sec. II, > 1/2 */
     double g_br;             /* Shan-Chen coupling g_rb = g_br of Eq. (4); g_rr = g_bb = 0 */
     double rho0;             /* reference density in the effective mass of Eq. (5), > 0 */

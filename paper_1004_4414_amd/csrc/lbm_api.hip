@@ -88,7 +88,7 @@ void set_dev_params(lb_handle *h) {
         d.rho_init[c] = p.rho_init[c];
         // FP32 keeps deviations from the rest state of the mean density, which
         // carries the small flow signal with ~50x finer resolution; FP64 keeps f
-        d.rho_ref[c] = p.precision == LB_FP32 ? p.rho_init[c] : 0.0;
+        d.rho_ref[c] = p.precision == LB_FP64 ? 0.0 : p.rho_init[c];
         d.psi_e[c] = p.rho0 * std::exp(-d.rho_ref[c] / p.rho0);
         d.inv_tau[c] = 1.0 / p.tau[c];
     }
@@ -118,7 +118,9 @@ int validate_params(const lb_params *p, std::string &msg) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return msg = "box edges must be >= 1", LB_EINVAL;
     const long long N = (long long)p->nx * p->ny * p->nz;
     if (N > 0x7fffffffLL / 2) return msg = "box too large (sites must fit 30 bits)", LB_EINVAL;
-    if (p->precision != LB_FP64 && p->precision != LB_FP32) return msg = "unknown precision", LB_EINVAL;
+    if (p->precision < LB_FP64 || p->precision > LB_BF16) return msg = "unknown precision", LB_EINVAL;
+    if ((p->precision == LB_FP16 || p->precision == LB_BF16) && p->kernel == LB_KERNEL_FUSED)
+        return msg = "the fused kernel stores FP32 or FP64 populations only", LB_EINVAL;
     for (int c = 0; c < 2; ++c)
         if (!(p->tau[c] > 0.5)) return msg = "tau must exceed 1/2", LB_EINVAL;
     if (!(p->rho0 > 0.0)) return msg = "rho0 must be positive", LB_EINVAL;
@@ -132,13 +134,33 @@ int validate_params(const lb_params *p, std::string &msg) {
     return LB_OK;
 }
 
+size_t pop_bytes(int precision) {
+    return precision == LB_FP64 ? 8 : (precision == LB_FP16 || precision == LB_BF16 ? 2 : 4);
+}
+
+// host conversions of stored populations
+double to_double(double v) { return v; }
+double to_double(float v) { return v; }
+double to_double(__half v) { return (double)__half2float(v); }
+double to_double(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
+template <typename T>
+T from_double(double v);
+template <>
+double from_double<double>(double v) { return v; }
+template <>
+float from_double<float>(double v) { return (float)v; }
+template <>
+__half from_double<__half>(double v) { return __float2half((float)v); }
+template <>
+__hip_bfloat16 from_double<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
+
 size_t fluid_bytes(const lb_params *p) {
     const long long N = (long long)p->nx * p->ny * p->nz;
-    const size_t ts = p->precision == LB_FP64 ? 8 : 4;
+    const size_t ts = pop_bytes(p->precision), tc = p->precision == LB_FP64 ? 8 : 4;
     size_t b = 0;
     const size_t Np = padded_sites(N);
     b += 2 * (size_t)(2 * Q) * Np * ts;  // two population buffers
-    b += 8 * Np * ts;                    // densities, Psi, shell force (padded to 4)
+    b += 8 * Np * tc;                    // densities, Psi, shell force (padded to 4)
     b += 3 * (size_t)N * 4;             // info, owner, stage
     b += 5 * (size_t)nblk(N) * 8 + 4096;
     return b;
@@ -177,7 +199,7 @@ void free_particles(lb_handle *h) {
 template <typename T>
 void to_host_populations(lb_handle *h, double *out) {
     const long long N = h->N;
-    std::vector<T> buf((size_t)2 * Q * padded_sites(N));
+    std::vector<T> buf((size_t)2 * Q * padded_sites(N));  // T: the storage type
     std::vector<int32_t> own((size_t)N);
     LB_HIP_CHECK(hipMemcpyAsync(buf.data(), h->f[h->cur], buf.size() * sizeof(T), hipMemcpyDeviceToHost, h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(own.data(), h->owner, own.size() * 4, hipMemcpyDeviceToHost, h->stream));
@@ -193,7 +215,7 @@ void to_host_populations(lb_handle *h, double *out) {
                         const long long n = ((long long)z * ny + y) * nx + x;
                         const long long src = ((long long)((z - cz(i) + nz) % nz) * ny + (y - cy(i) + ny) % ny) * nx +
                                               (x - cx(i) + nx) % nx;  // f_i(x) = slot (i, x - c_i)
-                        dst[n] = own[n] == OWN_FLUID ? (double)buf[pidx(c, i, (unsigned)src)] + w : 0.0;
+                        dst[n] = own[n] == OWN_FLUID ? to_double(buf[pidx(c, i, (unsigned)src)]) + w : 0.0;
                     }
         }
 }
@@ -217,7 +239,7 @@ void from_host_populations(lb_handle *h, const double *in) {
                         if (own[n] != OWN_FLUID) continue;
                         const long long dst = ((long long)((z - cz(i) + nz) % nz) * ny + (y - cy(i) + ny) % ny) * nx +
                                               (x - cx(i) + nx) % nx;
-                        buf[pidx(c, i, (unsigned)dst)] = (T)(src[n] - w);
+                        buf[pidx(c, i, (unsigned)dst)] = from_double<T>(src[n] - w);
                     }
         }
     LB_HIP_CHECK(hipMemcpyAsync(h->f[h->cur], buf.data(), buf.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
@@ -243,10 +265,9 @@ void choose_fused_tile(lb_handle *h) {
     auto fits = [&](int a, int b) { return a <= p.nx - 2 && b <= p.ny - 2; };
     bool known;
     if (p.precision == LB_FP64)
-        known = (tx == 32 && ty == 4) || (tx == 64 && ty == 4) || (tx == 16 && ty == 8);
+        known = (tx == 32 && ty == 4) || (tx == 16 && ty == 8);
     else
-        known = (tx == 64 && ty == 4) || (tx == 64 && ty == 8) || (tx == 32 && ty == 8) || (tx == 32 && ty == 4) ||
-                (tx == 128 && ty == 2) || (tx == 16 && ty == 8);
+        known = (tx == 64 && ty == 4) || (tx == 32 && ty == 8) || (tx == 32 && ty == 4) || (tx == 16 && ty == 8);
     if (!known || !fits(tx, ty)) {
         if (p.precision != LB_FP64 && fits(64, 4)) tx = 64, ty = 4;
         else if (fits(32, 4)) tx = 32, ty = 4;
@@ -372,12 +393,15 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         h->have_alloc = true;
     }
     h->N = (long long)p->nx * p->ny * p->nz;
-    h->tsize = p->precision == LB_FP64 ? 8 : 4;
+    h->tsize = pop_bytes(p->precision);
+    h->csize = p->precision == LB_FP64 ? 8 : 4;
     if (p->kernel == LB_KERNEL_FUSED && !fused_supported(*p)) {
         delete h;
         return LB_EINVAL;
     }
-    h->kernel = p->kernel == LB_KERNEL_AUTO ? (fused_supported(*p) ? LB_KERNEL_FUSED : LB_KERNEL_TWOPASS) : p->kernel;
+    const bool wide = p->precision == LB_FP64 || p->precision == LB_FP32;
+    h->kernel = p->kernel == LB_KERNEL_AUTO ? (wide && fused_supported(*p) ? LB_KERNEL_FUSED : LB_KERNEL_TWOPASS)
+                                            : p->kernel;
     for (int a = 0; a < 3; ++a) h->tile[a] = p->tile[a];
     choose_fused_tile(h);
     set_dev_params(h);
@@ -386,9 +410,9 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         const size_t fsz = (size_t)2 * Q * Np * h->tsize;
         h->f[0] = dev_alloc(h, fsz);
         h->f[1] = dev_alloc(h, fsz);
-        h->rho = dev_alloc(h, (size_t)2 * Np * h->tsize);
-        h->psi = dev_alloc(h, (size_t)2 * Np * h->tsize);
-        h->fsc = dev_alloc(h, (size_t)4 * Np * h->tsize);
+        h->rho = dev_alloc(h, (size_t)2 * Np * h->csize);
+        h->psi = dev_alloc(h, (size_t)2 * Np * h->csize);
+        h->fsc = dev_alloc(h, (size_t)4 * Np * h->csize);
         h->info = (uint32_t *)dev_alloc(h, (size_t)h->N * 4);
         h->owner = (int32_t *)dev_alloc(h, (size_t)h->N * 4);
         h->stage = (int32_t *)dev_alloc(h, (size_t)h->N * 4);
@@ -678,8 +702,7 @@ int lb_get_fields(lb_handle *h, double *rho, double *j, double *force, double *u
 int lb_get_populations(lb_handle *h, double *f) {
     if (!h || !f) return LB_EINVAL;
     LB_API_BEGIN
-    if (h->prm.precision == LB_FP64) to_host_populations<double>(h, f);
-    else to_host_populations<float>(h, f);
+    with_storage(h->prm, [&](auto tag) { to_host_populations<typename decltype(tag)::type>(h, f); });
     return LB_OK;
     LB_API_END
 }
@@ -687,8 +710,7 @@ int lb_get_populations(lb_handle *h, double *f) {
 int lb_set_populations(lb_handle *h, const double *f) {
     if (!h || !f) return LB_EINVAL;
     LB_API_BEGIN
-    if (h->prm.precision == LB_FP64) from_host_populations<double>(h, f);
-    else from_host_populations<float>(h, f);
+    with_storage(h->prm, [&](auto tag) { from_host_populations<typename decltype(tag)::type>(h, f); });
     return LB_OK;
     LB_API_END
 }

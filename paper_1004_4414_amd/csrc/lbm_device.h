@@ -6,6 +6,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
 #include <stdint.h>
 
 #include <type_traits>
@@ -83,7 +85,7 @@ struct PairOf<double> {
 };
 template <typename T>
 using Pair = typename PairOf<T>::type;
-// the pair at element index k (even)
+// the pair at element index k (even) of an array of the arithmetic type
 template <typename T>
 __device__ __forceinline__ Pair<T> load_pair(const T *__restrict__ a, size_t k) {
     return *reinterpret_cast<const Pair<T> *>(a + k);
@@ -94,6 +96,59 @@ __device__ __forceinline__ void store_pair(T *__restrict__ a, size_t k, T v0, T 
     v.x = v0;
     v.y = v1;
     *reinterpret_cast<Pair<T> *>(a + k) = v;
+}
+
+// Population storage types.  S is the stored scalar and Cmp<S> the type the
+// arithmetic runs in: FP64 and FP32 store what they compute; FP16 and BF16
+// store the deviations f_i - zeta_i rho_ref rounded to nearest, and every
+// update runs in FP32.  Populations move as component pairs (4, 8 or 16 B).
+template <typename S>
+struct Storage;
+template <>
+struct Storage<double> {
+    using T = double;
+    __device__ static double2 load(const double *a, size_t k) { return *reinterpret_cast<const double2 *>(a + k); }
+    __device__ static void store(double *a, size_t k, double x, double y) {
+        *reinterpret_cast<double2 *>(a + k) = make_double2(x, y);
+    }
+};
+template <>
+struct Storage<float> {
+    using T = float;
+    __device__ static float2 load(const float *a, size_t k) { return *reinterpret_cast<const float2 *>(a + k); }
+    __device__ static void store(float *a, size_t k, float x, float y) {
+        *reinterpret_cast<float2 *>(a + k) = make_float2(x, y);
+    }
+};
+template <>
+struct Storage<__half> {
+    using T = float;
+    __device__ static float2 load(const __half *a, size_t k) {
+        return __half22float2(*reinterpret_cast<const __half2 *>(a + k));
+    }
+    __device__ static void store(__half *a, size_t k, float x, float y) {
+        *reinterpret_cast<__half2 *>(a + k) = __floats2half2_rn(x, y);
+    }
+};
+template <>
+struct Storage<__hip_bfloat16> {
+    using T = float;
+    __device__ static float2 load(const __hip_bfloat16 *a, size_t k) {
+        return __bfloat1622float2(*reinterpret_cast<const __hip_bfloat162 *>(a + k));
+    }
+    __device__ static void store(__hip_bfloat16 *a, size_t k, float x, float y) {
+        *reinterpret_cast<__hip_bfloat162 *>(a + k) = __float22bfloat162_rn(make_float2(x, y));
+    }
+};
+template <typename S>
+using Cmp = typename Storage<S>::T;
+template <typename S>
+__device__ __forceinline__ Pair<Cmp<S>> load_pop(const S *__restrict__ a, size_t k) {
+    return Storage<S>::load(a, k);
+}
+template <typename S>
+__device__ __forceinline__ void store_pop(S *__restrict__ a, size_t k, Cmp<S> v0, Cmp<S> v1) {
+    Storage<S>::store(a, k, v0, v1);
 }
 __host__ __device__ __forceinline__ size_t padded_sites(long long N) { return (size_t)((N + VB - 1) / VB) * VB; }
 
@@ -362,16 +417,28 @@ __device__ __forceinline__ void moments(const T (&f)[Q], T ref, T &dr, T &r, T &
     });
 }
 
+// Compile-time choices of the collision: velocity_mode 0 = common Shan-Chen
+// velocity, 1 = per-component velocity (Sec. II); eq_order 2 or 3 (Eq. (3)).
+template <int VM, int EO>
+struct Model {
+    static constexpr int velocity_mode = VM;
+    static constexpr int eq_order = EO;
+};
+
+// reciprocal: the hardware approximation (1 ulp) in FP32, exact division in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // equilibrium velocities of both components (Sec. II, Eq. (6))
-template <typename T>
+template <typename T, int VM>
 __device__ __forceinline__ void eq_velocity(const DevParams &P, const T r[2], const T j[2][3], const T F[2][3],
                                             T ueq[2][3]) {
     T ubar[3] = {0, 0, 0};
-    if (P.velocity_mode == 0) {
+    if (VM == 0) {
         const T it0 = (T)P.inv_tau[0], it1 = (T)P.inv_tau[1];
         const T den = r[0] * it0 + r[1] * it1;
         if (den != (T)0) {
-            const T iden = (T)1 / den;
+            const T iden = recip(den);
 #pragma unroll
             for (int a = 0; a < 3; ++a) ubar[a] = (j[0][a] * it0 + j[1][a] * it1) * iden;
         }
@@ -379,14 +446,68 @@ __device__ __forceinline__ void eq_velocity(const DevParams &P, const T r[2], co
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const T tau = (T)P.tau[c];
-        const bool live = r[c] != (T)0;
-        const T ir = live ? (T)1 / r[c] : (T)0;
+        // zero density: the component is inert (no velocity, no shift)
+        const T ir = r[c] != (T)0 ? recip(r[c]) : (T)0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            // zero density: the component is inert (no velocity, no shift)
-            const T base = P.velocity_mode == 1 ? j[c][a] * ir : ubar[a];
+            const T base = VM == 1 ? j[c][a] * ir : ubar[a];
             ueq[c][a] = base + tau * F[c][a] * ir;
         }
+    }
+}
+
+// BGK relaxation, Eqs. (2), (3), of one component's stored deviations
+// d_i = f_i - zeta_i rho_ref toward f^eq_i - zeta_i rho_ref, with opposite
+// directions taken together: for the pair (i, opp(i)) the bracket of Eq. (3)
+// minus one splits into a part even in c_i.u, 4.5 (c.u)^2 - 1.5 u^2, and an
+// odd part, c.u (3 + 4.5 (c.u)^2 - 4.5 u^2) (third order) or 3 c.u.
+template <typename T, int EO>
+__device__ __forceinline__ void relax(T (&f)[Q], T dr, T r, T ux, T uy, T uz, T om) {
+    const T u2 = ux * ux + uy * uy + uz * uz;
+    const T m15u2 = (T)-1.5 * u2;
+    const T k3 = EO >= 3 ? (T)3 - (T)4.5 * u2 : (T)3;
+    {
+        const T feq = (T)(1.0 / 3.0) * (dr + r * m15u2);
+        f[0] = f[0] + om * (feq - f[0]);
+    }
+    const T zdr_f = (T)(1.0 / 18.0) * dr, zr_f = (T)(1.0 / 18.0) * r;
+    const T zdr_e = (T)(1.0 / 36.0) * dr, zr_e = (T)(1.0 / 36.0) * r;
+    Unroll<Q / 2>::run([&](auto kc) {
+        constexpr int i = 2 * decltype(kc)::value + 1;  // i + 1 = opp(i)
+        T cu = 0;
+        if (cx(i)) cu += cx(i) > 0 ? ux : -ux;
+        if (cy(i)) cu += cy(i) > 0 ? uy : -uy;
+        if (cz(i)) cu += cz(i) > 0 ? uz : -uz;
+        const T cu2 = cu * cu;
+        const T even = (T)4.5 * cu2 + m15u2;
+        const T odd = EO >= 3 ? cu * ((T)4.5 * cu2 + k3) : (T)3 * cu;
+        const T zr = norm2(i) == 1 ? zr_f : zr_e, zdr = norm2(i) == 1 ? zdr_f : zdr_e;
+        const T A = zdr + zr * even, B = zr * odd;
+        f[i] = f[i] + om * ((A + B) - f[i]);
+        f[i + 1] = f[i + 1] + om * ((A - B) - f[i + 1]);
+    });
+}
+
+// Eq. (4) neighbour sum: acc[c][a] = sum_{i=1..18} W_i pn[c][i-1] c_ia with
+// pn = Psi^c(x + c_i) - Psi^c(rho_ref) (the constant drops out because
+// sum_i W_i c_i = 0); faces and edges summed separately as opposite-pair
+// differences, then weighted
+template <typename T>
+__device__ __forceinline__ void psi_force_sum(const DevParams &P, const T (&pn)[2][Q - 1], T (&acc)[2][3]) {
+    const T wf = (T)P.w_face, we = (T)P.w_edge;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T sf[3] = {pn[c][0] - pn[c][1], pn[c][2] - pn[c][3], pn[c][4] - pn[c][5]};
+        T se[3] = {0, 0, 0};
+        Unroll<6>::run([&](auto kc) {
+            constexpr int i = 7 + 2 * decltype(kc)::value;  // edge pair (i, i + 1)
+            const T d = pn[c][i - 1] - pn[c][i];
+            if (cx(i)) se[0] += cx(i) > 0 ? d : -d;
+            if (cy(i)) se[1] += cy(i) > 0 ? d : -d;
+            if (cz(i)) se[2] += cz(i) > 0 ? d : -d;
+        });
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[c][a] = wf * sf[a] + we * se[a];
     }
 }
 
@@ -423,44 +544,28 @@ struct NbrOffsets {
 };
 
 // f_i(x) = slot (i, x - c_i) for both components
-template <typename T>
-__device__ __forceinline__ void pull_load(const T *__restrict__ fin, unsigned n, const NbrOffsets &o, T (&f)[2][Q]) {
+template <typename S, typename T = Cmp<S>>
+__device__ __forceinline__ void pull_load(const S *__restrict__ fin, unsigned n, const NbrOffsets &o, T (&f)[2][Q]) {
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const unsigned src = i == 0 ? n : (unsigned)((int)n + o.template off<opp(i)>());
-        const Pair<T> v = load_pair(fin, pidx(0, i, src));
+        const Pair<T> v = load_pop(fin, pidx(0, i, src));
         f[0][i] = v.x;
         f[1][i] = v.y;
     });
 }
 
-// Tuning macros of the sweep kernels (compile-time):
-//   LBM_COLLIDE_WAVES  minimum wavefronts per SIMD the collide sweep is
-//                      register-limited to (0: compiler's choice)
-//   LBM_NT_STORE       1: populations are written with non-temporal stores
+// Tuning macro of the collide sweep (compile-time): LBM_COLLIDE_WAVES is the
+// minimum number of wavefronts per SIMD its registers are limited to (0: the
+// compiler's choice)
 #ifndef LBM_COLLIDE_WAVES
 #define LBM_COLLIDE_WAVES 0
-#endif
-#ifndef LBM_NT_STORE
-#define LBM_NT_STORE 0
 #endif
 #if LBM_COLLIDE_WAVES > 0
 #define LBM_COLLIDE_ATTR __attribute__((amdgpu_waves_per_eu(LBM_COLLIDE_WAVES)))
 #else
 #define LBM_COLLIDE_ATTR
 #endif
-
-template <typename T>
-__device__ __forceinline__ void store_pop_pair(T *p, T v0, T v1) {
-    Pair<T> v;
-    v.x = v0;
-    v.y = v1;
-#if LBM_NT_STORE
-    __builtin_nontemporal_store(v, reinterpret_cast<Pair<T> *>(p));
-#else
-    *reinterpret_cast<Pair<T> *>(p) = v;
-#endif
-}
 
 // An empty asm statement that takes the values as inputs: loads issued
 // before it complete before it, and the compiler cannot sink them into the
@@ -472,14 +577,14 @@ __device__ __forceinline__ void hold_loads(const T (&v)[K]) {
 }
 
 // sum_i f_i(x) of both components (pull form)
-template <typename T>
-__device__ __forceinline__ void pull_sum(const T *__restrict__ fin, unsigned n, const NbrOffsets &o, T &s0, T &s1) {
+template <typename S, typename T = Cmp<S>>
+__device__ __forceinline__ void pull_sum(const S *__restrict__ fin, unsigned n, const NbrOffsets &o, T &s0, T &s1) {
     s0 = 0;
     s1 = 0;
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const unsigned src = i == 0 ? n : (unsigned)((int)n + o.template off<opp(i)>());
-        const Pair<T> v = load_pair(fin, pidx(0, i, src));
+        const Pair<T> v = load_pop(fin, pidx(0, i, src));
         s0 += v.x;
         s1 += v.y;
     });
@@ -495,10 +600,10 @@ __device__ __forceinline__ void pull_sum(const T *__restrict__ fin, unsigned n, 
 // (spheres: the link force sum; walls: the wall-plane kernel), which need
 // the density of x and therefore find it in rho_out at boundary sites.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename S, typename M, typename T = Cmp<S>>
 __device__ __forceinline__ void collide_and_store(const DevParams &P, T (&f)[2][Q], const T (&acc)[2][3],
                                                   uint32_t inf, unsigned n, const NbrOffsets &o,
-                                                  T *__restrict__ fout, T *__restrict__ rho_out, double &mass0,
+                                                  S *__restrict__ fout, T *__restrict__ rho_out, double &mass0,
                                                   double &mass1) {
     const T rho0 = (T)P.rho0, irho0 = (T)P.inv_rho0, g = (T)P.g;
     T dr[2], r[2], j[2][3], F[2][3];
@@ -513,20 +618,16 @@ __device__ __forceinline__ void collide_and_store(const DevParams &P, T (&f)[2][
         for (int a = 0; a < 3; ++a) F[c][a] = -ps * g * acc[1 - c][a] + r[c] * (T)P.body[a];
     }
     T ueq[2][3];
-    eq_velocity(P, r, j, F, ueq);
+    eq_velocity<T, M::velocity_mode>(P, r, j, F, ueq);
     if (rho_out && (inf & 0x7fffeu))  // density of a boundary site, read back by the link kernels
         store_pair(rho_out, sidx(0, n), dr[0], dr[1]);
-    const int order = P.eq_order;
-    const T om0 = (T)P.inv_tau[0], om1 = (T)P.inv_tau[1];
-    const T u20 = ueq[0][0] * ueq[0][0] + ueq[0][1] * ueq[0][1] + ueq[0][2] * ueq[0][2];
-    const T u21 = ueq[1][0] * ueq[1][0] + ueq[1][1] * ueq[1][1] + ueq[1][2] * ueq[1][2];
+    relax<T, M::eq_order>(f[0], dr[0], r[0], ueq[0][0], ueq[0][1], ueq[0][2], (T)P.inv_tau[0]);
+    relax<T, M::eq_order>(f[1], dr[1], r[1], ueq[1][0], ueq[1][1], ueq[1][2], (T)P.inv_tau[1]);
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const T fs0 = f[0][i] - (f[0][i] - feq_dev_dir<T>(i, dr[0], r[0], ueq[0][0], ueq[0][1], ueq[0][2], u20, order)) * om0;
-        const T fs1 = f[1][i] - (f[1][i] - feq_dev_dir<T>(i, dr[1], r[1], ueq[1][0], ueq[1][1], ueq[1][2], u21, order)) * om1;
-        store_pop_pair(fout + pidx(0, i, n), fs0, fs1);
+        store_pop(fout, pidx(0, i, n), f[0][i], f[1][i]);
         if (i != 0 && (inf & (1u << i)))
-            store_pair(fout, pidx(0, opp(i), (unsigned)((int)n + o.template off<i>())), fs0, fs1);
+            store_pop(fout, pidx(0, opp(i), (unsigned)((int)n + o.template off<i>())), f[0][i], f[1][i]);
     });
 }
 

@@ -38,26 +38,29 @@ __global__ void k_init_owner(DevParams P, int32_t *owner) {
 
 // initial densities rho^c = rho_init^c + noise (2U - 1), f = zeta_i rho^c,
 // stored as f - zeta_i rho_ref^c in the slots (i, x - c_i) the site reads
-template <typename T>
+template <typename S>
 __global__ void k_init_fluid(DevParams P, uint64_t seed, double noise, const int32_t *__restrict__ owner,
-                             T *__restrict__ f) {
+                             S *__restrict__ f) {
 #pragma clang fp contract(off)
+    using T = Cmp<S>;
     unsigned n;
     int x, y, z;
     if (!dense_site(P, n, x, y, z)) return;
     if (owner[n] != OWN_FLUID) return;
     const NbrOffsets o(P, x, y, z);
+    double r[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const double U = (double)(splitmix64_at(seed, 2ull * (unsigned long long)n + c) >> 11) *
                          (1.0 / 9007199254740992.0);
-        const double r = P.rho_init[c] + noise * (2.0 * U - 1.0);
-        Unroll<Q>::run([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const unsigned dst = i == 0 ? n : (unsigned)((int)n + o.template off<opp(i)>());
-            f[pidx(c, i, dst)] = (T)(zeta(i) * r - zeta(i) * P.rho_ref[c]);
-        });
+        r[c] = P.rho_init[c] + noise * (2.0 * U - 1.0);
     }
+    Unroll<Q>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const unsigned dst = i == 0 ? n : (unsigned)((int)n + o.template off<opp(i)>());
+        store_pop(f, pidx(0, i, dst), (T)(zeta(i) * r[0] - zeta(i) * P.rho_ref[0]),
+                  (T)(zeta(i) * r[1] - zeta(i) * P.rho_ref[1]));
+    });
 }
 
 __global__ void k_info_dense(DevParams P, const int32_t *__restrict__ owner, uint32_t *__restrict__ info) {
@@ -84,8 +87,8 @@ __global__ void k_fill_int(int32_t *p, long long n, int32_t v) {
 // on fluid sites (rho = 0 elsewhere), optionally with per-block FP64 partial
 // sums of the fluid mass
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const T *__restrict__ f,
+template <typename S, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restrict__ f,
                                                    const uint32_t *__restrict__ info, T *__restrict__ rho,
                                                    T *__restrict__ psi, double *__restrict__ partial) {
     __shared__ double lds[2 * (BLOCK / 64)];
@@ -211,25 +214,6 @@ __device__ __forceinline__ void load_psi_neighbours(const T *__restrict__ psi, u
     });
 }
 
-// acc[c][a] = sum_{i=1..18} W_i (Psi^c(x + c_i) - Psi^c(rho_ref)) c_ia
-template <typename T>
-__device__ __forceinline__ void psi_force_sum(const DevParams &P, const T (&pn)[2][Q - 1], T (&acc)[2][3]) {
-    const T wf = (T)P.w_face, we = (T)P.w_edge;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[c][0] = acc[c][1] = acc[c][2] = 0;
-    Unroll<Q - 1>::run([&](auto ic) {
-        constexpr int i = decltype(ic)::value + 1;
-        const T w = norm2(i) == 1 ? wf : we;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const T wp = w * pn[c][i - 1];
-            if (cx(i)) acc[c][0] += cx(i) > 0 ? wp : -wp;
-            if (cy(i)) acc[c][1] += cy(i) > 0 ? wp : -wp;
-            if (cz(i)) acc[c][2] += cz(i) > 0 ? wp : -wp;
-        }
-    });
-}
-
 // ---------------------------------------------------------------------------
 // collide and stream (two-pass variant, second sweep): populations of the
 // site, Psi of the neighbours from the Psi array.  On shell sites it stores
@@ -237,9 +221,9 @@ __device__ __forceinline__ void psi_force_sum(const DevParams &P, const T (&pn)[
 // before its classification is known (all addresses lie in the box), so a
 // wavefront has its whole working set in flight at once.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevParams P, const T *__restrict__ fin,
-                                                                          T *__restrict__ fout, const T *__restrict__ rho,
+template <typename S, typename M, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevParams P, const S *__restrict__ fin,
+                                                                          S *__restrict__ fout, const T *__restrict__ rho,
                                                                           const T *__restrict__ psi,
                                                                           const uint32_t *__restrict__ info,
                                                                           T *__restrict__ fsc) {
@@ -269,7 +253,7 @@ __global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevPa
         return;
     }
     double m0 = 0.0, m1 = 0.0;
-    collide_and_store(P, f, acc, inf, n, o, fout, (T *)nullptr, m0, m1);
+    collide_and_store<S, M>(P, f, acc, inf, n, o, fout, (T *)nullptr, m0, m1);
 }
 
 // ---------------------------------------------------------------------------
@@ -279,8 +263,8 @@ __global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevPa
 // (c_i . u_wall).  Only the planes next to the walls hold such links; the
 // grid covers both (one thread per site of the two planes).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_wall_links(DevParams P, T *__restrict__ fout, const T *__restrict__ rho,
+template <typename S, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_wall_links(DevParams P, S *__restrict__ fout, const T *__restrict__ rho,
                                                       const uint32_t *__restrict__ info,
                                                       const int32_t *__restrict__ owner) {
     const int ax = P.wall_axis;
@@ -311,13 +295,10 @@ __global__ __launch_bounds__(BLOCK) void k_wall_links(DevParams P, T *__restrict
         if (cy(i)) cub += cy(i) * (lo ? P.wall_vel[0][1] : P.wall_vel[1][1]);
         if (cz(i)) cub += cz(i) * (lo ? P.wall_vel[0][2] : P.wall_vel[1][2]);
         if (cub == 0.0) continue;
-        const double wz = 6.0 * zeta(i) * cub;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const T rc = rho[sidx(c, n)] + (T)P.rho_ref[c];
-            T *p = fout + pidx(c, opp(i), m);
-            *p = *p - (T)wz * rc;
-        }
+        const T wz = (T)(6.0 * zeta(i) * cub);
+        const Pair<T> rr = load_pair(rho, sidx(0, n));
+        const Pair<T> ff = load_pop(fout, pidx(0, opp(i), m));
+        store_pop(fout, pidx(0, opp(i), m), ff.x - wz * (rr.x + (T)P.rho_ref[0]), ff.y - wz * (rr.y + (T)P.rho_ref[1]));
     }
 }
 
@@ -325,8 +306,8 @@ __global__ __launch_bounds__(BLOCK) void k_wall_links(DevParams P, T *__restrict
 // fields of the current state (double): rho [2][N], j [2][N][3], F [2][N][3],
 // u [N][3]; expects the density and Psi arrays filled (with virtual fluid)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const T *__restrict__ fin, const T *__restrict__ rho,
+template <typename S, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const S *__restrict__ fin, const T *__restrict__ rho,
                                                   const T *__restrict__ psi, const uint32_t *__restrict__ info,
                                                   double *__restrict__ out) {
     unsigned n;
@@ -380,8 +361,8 @@ __global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const T *__restri
 }
 
 // per-block FP64 sums of mass [2] and momentum [3] over fluid sites
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_sums(DevParams P, const T *__restrict__ fin,
+template <typename S, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_sums(DevParams P, const S *__restrict__ fin,
                                                 const uint32_t *__restrict__ info, double *__restrict__ partial) {
     __shared__ double lds[5 * (BLOCK / 64)];
     double v[5] = {0, 0, 0, 0, 0};
@@ -417,23 +398,13 @@ __global__ __launch_bounds__(BLOCK) void k_sums(DevParams P, const T *__restrict
 static inline unsigned nblocks(long long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 static inline unsigned dense_blocks(const lb_handle *h) { return nblocks(h->N); }
 
-#define LB_DISPATCH(h, KERNEL_CALL_FLOAT, KERNEL_CALL_DOUBLE) \
-    do {                                                     \
-        if ((h)->prm.precision == LB_FP64) {                 \
-            KERNEL_CALL_DOUBLE;                              \
-        } else {                                             \
-            KERNEL_CALL_FLOAT;                               \
-        }                                                    \
-    } while (0)
-
 void launch_init_fluid(lb_handle *h) {
     const unsigned nb = dense_blocks(h);
     k_init_owner<<<nb, BLOCK, 0, h->stream>>>(h->dp, h->owner);
-    LB_DISPATCH(h,
-                (k_init_fluid<float><<<nb, BLOCK, 0, h->stream>>>(h->dp, h->prm.seed, h->prm.noise_amp, h->owner,
-                                                                   (float *)h->f[h->cur])),
-                (k_init_fluid<double><<<nb, BLOCK, 0, h->stream>>>(h->dp, h->prm.seed, h->prm.noise_amp, h->owner,
-                                                                    (double *)h->f[h->cur])));
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        k_init_fluid<S><<<nb, BLOCK, 0, h->stream>>>(h->dp, h->prm.seed, h->prm.noise_amp, h->owner, (S *)h->f[h->cur]);
+    });
     k_info_dense<<<nb, BLOCK, 0, h->stream>>>(h->dp, h->owner, h->info);
     LB_HIP_CHECK(hipGetLastError());
 }
@@ -457,11 +428,11 @@ void launch_fill_int(lb_handle *h, int32_t *p, long long n, int32_t v) {
 void launch_density(lb_handle *h, const void *f, bool partial_sums) {
     const unsigned nb = dense_blocks(h);
     double *part = partial_sums ? h->partial : nullptr;
-    LB_DISPATCH(h,
-                (k_density<float><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const float *)f, h->info, (float *)h->rho,
-                                                                (float *)h->psi, part)),
-                (k_density<double><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const double *)f, h->info, (double *)h->rho,
-                                                                 (double *)h->psi, part)));
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        using T = Cmp<S>;
+        k_density<S><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho, (T *)h->psi, part);
+    });
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -474,23 +445,24 @@ void launch_finalize_mass_n(lb_handle *h, int nb) {
 
 void launch_shell_fill(lb_handle *h) {
     if (h->np == 0) return;
-    LB_DISPATCH(h,
-                (k_shell_fill<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->info, (float *)h->rho,
-                                                                      (float *)h->psi)),
-                (k_shell_fill<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->info, (double *)h->rho,
-                                                                       (double *)h->psi)));
+    if (h->prm.precision == LB_FP64)
+        k_shell_fill<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->info, (double *)h->rho,
+                                                             (double *)h->psi);
+    else
+        k_shell_fill<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->info, (float *)h->rho, (float *)h->psi);
     LB_HIP_CHECK(hipGetLastError());
 }
 
 void launch_collide_stream(lb_handle *h, const void *fin, void *fout) {
     const unsigned nb = dense_blocks(h);
-    LB_DISPATCH(h,
-                (k_collide_stream<float><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const float *)fin, (float *)fout,
-                                                                       (const float *)h->rho, (const float *)h->psi,
-                                                                       h->info, (float *)h->fsc)),
-                (k_collide_stream<double><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const double *)fin, (double *)fout,
-                                                                        (const double *)h->rho, (const double *)h->psi,
-                                                                        h->info, (double *)h->fsc)));
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        using T = Cmp<S>;
+        with_model(h->prm, [&](auto m) {
+            k_collide_stream<S, decltype(m)><<<nb, BLOCK, 0, h->stream>>>(
+                h->dp, (const S *)fin, (S *)fout, (const T *)h->rho, (const T *)h->psi, h->info, (T *)h->fsc);
+        });
+    });
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -500,28 +472,31 @@ void launch_wall_links(lb_handle *h, void *fout) {
     const long long plane = ax == 0 ? (long long)h->prm.ny * h->prm.nz
                                     : (ax == 1 ? (long long)h->prm.nx * h->prm.nz : (long long)h->prm.nx * h->prm.ny);
     const unsigned nb = nblocks(2 * plane);
-    LB_DISPATCH(h,
-                (k_wall_links<float><<<nb, BLOCK, 0, h->stream>>>(h->dp, (float *)fout, (const float *)h->rho, h->info,
-                                                                   h->owner)),
-                (k_wall_links<double><<<nb, BLOCK, 0, h->stream>>>(h->dp, (double *)fout, (const double *)h->rho,
-                                                                    h->info, h->owner)));
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        using T = Cmp<S>;
+        k_wall_links<S><<<nb, BLOCK, 0, h->stream>>>(h->dp, (S *)fout, (const T *)h->rho, h->info, h->owner);
+    });
     LB_HIP_CHECK(hipGetLastError());
 }
 
 void launch_fields(lb_handle *h, const void *f, double *out) {
     const unsigned nb = dense_blocks(h);
-    LB_DISPATCH(h,
-                (k_fields<float><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const float *)f, (const float *)h->rho,
-                                                               (const float *)h->psi, h->info, out)),
-                (k_fields<double><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const double *)f, (const double *)h->rho,
-                                                                (const double *)h->psi, h->info, out)));
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        using T = Cmp<S>;
+        k_fields<S><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, (const T *)h->rho, (const T *)h->psi, h->info,
+                                                  out);
+    });
     LB_HIP_CHECK(hipGetLastError());
 }
 
 void launch_sums(lb_handle *h, const void *f) {
     const unsigned nb = dense_blocks(h);
-    LB_DISPATCH(h, (k_sums<float><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const float *)f, h->info, h->partial)),
-                (k_sums<double><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const double *)f, h->info, h->partial)));
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        k_sums<S><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, h->partial);
+    });
     LB_HIP_CHECK(hipGetLastError());
 }
 

@@ -47,7 +47,7 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
     return (b % 8u) * (nb / 8u) + b / 8u;
 }
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, typename M>
 __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles D, const T *__restrict__ fin,
                                                        T *__restrict__ fout, T *__restrict__ rho,
                                                        const uint32_t *__restrict__ info,
@@ -68,7 +68,6 @@ __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles
     const T e0 = (T)P.psi_e[0], e1 = (T)P.psi_e[1];
     // Psi - Psi(rho_ref) of a site without fluid (Psi = 0)
     const T psolid0 = psi_dev(-ref0, e0, irho0), psolid1 = psi_dev(-ref1, e1, irho0);
-    const T wf = (T)P.w_face, we = (T)P.w_edge;
     double mass0 = 0.0, mass1 = 0.0;
 
     // own site of this thread in stage C
@@ -154,21 +153,16 @@ __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles
             const uint32_t cls = site_class(inf);
             const long long n = ((long long)zc * ny + ys) * nx + xs;
             if (cls == CLS_FLUID || cls == CLS_SHELL) {
-                // Eq. (4): acc[c] = sum_i W_i (Psi^c(x + c_i) - Psi^c(rho_ref)) c_i
-                T acc[2][3] = {{0, 0, 0}, {0, 0, 0}};
+                // Eq. (4) from the Psi ring
+                T pn[2][Q - 1], acc[2][3];
 #pragma unroll
                 for (int i = 1; i < Q; ++i) {
                     const int sl = cz(i) < 0 ? sl_m : (cz(i) > 0 ? sl_p : sl_0);
                     const int bn = bs + cy(i) * S::BX + cx(i);
-                    const T w = norm2(i) == 1 ? wf : we;
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const T wp = w * sm.psi[sl][c][bn];
-                        if (cx(i)) acc[c][0] += cx(i) > 0 ? wp : -wp;
-                        if (cy(i)) acc[c][1] += cy(i) > 0 ? wp : -wp;
-                        if (cz(i)) acc[c][2] += cz(i) > 0 ? wp : -wp;
-                    }
+                    pn[0][i - 1] = sm.psi[sl][0][bn];
+                    pn[1][i - 1] = sm.psi[sl][1][bn];
                 }
+                psi_force_sum(P, pn, acc);
                 if (cls == CLS_SHELL) {
                     const T ps0 = psi_of(sm.drho[sl_0][0][as] + ref0, rho0, irho0);
                     const T ps1 = psi_of(sm.drho[sl_0][1][as] + ref1, rho0, irho0);
@@ -178,7 +172,7 @@ __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles
                     const NbrOffsets o(P, xs, ys, zc);
                     T f[2][Q];
                     pull_load(fin, (unsigned)n, o, f);
-                    collide_and_store(P, f, acc, inf, (unsigned)n, o, fout, rho, mass0, mass1);
+                    collide_and_store<T, M>(P, f, acc, inf, (unsigned)n, o, fout, rho, mass0, mass1);
                 }
             }
         }
@@ -211,8 +205,11 @@ static void launch_fused_t(lb_handle *h, const void *fin, void *fout) {
     const int TZ = h->fused_tz;
     const int nseg = (h->prm.nz + TZ - 1) / TZ;
     const unsigned nb = (unsigned)(ntx * nty * nseg);
-    k_fused_step<T, TX, TY><<<nb, TX * TY, 0, h->stream>>>(h->dp, h->dpart, (const T *)fin, (T *)fout, (T *)h->rho,
-                                                           h->info, h->owner, (T *)h->fsc, h->partial, TZ, ntx, nty);
+    with_model(h->prm, [&](auto m) {
+        k_fused_step<T, TX, TY, decltype(m)><<<nb, TX * TY, 0, h->stream>>>(
+            h->dp, h->dpart, (const T *)fin, (T *)fout, (T *)h->rho, h->info, h->owner, (T *)h->fsc, h->partial, TZ,
+            ntx, nty);
+    });
     LB_HIP_CHECK(hipGetLastError());
     h->n_fused_blocks = (int)nb;
 }
@@ -225,14 +222,11 @@ void launch_fused(lb_handle *h, const void *fin, void *fout) {
     const int tx = h->fused_tx, ty = h->fused_ty;
     if (h->prm.precision == LB_FP64) {
         if (tx == 32 && ty == 4) launch_fused_t<double, 32, 4>(h, fin, fout);
-        else if (tx == 64 && ty == 4) launch_fused_t<double, 64, 4>(h, fin, fout);
         else launch_fused_t<double, 16, 8>(h, fin, fout);
     } else {
         if (tx == 64 && ty == 4) launch_fused_t<float, 64, 4>(h, fin, fout);
-        else if (tx == 64 && ty == 8) launch_fused_t<float, 64, 8>(h, fin, fout);
         else if (tx == 32 && ty == 8) launch_fused_t<float, 32, 8>(h, fin, fout);
         else if (tx == 32 && ty == 4) launch_fused_t<float, 32, 4>(h, fin, fout);
-        else if (tx == 128 && ty == 2) launch_fused_t<float, 128, 2>(h, fin, fout);
         else launch_fused_t<float, 16, 8>(h, fin, fout);
     }
 }

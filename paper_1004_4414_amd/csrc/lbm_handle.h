@@ -18,6 +18,7 @@ struct lb_handle {
     std::string err;
     long long N = 0;
     size_t tsize = 4;  // bytes per stored population
+    size_t csize = 4;  // bytes of the arithmetic type (densities, Psi, forces)
 
     // fluid
     void *f[2] = {nullptr, nullptr};
@@ -65,6 +66,32 @@ void launch_init_fluid(lb_handle *h);
 void launch_density(lb_handle *h, const void *f, bool partial_sums);
 void launch_finalize_mass(lb_handle *h);
 void launch_shell_fill(lb_handle *h);
+// calls fn(tag) with tag::type the population storage type of the precision
+template <typename S>
+struct StorageTag {
+    using type = S;
+};
+template <typename Fn>
+void with_storage(const lb_params &p, Fn &&fn) {
+    switch (p.precision) {
+    case LB_FP64: fn(StorageTag<double>{}); break;
+    case LB_FP16: fn(StorageTag<__half>{}); break;
+    case LB_BF16: fn(StorageTag<__hip_bfloat16>{}); break;
+    default: fn(StorageTag<float>{}); break;
+    }
+}
+
+// calls fn(Model<velocity_mode, eq_order>{}) for the handle's parameters
+template <typename Fn>
+void with_model(const lb_params &p, Fn &&fn) {
+    if (p.velocity_mode == 1) {
+        if (p.eq_order == 3) fn(Model<1, 3>{});
+        else fn(Model<1, 2>{});
+    } else {
+        if (p.eq_order == 3) fn(Model<0, 3>{});
+        else fn(Model<0, 2>{});
+    }
+}
 void launch_collide_stream(lb_handle *h, const void *fin, void *fout);
 void launch_wall_links(lb_handle *h, void *fout);
 void launch_fields(lb_handle *h, const void *f, double *out);

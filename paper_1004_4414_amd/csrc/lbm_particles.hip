@@ -139,8 +139,8 @@ __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &
 // handled LINKS_PER_PASS per thread with all their loads issued together.
 constexpr int LINKS_PER_PASS = 4;
 
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, T *__restrict__ fout,
+template <typename S, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, S *__restrict__ fout,
                                                                 const T *__restrict__ rho, const T *__restrict__ fsc,
                                                                 const uint32_t *__restrict__ info) {
     __shared__ double lds[6 * (BLOCK / 64)];
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
 #pragma unroll
             for (int u = 0; u < LINKS_PER_PASS; ++u) {
                 const Pair<T> rr = load_pair(rho, sidx(0, ml[u]));
-                const Pair<T> ff = load_pair(fout, pidx(0, jl[u], sl[u]));
+                const Pair<T> ff = load_pop(fout, pidx(0, jl[u], sl[u]));
                 r0[u] = rr.x;
                 r1[u] = rr.y;
                 raw0[u] = ff.x;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
                 const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
                 const T wz = (T)(6.0 * zeta(i) * cub);
                 const T w0 = wz * (r0[u] + ref0), w1 = wz * (r1[u] + ref1);
-                store_pair(fout, pidx(0, j, ss), raw0[u] - w0, raw1[u] - w1);
+                store_pop(fout, pidx(0, j, ss), raw0[u] - w0, raw1[u] - w1);
                 const double sum = (2.0 * ((double)raw0[u] + zeta(i) * P.rho_ref[0]) - (double)w0) +
                                    (2.0 * ((double)raw1[u] + zeta(i) * P.rho_ref[1]) - (double)w1);
                 const double dp[3] = {cx(i) * sum, cy(i) * sum, cz(i) * sum};
@@ -428,8 +428,8 @@ __global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles 
 // neighbours that are fluid before and after the move, scaled by the mass
 // correction; the sphere loses the created momentum.  Both impulses are
 // applied in the next step's integration.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticles D, T *__restrict__ f,
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticles D, S *__restrict__ f,
                                                         const int32_t *__restrict__ owner,
                                                         const int32_t *__restrict__ stage, DevState *st) {
     __shared__ double lds[6 * (BLOCK / 64)];
@@ -451,14 +451,14 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
         // f_i(y) = slot (i, y - c_i); the reference part of the stored values
         // has no momentum.  Nothing reads those slots once y is solid.
         double mom[3] = {0, 0, 0};
-        for (int c = 0; c < 2; ++c)
-            for (int i = 0; i < Q; ++i) {
-                const long long src = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
-                const double di = (double)f[pidx(c, i, (unsigned)src)];
-                mom[0] += di * cx(i);
-                mom[1] += di * cy(i);
-                mom[2] += di * cz(i);
-            }
+        for (int i = 0; i < Q; ++i) {
+            const long long src = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
+            const auto d2 = load_pop(f, pidx(0, i, (unsigned)src));
+            const double di = (double)d2.x + (double)d2.y;
+            mom[0] += di * cx(i);
+            mom[1] += di * cy(i);
+            mom[2] += di * cz(i);
+        }
         const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
         for (int a = 0; a < 3; ++a) v[a] += mom[a];
         v[3] += r[1] * mom[2] - r[2] * mom[1];
@@ -483,15 +483,16 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
             const long long m = site_of(mx, my, mz, P);
             use = owner[m] == OWN_FLUID && stage[m] == STAGE_NONE;
             if (use) {
-                for (int c = 0; c < 2; ++c) {
-                    double r = 0.0;
-                    for (int q = 0; q < Q; ++q) {
-                        const long long src =
-                            site_of(wrapc(mx - cx(q), P.nx), wrapc(my - cy(q), P.ny), wrapc(mz - cz(q), P.nz), P);
-                        r += (double)f[pidx(c, q, (unsigned)src)];
-                    }
-                    rn[c] = r + P.rho_ref[c];
+                double r0 = 0.0, r1 = 0.0;
+                for (int q = 0; q < Q; ++q) {
+                    const long long src =
+                        site_of(wrapc(mx - cx(q), P.nx), wrapc(my - cy(q), P.ny), wrapc(mz - cz(q), P.nz), P);
+                    const auto d2 = load_pop(f, pidx(0, q, (unsigned)src));
+                    r0 += (double)d2.x;
+                    r1 += (double)d2.y;
                 }
+                rn[0] = r0 + P.rho_ref[0];
+                rn[1] = r1 + P.rho_ref[1];
             }
         }
         const int cnt = __popcll(__ballot(use));
@@ -511,12 +512,14 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
         const double us[3] = {U[0] + (W[1] * r[2] - W[2] * r[1]), U[1] + (W[2] * r[0] - W[0] * r[2]),
                               U[2] + (W[0] * r[1] - W[1] * r[0])};
         const double u2 = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
-        if (lane < 2 * Q) {
+        if (lane < Q) {
             // written where the site reads it: slot (i, y - c_i), read by nobody else
-            const int c = lane / Q, i = lane % Q;
+            const int i = lane;
             const long long dst = site_of(wrapc(x - cx(i), P.nx), wrapc(y - cy(i), P.ny), wrapc(z - cz(i), P.nz), P);
-            f[pidx(c, i, (unsigned)dst)] =
-                (T)(feq_dir<double>(i, rnew[c], us[0], us[1], us[2], u2, P.eq_order) - zeta(i) * P.rho_ref[c]);
+            using T = Cmp<S>;
+            store_pop(f, pidx(0, i, (unsigned)dst),
+                      (T)(feq_dir<double>(i, rnew[0], us[0], us[1], us[2], u2, P.eq_order) - zeta(i) * P.rho_ref[0]),
+                      (T)(feq_dir<double>(i, rnew[1], us[0], us[1], us[2], u2, P.eq_order) - zeta(i) * P.rho_ref[1]));
         }
         if (lane == 0) {
             if (cnt == 0) ++fallback;
@@ -642,12 +645,12 @@ __global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles
 // ---------------------------------------------------------------------------
 void launch_particle_fluid_force(lb_handle *h, void *fout) {
     if (!h->np) return;
-    if (h->prm.precision == LB_FP64)
-        k_particle_fluid_force<double><<<h->np, BLOCK, 0, h->stream>>>(
-            h->dp, h->dpart, (double *)fout, (const double *)h->rho, (const double *)h->fsc, h->info);
-    else
-        k_particle_fluid_force<float><<<h->np, BLOCK, 0, h->stream>>>(
-            h->dp, h->dpart, (float *)fout, (const float *)h->rho, (const float *)h->fsc, h->info);
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        using T = Cmp<S>;
+        k_particle_fluid_force<S><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (S *)fout, (const T *)h->rho,
+                                                                  (const T *)h->fsc, h->info);
+    });
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -677,12 +680,10 @@ void launch_map_events(lb_handle *h) {
 
 void launch_cover_refill(lb_handle *h, void *fout) {
     if (!h->np) return;
-    if (h->prm.precision == LB_FP64)
-        k_cover_refill<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (double *)fout, h->owner, h->stage,
-                                                               h->dstate);
-    else
-        k_cover_refill<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (float *)fout, h->owner, h->stage,
-                                                              h->dstate);
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        k_cover_refill<S><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (S *)fout, h->owner, h->stage, h->dstate);
+    });
     LB_HIP_CHECK(hipGetLastError());
 }
 

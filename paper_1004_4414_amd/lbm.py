@@ -16,9 +16,9 @@ LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 Q = 19
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EOVERLAP, LB_ESTATE, LB_EUNSTABLE, LB_ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
-LB_FP64, LB_FP32 = 0, 1
+LB_FP64, LB_FP32, LB_FP16, LB_BF16 = 0, 1, 2, 3
 LB_KERNEL_AUTO, LB_KERNEL_FUSED, LB_KERNEL_TWOPASS = 0, 1, 2
-PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32}
+PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32, "fp16": LB_FP16, "bf16": LB_BF16}
 KERNELS = {"auto": LB_KERNEL_AUTO, "fused": LB_KERNEL_FUSED, "twopass": LB_KERNEL_TWOPASS}
 
 #: C-ABI entry points declared in include/lbm.h
