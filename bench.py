@@ -58,10 +58,112 @@ def cpu_baseline(seconds_budget=20.0):
                        f"{steps} steps, single thread")
 
 
+def bench_ensemble(args):
+    """Batched ensemble: 64 boxes (edges 32-96, ratios 50:50-80:20, particle
+    fractions 0.05-0.25, radii 4-6, contact angles 60-120 degrees), FP32,
+    2000 steps each.  Every distinct box edge gets its sweep variant from the
+    autotuner; the boxes are then run (a) one job at a time with lb_step and
+    (b) all resident together, advanced by graph launches of a batch."""
+    import torch
+    from paper_1004_4414_amd import lbm, workloads as W
+    steps = args.steps or 2000
+    k = 20 if steps % 20 == 0 else 2
+    jobs = W.ensemble(64, seed=1004, steps=steps)
+    tuned = {}
+    t_tune = time.perf_counter()
+    for j in jobs:
+        e = j["params"]["nx"]
+        if e not in tuned:
+            tuned[e] = lbm.autotune(j["params"], j["particles"], "fp32", trial_steps=10)
+    t_tune = time.perf_counter() - t_tune
+    print(f"# autotuned {sorted((e, v[0], v[1]) for e, v in tuned.items())} in {t_tune:.1f} s", file=sys.stderr,
+          flush=True)
+
+    def make(j):
+        kern, tile, _ = tuned[j["params"]["nx"]]
+        lat = lbm.Lattice(j["params"], precision="fp32", kernel=kern, tile=tile)
+        parts = {kk: v.copy() for kk, v in j["particles"].items()}
+        parts["color"][:] = lbm.contact_angle_to_color(j["contact_angle"])
+        lat.add_particles(parts)
+        return lat
+
+    sites = sum(j["params"]["nx"] ** 3 for j in jobs)
+    # (a) one job at a time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in jobs:
+        lat = make(j)
+        lat.step(steps)
+        lat.synchronize()
+        lat.close()
+    t_alone = time.perf_counter() - t0
+    print(f"# one at a time: {t_alone:.2f} s", file=sys.stderr, flush=True)
+    # (b) resident batch, one graph launch per k steps of all 64 boxes
+    lats = [make(j) for j in jobs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = lbm.Batch(lats, steps_per_launch=k)
+    t_capture = time.perf_counter() - t0
+    batch.step(steps // k)
+    for lat in lats:
+        lat.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"# batched: {t_batch:.2f} s (capture {t_capture:.2f} s)", file=sys.stderr, flush=True)
+    batch.close()
+    jph = len(jobs) / t_batch * 3600.0
+    return {
+        "metric": "jobs/hour (batched ensemble of 64 boxes, 2000 steps each)",
+        "value": round(jph, 1), "unit": "jobs/hour", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(t_batch / steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ensemble64: 64 periodic boxes, edges {32,48,64,96}, ratios 50:50-80:20, "
+                               "fractions 0.05-0.25, radii 4-6, contact angles 60-120 deg, FP32",
+                   "sites": sites, "spheres": int(sum(len(j["particles"]["radius"]) for j in jobs)),
+                   "steps_per_launch": k, "autotuned": {str(e): [v[0], list(v[1])] for e, v in tuned.items()}},
+        "one_at_a_time": {"jobs_per_hour": round(len(jobs) / t_alone * 3600.0, 1), "seconds": round(t_alone, 3)},
+        "batched": {"seconds": round(t_batch, 3), "capture_seconds": round(t_capture, 3),
+                    "mlups": round(sites * steps / t_batch / 1e6, 1)},
+        "speedup": round(t_alone / t_batch, 3),
+    }
+
+
+def bench_serving(args):
+    """Serving trace, compressed: Poisson arrivals (20 jobs/min, arrival times
+    divided by 60) of boxes with edges 48-192, radii 4-8 at fractions
+    0.05-0.3, contact angles 45-135 degrees, 2000-20000 steps scaled by 1/20.
+    The continuous-batching server (BF16 storage, admission by footprint)
+    against one-at-a-time FP32 stepping."""
+    import torch
+    from paper_1004_4414_amd import serving as S, workloads as W
+    k = 10
+    trace = W.serving_trace(40, seed=1005, rate_per_min=20.0, time_scale=60.0, step_scale=0.05, step_quantum=k)
+    jobs = [S.Job(t["params"], t["particles"], t["steps"], arrival=t["arrival"], contact_angle=t["contact_angle"],
+                  name=f"job{i}") for i, t in enumerate(trace)]
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.6 * free)
+    srv = S.Server(budget, precision="bf16", steps_per_launch=k)
+    served = S.summary(srv.run(jobs))
+    print(f"# served: {served}, batch rebuilds {srv.batch_rebuilds}", file=sys.stderr, flush=True)
+    alone = S.summary(S.run_alone(jobs, precision="fp32"))
+    print(f"# one at a time (FP32): {alone}", file=sys.stderr, flush=True)
+    return {
+        "metric": "jobs/hour and p50/p99 time-to-result (served trace, continuous batching)",
+        "value": round(served["jobs_per_hour"], 1), "unit": "jobs/hour", "n_gpus": 1,
+        "steps": int(sum(j.steps for j in jobs)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving trace: 40 jobs, Poisson 20/min (times / 60), edges 48-192, radii 4-8, "
+                               "fractions 0.05-0.3, angles 45-135 deg, 2000-20000 steps x 1/20; BF16 storage",
+                   "budget_bytes": budget, "steps_per_launch": k},
+        "served_bf16": served, "one_at_a_time_fp32": alone,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 100 for bijel256, 2000 per box for ensemble64)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--workload", default="bijel256")
@@ -90,6 +192,15 @@ def main():
         del src, dst
         print(f"# calibration copy: 3 x {args.copy_mib} MiB read + {args.copy_mib} MiB written", file=sys.stderr,
               flush=True)
+
+    if args.workload == "ensemble64":
+        print(json.dumps(bench_ensemble(args)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
+        return
+    if args.steps is None:
+        args.steps = 100
 
     p, parts, _, precision = W.config(args.workload)
     if args.precision:

@@ -141,7 +141,8 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
 /* Release the handle and all its device memory (after the stream drains). */
 void lb_destroy(lb_handle *h);
 
-/* Message of the last failure on h ("" if none); valid until the next call. */
+/* Message of the last failure on h ("" if none), valid until the next call;
+ * with h == NULL, of the last failed lb_create on the calling thread. */
 const char *lb_last_error(const lb_handle *h);
 
 /* Add n spheres (Sec. III); allowed only before the first lb_step. The sites
@@ -217,6 +218,37 @@ int lb_kernel_timing(lb_handle *h, int32_t which, double *ms, int64_t *launches)
 /* Device bytes a handle with these parameters and n spheres of radius at most
  * max_radius would allocate, before any lb_get_fields call. */
 int lb_footprint_bytes(const lb_params *p, int32_t n_particles, double max_radius, size_t *bytes);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many lattices advanced by one graph launch.
+ *
+ * lb_batch_create captures steps_per_launch (even, >= 2) time steps of every
+ * member into one HIP graph, each member's kernels on a branch of its own so
+ * that the members run concurrently; lb_batch_step replays it nlaunches
+ * times on `stream` (ordered after the members' pending work, and the
+ * members' later calls are ordered after it).  The kernels are exactly those
+ * of lb_step, so every member's result is bitwise the same alone and in a
+ * batch.  Members must be fully set up (spheres added); while in a batch they
+ * refuse lb_add_particles and lb_set_state, must not record kernel timing,
+ * and must outlive the batch.  Errors: LB_EINVAL (bad arguments, a member
+ * already in a batch or timing), LB_EDEVICE (capture or launch failed; the
+ * message is in lb_batch_last_error).
+ * ------------------------------------------------------------------------- */
+typedef struct lb_batch lb_batch;
+int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, void *stream, lb_batch **out);
+int lb_batch_step(lb_batch *b, int32_t nlaunches);
+int32_t lb_batch_steps_per_launch(const lb_batch *b);
+const char *lb_batch_last_error(const lb_batch *b);
+void lb_batch_destroy(lb_batch *b);
+
+/* Autotuner: times trial_steps steps of every compiled sweep variant (the
+ * two-pass sweep and the fused sweep with each tile shape and z segment that
+ * fits the box and precision) on the given box and spheres, and writes the
+ * fastest choice into p->kernel and p->tile (and its step time in
+ * milliseconds into *best_ms_per_step if non-null).  Each candidate is a
+ * lattice of its own, created and destroyed in turn, so device memory for
+ * one more lattice must be free.  Returns LB_EDEVICE if no candidate ran. */
+int lb_autotune(lb_params *p, int32_t n, const lb_particle *parts, int32_t trial_steps, double *best_ms_per_step);
 
 #ifdef __cplusplus
 }

@@ -594,9 +594,20 @@ static void shan_chen_on_particles(orc_state *s) {
 /* integration of Eqs. (9), (10).                                              */
 /* Readings: K_Hertz is a parameter; the Hertz force is -dV/dr along the      */
 /* centre line with 2 r_par generalised to r_a + r_b.  The lubrication force  */
-/* is -6 pi nu rho_0 (r_a r_b/(r_a+r_b))^2 rhat [rhat.(u_1-u_2)] (1/h - 1/h_c) */
-/* for gaps h = |r| - r_a - r_b below h_c, with h clamped at h_min; nu is the  */
-/* mean of c_s^2 (tau^c - 1/2).                                                 */
+/* is -c rhat [rhat.(u_1-u_2)] with c = 6 pi nu rho_0 (r_a r_b/(r_a+r_b))^2    */
+/* (1/h - 1/h_c) for gaps h = |r| - r_a - r_b below h_c, with h clamped at     */
+/* h_min; nu is the mean of c_s^2 (tau^c - 1/2).                               */
+/* Reading (integration): the paper gives no scheme for this velocity-       */
+/* dependent force, and applied explicitly at the h_min clamp it is stiffer   */
+/* than one step can carry once a sphere has close neighbours at particle    */
+/* densities near the fluid's.  It is applied as pair impulses: with v* the  */
+/* velocities after every other force, w = n.(v*_p - v*_q) the approach      */
+/* speed and k_p the number of lubrication contacts of sphere p, the pair    */
+/* exchanges J = c w / (1 + c (k_p/m_p + k_q/m_q)) along n, equal and        */
+/* opposite.  For an isolated pair (k = 1) this is the backward-Euler        */
+/* solution of the pair's lubrication; sharing each sphere's mass among its  */
+/* contacts keeps the simultaneous impulses from overshooting.  A sphere     */
+/* with prescribed motion counts as infinitely heavy.                        */
 /* ------------------------------------------------------------------------- */
 static void move_particles(orc_state *s) {
     const double L[3] = {s->nx, s->ny, s->nz};
@@ -609,6 +620,10 @@ static void move_particles(orc_state *s) {
             s->Ftot[3 * p + a] = s->Ffl[3 * p + a] + s->P[3 * p + a];
             s->Ttot[3 * p + a] = s->Tfl[3 * p + a] + s->PT[3 * p + a];
         }
+    /* Hertz repulsion; lubrication contacts (p < q, unit vector n from p to q) */
+    int ncon = 0, capcon = 16;
+    int *cp = malloc(sizeof(int) * capcon), *cq = malloc(sizeof(int) * capcon);
+    double *cc = malloc(sizeof(double) * capcon), *cn = malloc(sizeof(double) * 3 * capcon);
     for (int p = 0; p < np; ++p)
         for (int q = p + 1; q < np; ++q) {
             double d[3], dist2 = 0.0;
@@ -631,20 +646,57 @@ static void move_particles(orc_state *s) {
             if (s->p.lub_hc > 0.0 && h < s->p.lub_hc) { /* h_c <= 0 switches it off */
                 double hh = h < s->p.lub_hmin ? s->p.lub_hmin : h;
                 double ared = s->rad[p] * s->rad[q] / rsum;
-                double coef = 6.0 * M_PI * nu * s->p.rho0 * ared * ared;
-                double vrel = 0.0;
-                for (int a = 0; a < 3; ++a) vrel += nh[a] * (s->U[3 * p + a] - s->U[3 * q + a]);
-                double fl = -coef * vrel * (1.0 / hh - 1.0 / s->p.lub_hc);
-                for (int a = 0; a < 3; ++a) {
-                    s->Ftot[3 * p + a] += fl * nh[a];
-                    s->Ftot[3 * q + a] -= fl * nh[a];
+                if (ncon == capcon) {
+                    capcon *= 2;
+                    cp = realloc(cp, sizeof(int) * capcon);
+                    cq = realloc(cq, sizeof(int) * capcon);
+                    cc = realloc(cc, sizeof(double) * capcon);
+                    cn = realloc(cn, sizeof(double) * 3 * capcon);
                 }
+                cp[ncon] = p;
+                cq[ncon] = q;
+                cc[ncon] = 6.0 * M_PI * nu * s->p.rho0 * ared * ared * (1.0 / hh - 1.0 / s->p.lub_hc);
+                for (int a = 0; a < 3; ++a) cn[3 * ncon + a] = nh[a];
+                ++ncon;
             }
         }
+    /* velocities after every other force */
+    double *vs = malloc(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
+    for (int p = 0; p < np; ++p)
+        for (int a = 0; a < 3; ++a)
+            vs[3 * p + a] = s->U[3 * p + a] + (s->prescribed[p] ? 0.0 : s->Ftot[3 * p + a] / s->mass[p]);
+    if (ncon > 0) {
+        int *kc = calloc((size_t)np, sizeof(int));
+        for (int k = 0; k < ncon; ++k) {
+            ++kc[cp[k]];
+            ++kc[cq[k]];
+        }
+        double *imp = calloc((size_t)3 * np, sizeof(double));
+        for (int k = 0; k < ncon; ++k) {
+            const int p = cp[k], q = cq[k];
+            const double *n = cn + 3 * k;
+            double w = 0.0;
+            for (int a = 0; a < 3; ++a) w += n[a] * (vs[3 * p + a] - vs[3 * q + a]);
+            const double inv = (s->prescribed[p] ? 0.0 : kc[p] / s->mass[p]) +
+                               (s->prescribed[q] ? 0.0 : kc[q] / s->mass[q]);
+            const double J = cc[k] * w / (1.0 + cc[k] * inv);
+            for (int a = 0; a < 3; ++a) {
+                imp[3 * p + a] -= J * n[a];
+                imp[3 * q + a] += J * n[a];
+            }
+        }
+        for (int p = 0; p < np; ++p)
+            for (int a = 0; a < 3; ++a) {
+                s->Ftot[3 * p + a] += imp[3 * p + a];
+                if (!s->prescribed[p]) vs[3 * p + a] += imp[3 * p + a] / s->mass[p];
+            }
+        free(kc);
+        free(imp);
+    }
     for (int p = 0; p < np; ++p) {
         for (int a = 0; a < 3; ++a) {
             if (!s->prescribed[p]) {
-                s->U[3 * p + a] += s->Ftot[3 * p + a] / s->mass[p];
+                s->U[3 * p + a] = vs[3 * p + a];
                 s->W[3 * p + a] += s->Ttot[3 * p + a] / s->inertia[p];
             }
             double r = s->R[3 * p + a] + s->U[3 * p + a];
@@ -655,6 +707,11 @@ static void move_particles(orc_state *s) {
             s->PT[3 * p + a] = 0.0;
         }
     }
+    free(vs);
+    free(cp);
+    free(cq);
+    free(cc);
+    free(cn);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -169,7 +169,7 @@ size_t fluid_bytes(const lb_params *p) {
 size_t particle_bytes(const lb_params *p, int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
     const size_t cells = (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
-    size_t b = (size_t)np * (34 * 8 + 16 * 4) + 4 * cells;
+    size_t b = (size_t)np * (37 * 8 + (17 + MAX_LUB_CONTACTS) * 4 + MAX_LUB_CONTACTS * 32) + 4 * cells;
     b += (size_t)np * sc * (4 + 2 * 4);  // virtual-fluid sites, covered and uncovered sites
     return b + 4096;
 }
@@ -253,6 +253,7 @@ int check_device_state(lb_handle *h) {
     if (st.unstable) return fail(h, LB_EUNSTABLE, "the fluid mass became non-finite");
     if (st.overflow & 8) return fail(h, LB_EUNSTABLE, "a sphere moved one lattice site or more in one step");
     if (st.overflow & 7) return fail(h, LB_ECAPACITY, "a per-sphere list overflowed");
+    if (st.overflow & 16) return fail(h, LB_ECAPACITY, "a sphere has more lubrication contacts than the list holds");
     return LB_OK;
 }
 
@@ -279,7 +280,7 @@ void choose_fused_tile(lb_handle *h) {
     h->fused_tz = std::max(1, std::min(tz, p.nz - 1));
 }
 
-void one_step(lb_handle *h) {
+void enqueue_step(lb_handle *h) {
     void *fin = h->f[h->cur], *fout = h->f[1 - h->cur];
     hipEvent_t t_step = h->timing_begin(2);
     if (h->kernel == LB_KERNEL_FUSED) {
@@ -326,6 +327,8 @@ void release_events(lb_handle *h) {
 }
 
 }  // namespace
+
+void lbm::one_step(lb_handle *h) { enqueue_step(h); }
 
 hipEvent_t lb_handle::timing_begin(int) {
     if (!timing) return nullptr;
@@ -378,12 +381,18 @@ void lb_default_params(lb_params *p) {
     p->kernel = LB_KERNEL_AUTO;
 }
 
+// message of the last failed lb_create on this thread (lb_last_error(NULL))
+thread_local std::string g_create_error = "null handle";
+
 int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_handle **out) {
     if (!p || !out) return LB_EINVAL;
     *out = nullptr;
     std::string msg;
     int rc = validate_params(p, msg);
-    if (rc != LB_OK) return rc;
+    if (rc != LB_OK) {
+        g_create_error = msg;
+        return rc;
+    }
     lb_handle *h = new (std::nothrow) lb_handle();
     if (!h) return LB_ENOMEM;
     h->prm = *p;
@@ -427,11 +436,11 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         launch_init_fluid(h);
         LB_HIP_CHECK(hipStreamSynchronize(h->stream));
     } catch (const lbm::HipFailure &e) {
-        std::string w = e.what;
+        g_create_error = e.what;
         lb_destroy(h);
-        (void)w;
         return LB_EDEVICE;
     } catch (const std::bad_alloc &) {
+        g_create_error = "device allocation failed";
         lb_destroy(h);
         return LB_ENOMEM;
     }
@@ -450,11 +459,12 @@ void lb_destroy(lb_handle *h) {
     delete h;
 }
 
-const char *lb_last_error(const lb_handle *h) { return h ? h->err.c_str() : "null handle"; }
+const char *lb_last_error(const lb_handle *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
 int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     if (!h) return LB_EINVAL;
     if (h->step > 0) return fail(h, LB_ESTATE, "spheres can only be added before the first step");
+    if (h->in_batch) return fail(h, LB_ESTATE, "the lattice belongs to a batch");
     if (n < 0 || (n > 0 && !parts)) return fail(h, LB_EINVAL, "bad particle array");
     if (n == 0) return LB_OK;
     if (h->prm.wall_axis >= 0) return fail(h, LB_EINVAL, "spheres and walls cannot be combined");
@@ -577,8 +587,18 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.cgz = (h->prm.nz + (1 << CELL_SHIFT) - 1) >> CELL_SHIFT;
     D.dirty = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)D.cgx * D.cgy * D.cgz);
     D.lbox = (int32_t *)dev_alloc(h, sizeof(int32_t) * 6 * (size_t)tot);
+    D.ncont = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+    D.cont = (int32_t *)dev_alloc(h, sizeof(int32_t) * MAX_LUB_CONTACTS * (size_t)tot);
+    D.vs = (double *)dev_alloc(h, sizeof(double) * 3 * (size_t)tot);
+    D.cont_c = (double *)dev_alloc(h, sizeof(double) * MAX_LUB_CONTACTS * (size_t)tot);
+    D.cont_n = (double *)dev_alloc(h, sizeof(double) * 3 * MAX_LUB_CONTACTS * (size_t)tot);
+    h->part_allocs.push_back(D.cont_c);
+    h->part_allocs.push_back(D.cont_n);
     h->part_allocs.push_back(D.dirty);
     h->part_allocs.push_back(D.lbox);
+    h->part_allocs.push_back(D.ncont);
+    h->part_allocs.push_back(D.cont);
+    h->part_allocs.push_back(D.vs);
     D.shell = (int32_t *)dev_alloc(h, sizeof(int32_t) * ssum);
     D.cov = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.unc = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
@@ -625,7 +645,7 @@ int lb_step(lb_handle *h, int32_t nsteps) {
     if (!h) return LB_EINVAL;
     if (nsteps < 0) return fail(h, LB_EINVAL, "nsteps must be >= 0");
     LB_API_BEGIN
-    for (int s = 0; s < nsteps; ++s) one_step(h);
+    for (int s = 0; s < nsteps; ++s) enqueue_step(h);
     return LB_OK;
     LB_API_END
 }
@@ -850,6 +870,7 @@ int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
 
 int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
     if (!h || !buf) return LB_EINVAL;
+    if (h->in_batch) return fail(h, LB_ESTATE, "the lattice belongs to a batch");
     const char *in = (const char *)buf;
     if (bytes < 8 + 24 + 8 + sizeof(DevState) || std::memcmp(in, kStateMagic, 8) != 0)
         return fail(h, LB_EINVAL, "not a checkpoint");

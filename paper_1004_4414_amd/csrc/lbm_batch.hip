@@ -1,0 +1,216 @@
+// Batched stepping of many lattices with one graph launch, and the tile /
+// kernel autotuner.
+//
+// A batch captures `k` time steps of every member into one HIP graph.  Each
+// member's kernels are captured from a stream of its own, forked from and
+// joined into the capture stream, so the graph holds independent branches
+// and the members' kernels overlap on the device; a replay advances every
+// member by k steps with one launch.  The kernels are the members' own
+// (identical launches to lb_step), so a member's result is bitwise the same
+// alone and in a batch.
+#include <chrono>
+#include <cstring>
+
+#include "lbm_handle.h"
+
+struct lb_batch {
+    std::vector<lb_handle *> m;
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> ev_member;
+    hipStream_t stream = nullptr;  // the caller's stream; replays are ordered on it
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev_done = nullptr;
+    int k = 2;
+    std::string err;
+};
+
+namespace {
+
+int bfail(lb_batch *b, int code, const std::string &msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+void release(lb_batch *b) {
+    for (lb_handle *h : b->m) h->in_batch = false;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipStream_t s : b->branch) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->ev_member) (void)hipEventDestroy(e);
+    if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->branch.clear();
+    b->ev_member.clear();
+    b->ev_done = nullptr;
+}
+
+#define BATCH_CHECK(expr) LB_HIP_CHECK(expr)
+
+}  // namespace
+
+extern "C" {
+
+int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, void *hip_stream, lb_batch **out) {
+    if (!out) return LB_EINVAL;
+    *out = nullptr;
+    if (n < 1 || !members) return LB_EINVAL;
+    if (steps_per_launch < 2 || steps_per_launch % 2) return LB_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!members[i] || members[i]->in_batch || members[i]->timing) return LB_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (members[j] == members[i]) return LB_EINVAL;
+    }
+    lb_batch *b = new lb_batch;
+    b->m.assign(members, members + n);
+    b->k = steps_per_launch;
+    b->stream = (hipStream_t)hip_stream;
+    std::vector<hipStream_t> saved(n);
+    hipStream_t cs = nullptr;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
+    try {
+        for (lb_handle *h : b->m) BATCH_CHECK(hipStreamSynchronize(h->stream));
+        b->branch.resize(n);
+        b->ev_member.resize(n);
+        for (int i = 0; i < n; ++i) {
+            BATCH_CHECK(hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking));
+            BATCH_CHECK(hipEventCreateWithFlags(&b->ev_member[i], hipEventDisableTiming));
+        }
+        BATCH_CHECK(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+        BATCH_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        BATCH_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        joins.resize(n, nullptr);
+        for (int i = 0; i < n; ++i) BATCH_CHECK(hipEventCreateWithFlags(&joins[i], hipEventDisableTiming));
+        BATCH_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        BATCH_CHECK(hipEventRecord(fork, cs));
+        for (int i = 0; i < n; ++i) {
+            lb_handle *h = b->m[i];
+            BATCH_CHECK(hipStreamWaitEvent(b->branch[i], fork, 0));
+            saved[i] = h->stream;
+            h->stream = b->branch[i];
+            for (int s = 0; s < b->k; ++s) lbm::one_step(h);
+            h->stream = saved[i];
+            h->step -= b->k;  // the capture only recorded the steps
+            BATCH_CHECK(hipEventRecord(joins[i], b->branch[i]));
+            BATCH_CHECK(hipStreamWaitEvent(cs, joins[i], 0));
+        }
+        BATCH_CHECK(hipStreamEndCapture(cs, &b->graph));
+        BATCH_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    } catch (const lbm::HipFailure &e) {
+        for (int i = 0; i < n; ++i)
+            if (saved[i]) b->m[i]->stream = saved[i];
+        if (cs) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+        }
+        release(b);
+        for (hipEvent_t e2 : joins)
+            if (e2) (void)hipEventDestroy(e2);
+        if (fork) (void)hipEventDestroy(fork);
+        if (cs) (void)hipStreamDestroy(cs);
+        delete b;
+        return LB_EDEVICE;
+    }
+    for (hipEvent_t e : joins) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(fork);
+    (void)hipStreamDestroy(cs);
+    for (lb_handle *h : b->m) h->in_batch = true;
+    *out = b;
+    return LB_OK;
+}
+
+int lb_batch_step(lb_batch *b, int32_t nlaunches) {
+    if (!b) return LB_EINVAL;
+    if (nlaunches < 0) return bfail(b, LB_EINVAL, "nlaunches must be >= 0");
+    if (nlaunches == 0) return LB_OK;
+    const int n = (int)b->m.size();
+    try {
+        // after whatever the members' own streams hold ...
+        for (int i = 0; i < n; ++i) {
+            BATCH_CHECK(hipEventRecord(b->ev_member[i], b->m[i]->stream));
+            BATCH_CHECK(hipStreamWaitEvent(b->stream, b->ev_member[i], 0));
+        }
+        for (int r = 0; r < nlaunches; ++r) BATCH_CHECK(hipGraphLaunch(b->exec, b->stream));
+        // ... and before whatever they enqueue next
+        BATCH_CHECK(hipEventRecord(b->ev_done, b->stream));
+        for (int i = 0; i < n; ++i) BATCH_CHECK(hipStreamWaitEvent(b->m[i]->stream, b->ev_done, 0));
+    } catch (const lbm::HipFailure &e) {
+        return bfail(b, LB_EDEVICE, e.what);
+    }
+    for (lb_handle *h : b->m) h->step += (long long)b->k * nlaunches;
+    return LB_OK;
+}
+
+int32_t lb_batch_steps_per_launch(const lb_batch *b) { return b ? b->k : 0; }
+
+const char *lb_batch_last_error(const lb_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+void lb_batch_destroy(lb_batch *b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    release(b);
+    delete b;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times `trial_steps` steps of every compiled kernel variant and
+// fused tile on the given box and spheres, and writes the fastest into
+// p->kernel and p->tile.  Each candidate is a lattice of its own, created and
+// destroyed in turn (the caller must leave room for one).
+// ---------------------------------------------------------------------------
+int lb_autotune(lb_params *p, int32_t n, const lb_particle *parts, int32_t trial_steps, double *best_ms_per_step) {
+    if (!p || trial_steps < 1 || (n > 0 && !parts)) return LB_EINVAL;
+    struct Cand {
+        int kernel, tx, ty, tz;
+    };
+    std::vector<Cand> cands;
+    cands.push_back({LB_KERNEL_TWOPASS, 0, 0, 0});
+    const bool wide = p->precision == LB_FP64 || p->precision == LB_FP32;
+    if (wide && lbm::fused_supported(*p)) {
+        const int shapes[4][2] = {{64, 4}, {32, 8}, {32, 4}, {16, 8}};
+        for (auto &sh : shapes) {
+            if (p->precision == LB_FP64 && !((sh[0] == 32 && sh[1] == 4) || (sh[0] == 16 && sh[1] == 8))) continue;
+            if (sh[0] > p->nx - 2 || sh[1] > p->ny - 2) continue;
+            for (int tz : {8, 16, 32, 64})
+                if (tz < p->nz) cands.push_back({LB_KERNEL_FUSED, sh[0], sh[1], tz});
+        }
+    }
+    double best = 1e300;
+    Cand pick = cands[0];
+    for (const Cand &c : cands) {
+        lb_params q = *p;
+        q.kernel = c.kernel;
+        q.tile[0] = c.tx;
+        q.tile[1] = c.ty;
+        q.tile[2] = c.tz;
+        lb_handle *h = nullptr;
+        if (lb_create(&q, nullptr, nullptr, &h) != LB_OK) continue;
+        int rc = n > 0 ? lb_add_particles(h, n, parts) : LB_OK;
+        if (rc == LB_OK) rc = lb_step(h, 2);
+        if (rc == LB_OK) rc = lb_synchronize(h);
+        if (rc == LB_OK) {
+            lb_enable_timing(h, 1);
+            rc = lb_step(h, trial_steps);
+            if (rc == LB_OK) rc = lb_synchronize(h);
+            double ms = 0.0;
+            int64_t cnt = 0;
+            if (rc == LB_OK && lb_kernel_timing(h, 2, &ms, &cnt) == LB_OK && cnt > 0 && ms / cnt < best) {
+                best = ms / cnt;
+                pick = c;
+            }
+        }
+        lb_destroy(h);
+    }
+    if (best == 1e300) return LB_EDEVICE;
+    p->kernel = pick.kernel;
+    p->tile[0] = pick.tx;
+    p->tile[1] = pick.ty;
+    p->tile[2] = pick.tz;
+    if (best_ms_per_step) *best_ms_per_step = best;
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -209,7 +209,7 @@ struct DevState {
     double Mstep[2];   // fluid mass at the start of the current step
     int32_t have_M0;
     int32_t unstable;
-    int32_t overflow;  // bit 1 shell list, bit 2 event lists, bit 3 a sphere moved >= 1 site
+    int32_t overflow;  // bit 1 shell list, bit 2 event lists, bit 3 a sphere moved >= 1 site, bit 4 contacts
     int32_t pad;
     unsigned long long covered_total, uncovered_total, refill_fallback;
 };
@@ -234,9 +234,14 @@ struct DevParticles {
     int32_t *changed;
     int32_t *dirty;
     int32_t *lbox;  // np x 6: box (lo, ext) of the last list build
+    // lubrication contacts (index order) and the velocities after every other force
+    int32_t *ncont, *cont;    // np, np x MAX_LUB_CONTACTS
+    double *cont_c, *cont_n;  // coefficient c and unit vector (lower to higher index) of each contact
+    double *vs;               // np x 3
     int cgx, cgy, cgz;
 };
 constexpr int CELL_SHIFT = 3;  // coarse cells of 8^3 sites
+constexpr int MAX_LUB_CONTACTS = 32;
 
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 

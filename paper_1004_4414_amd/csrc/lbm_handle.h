@@ -46,6 +46,7 @@ struct lb_handle {
     int fused_tx = 64, fused_ty = 4, fused_tz = 32;  // fused-kernel tile
     int n_fused_blocks = 0;
     long long step = 0;
+    bool in_batch = false;      // a batch graph holds this lattice's pointers
     std::vector<void *> owned;  // every device allocation, freed by lb_destroy
 
     // event timing (measurement only): per kind, pairs of recorded events
@@ -59,6 +60,7 @@ struct lb_handle {
 namespace lbm {
 
 void *dev_alloc(lb_handle *h, size_t bytes);
+void one_step(lb_handle *h);  // enqueue one time step on h->stream
 void dev_free(lb_handle *h, void *p);
 
 // fluid (lbm_fluid.hip)

@@ -277,66 +277,112 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
 
 // ---------------------------------------------------------------------------
 // pair forces, Eqs. (21) and (22), then the total force and torque: Hertz
-// repulsion (5/2) K (r_a + r_b - d)^(3/2) along the centre line, lubrication
-// -6 pi nu rho0 (r_a r_b/(r_a+r_b))^2 [n.(u_p - u_q)] (1/h - 1/h_c) n for gaps
-// h < h_c, h clamped at h_min.
+// repulsion (5/2) K (r_a + r_b - d)^(3/2) along the centre line, and the
+// lubrication contacts (gaps h < h_c) of each sphere, listed in index order.
+// The lubrication, c = 6 pi nu rho0 (r_a r_b/(r_a+r_b))^2 (1/h - 1/h_c) with h
+// clamped at h_min, acting on the approach speed, is stiff at the clamp; it is
+// applied as pair impulses in k_integrate: with v* the velocities after every
+// other force, w = n.(v*_p - v*_q) and k_p the number of contacts of sphere p,
+// the pair exchanges J = c w / (1 + c (k_p/m_p + k_q/m_q)) along n (the
+// backward-Euler solution for an isolated pair; sharing a sphere's mass among
+// its contacts keeps simultaneous impulses from overshooting).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_pair_forces(DevParams P, DevParticles D) {
+__global__ __launch_bounds__(BLOCK) void k_pair_forces(DevParams P, DevParticles D, DevState *st) {
     __shared__ double lds[3 * (BLOCK / 64)];
+    __shared__ int clds[8];
     const int p = blockIdx.x;
-    double Rp[3], Up[3];
+    double Rp[3];
     load3(D.R, p, Rp);
-    load3(D.U, p, Up);
     const double rp = D.rad[p];
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
     double F[3] = {0, 0, 0};
-    for (int q = threadIdx.x; q < P.np; q += BLOCK) {
-        if (q == p) continue;
-        double d[3], dist2 = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            d[a] = minimg(D.R[3 * q + a] - Rp[a], L[a]);
-            dist2 += d[a] * d[a];
+    int ncont = 0;
+    double nu = 0.0;  // mean kinematic viscosity of the two components
+    for (int c = 0; c < 2; ++c) nu += (1.0 / 3.0) * (P.tau[c] - 0.5);
+    nu /= 2.0;
+    for (int q0 = 0; q0 < P.np; q0 += BLOCK) {
+        const int q = q0 + threadIdx.x;
+        bool lub = false;
+        if (q < P.np && q != p) {
+            double d[3], dist2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = minimg(D.R[3 * q + a] - Rp[a], L[a]);
+                dist2 += d[a] * d[a];
+            }
+            const double rsum = rp + D.rad[q];
+            const double reach = rsum + (P.lub_hc > 0.0 ? P.lub_hc : 0.0);
+            if (dist2 < reach * reach) {
+                const double dist = sqrt(dist2);
+                if (dist > 0.0) {
+                    if (dist < rsum) {
+                        const double fh = 2.5 * P.k_hertz * pow(rsum - dist, 1.5);
+                        for (int a = 0; a < 3; ++a) F[a] -= fh * d[a] / dist;
+                    }
+                    lub = P.lub_hc > 0.0 && dist - rsum < P.lub_hc;
+                }
+            }
         }
-        const double rsum = rp + D.rad[q];
-        const double reach = rsum + (P.lub_hc > 0.0 ? P.lub_hc : 0.0);
-        if (dist2 >= reach * reach) continue;
-        const double dist = sqrt(dist2);
-        if (dist <= 0.0) continue;
-        const double nh[3] = {d[0] / dist, d[1] / dist, d[2] / dist};
-        if (dist < rsum) {
-            const double fh = 2.5 * P.k_hertz * pow(rsum - dist, 1.5);
-            for (int a = 0; a < 3; ++a) F[a] -= fh * nh[a];
-        }
-        const double h = dist - rsum;
-        if (P.lub_hc > 0.0 && h < P.lub_hc) {
+        const int slot = block_compact(lub, ncont, clds);
+        if (lub && slot < MAX_LUB_CONTACTS) {
+            // the pair's geometry as both ends compute it: from the lower index to the higher
+            const int lo = min(p, q), hi = max(p, q);
+            double d[3], dist2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = minimg(D.R[3 * hi + a] - D.R[3 * lo + a], L[a]);
+                dist2 += d[a] * d[a];
+            }
+            const double dist = sqrt(dist2);
+            const double rsum = D.rad[lo] + D.rad[hi];
+            const double h = dist - rsum;
             const double hh = h < P.lub_hmin ? P.lub_hmin : h;
-            const double ared = rp * D.rad[q] / rsum;
-            const double coef = 6.0 * M_PI * P.nu * P.rho0 * ared * ared;
-            double vrel = 0.0;
-            for (int a = 0; a < 3; ++a) vrel += nh[a] * (Up[a] - D.U[3 * q + a]);
-            const double fl = -coef * vrel * (1.0 / hh - 1.0 / P.lub_hc);
-            for (int a = 0; a < 3; ++a) F[a] += fl * nh[a];
+            const double ared = D.rad[lo] * D.rad[hi] / rsum;
+            const size_t e = (size_t)p * MAX_LUB_CONTACTS + slot;
+            D.cont[e] = q;
+            D.cont_c[e] = 6.0 * M_PI * nu * P.rho0 * ared * ared * (1.0 / hh - 1.0 / P.lub_hc);
+            for (int a = 0; a < 3; ++a) D.cont_n[3 * e + a] = d[a] / dist;
         }
     }
     block_sum<3>(F, lds);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+        D.ncont[p] = min(ncont, MAX_LUB_CONTACTS);
+        if (ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
             D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + F[a];
             D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
+            D.vs[3 * p + a] = D.U[3 * p + a] + (D.prescribed[p] ? 0.0 : D.Ftot[3 * p + a] / D.mass[p]);
         }
+    }
 }
 
-// leap-frog of Eqs. (9), (10): U(t+1/2) = U(t-1/2) + F/m, R(t+1) = R(t) + U,
-// Omega(t+1/2) = Omega(t-1/2) + D/J; the pending impulses are consumed
+// lubrication impulses, then the leap-frog of Eqs. (9), (10):
+// U(t+1/2) = v* + impulses / m, R(t+1) = R(t) + U, Omega(t+1/2) = Omega(t-1/2)
+// + D/J; the pending impulses are consumed
 __global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
     const int p = blockIdx.x * BLOCK + threadIdx.x;
     if (p >= P.np) return;
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    double imp[3] = {0, 0, 0};
+    const int kp = D.ncont[p];
+    const double inv_p = D.prescribed[p] ? 0.0 : kp / D.mass[p];
+    for (int k = 0; k < kp; ++k) {
+        const size_t e = (size_t)p * MAX_LUB_CONTACTS + k;
+        const int q = D.cont[e];
+        const int lo = min(p, q), hi = max(p, q);
+        const double c = D.cont_c[e];
+        const double n[3] = {D.cont_n[3 * e], D.cont_n[3 * e + 1], D.cont_n[3 * e + 2]};
+        double w = 0.0;
+        for (int a = 0; a < 3; ++a) w += n[a] * (D.vs[3 * lo + a] - D.vs[3 * hi + a]);
+        const double inv_q = D.prescribed[q] ? 0.0 : D.ncont[q] / D.mass[q];
+        const double J = c * w / (1.0 + c * (p == lo ? inv_p + inv_q : inv_q + inv_p));
+        const double sgn = p == lo ? -1.0 : 1.0;
+        for (int a = 0; a < 3; ++a) imp[a] += sgn * J * n[a];
+    }
     double step2 = 0.0;
     for (int a = 0; a < 3; ++a) {
         D.Rprev[3 * p + a] = D.R[3 * p + a];
+        D.Ftot[3 * p + a] += imp[a];
         if (!D.prescribed[p]) {
-            D.U[3 * p + a] += D.Ftot[3 * p + a] / D.mass[p];
+            D.U[3 * p + a] = D.vs[3 * p + a] + imp[a] / D.mass[p];
             D.W[3 * p + a] += D.Ttot[3 * p + a] / D.inertia[p];
         }
         double r = D.R[3 * p + a] + D.U[3 * p + a];
@@ -656,7 +702,7 @@ void launch_particle_fluid_force(lb_handle *h, void *fout) {
 
 void launch_pair_forces(lb_handle *h) {
     if (!h->np) return;
-    k_pair_forces<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart);
+    k_pair_forces<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->dstate);
     LB_HIP_CHECK(hipGetLastError());
 }
 

@@ -28,6 +28,8 @@ ENTRY_POINTS = [
     "lb_get_owner", "lb_num_particles", "lb_get_particles", "lb_set_particle_state", "lb_particle_counts",
     "lb_get_state", "lb_set_state", "lb_contact_angle_to_color", "lb_footprint_bytes",
     "lb_enable_timing", "lb_kernel_timing",
+    "lb_batch_create", "lb_batch_step", "lb_batch_steps_per_launch", "lb_batch_last_error", "lb_batch_destroy",
+    "lb_autotune",
 ]
 
 
@@ -90,6 +92,9 @@ def lib():
     """Load the HIP library; fails loudly when it has not been built."""
     global _lib
     if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so both share one runtime (and its view of the devices)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1004_4414_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)
@@ -118,6 +123,14 @@ def lib():
                                                   ctypes.POINTER(ctypes.c_size_t)]),
             "lb_enable_timing": (ctypes.c_int, [vp, ctypes.c_int32]),
             "lb_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64)]),
+            "lb_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32, vp,
+                                               ctypes.POINTER(vp)]),
+            "lb_batch_step": (ctypes.c_int, [vp, ctypes.c_int32]),
+            "lb_batch_steps_per_launch": (ctypes.c_int32, [vp]),
+            "lb_batch_last_error": (ctypes.c_char_p, [vp]),
+            "lb_batch_destroy": (None, [vp]),
+            "lb_autotune": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(Particle),
+                                           ctypes.c_int32, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -184,6 +197,22 @@ class _TorchAllocator:
         self.live.pop(ptr, None)
 
 
+def _particle_array(parts):
+    n = len(parts["radius"])
+    arr = (Particle * max(n, 1))()
+    for k in range(n):
+        q = arr[k]
+        for a in range(3):
+            q.pos[a] = float(parts["pos"][k][a])
+            q.vel[a] = float(parts["vel"][k][a])
+            q.omega[a] = float(parts["omega"][k][a])
+        q.radius = float(parts["radius"][k])
+        q.density = float(parts["density"][k])
+        q.color = float(parts["color"][k])
+        q.prescribed = int(parts["prescribed"][k])
+    return n, arr
+
+
 class Lattice:
     """One lattice on one GPU.  ``params`` is a plain dict (workloads.params)."""
 
@@ -204,7 +233,7 @@ class Lattice:
             rc = lib().lb_create(ctypes.byref(self._p), ctypes.byref(self._allocator.struct),
                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
         if rc != LB_OK:
-            raise LBError(rc, "lb_create failed")
+            raise LBError(rc, "lb_create failed: " + lib().lb_last_error(None).decode())
         self._h = h
 
     def close(self):
@@ -226,18 +255,7 @@ class Lattice:
 
     # -- particles -----------------------------------------------------------
     def add_particles(self, parts, check=True):
-        n = len(parts["radius"])
-        arr = (Particle * max(n, 1))()
-        for k in range(n):
-            q = arr[k]
-            for a in range(3):
-                q.pos[a] = float(parts["pos"][k][a])
-                q.vel[a] = float(parts["vel"][k][a])
-                q.omega[a] = float(parts["omega"][k][a])
-            q.radius = float(parts["radius"][k])
-            q.density = float(parts["density"][k])
-            q.color = float(parts["color"][k])
-            q.prescribed = int(parts["prescribed"][k])
+        n, arr = _particle_array(parts)
         rc = lib().lb_add_particles(self._h, n, arr)
         if check:
             self._check(rc)
@@ -354,3 +372,52 @@ def footprint_bytes(params, n_particles=0, max_radius=0.0, precision="fp32"):
     if rc != LB_OK:
         raise LBError(rc, "invalid parameters")
     return out.value
+
+
+class Batch:
+    """Lattices advanced together by one graph launch of ``steps_per_launch``
+    steps each (lb_batch_*).  The members must be set up and outlive the batch."""
+
+    def __init__(self, members, steps_per_launch=2, stream=None):
+        import torch
+        self.members = list(members)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.members[0].device)
+        self.stream = stream
+        arr = (ctypes.c_void_p * len(self.members))(*[m._h.value for m in self.members])
+        b = ctypes.c_void_p()
+        rc = lib().lb_batch_create(arr, len(self.members), int(steps_per_launch), ctypes.c_void_p(stream.cuda_stream),
+                                   ctypes.byref(b))
+        if rc != LB_OK:
+            raise LBError(rc, "lb_batch_create failed")
+        self._b = b
+        self.steps_per_launch = lib().lb_batch_steps_per_launch(b)
+
+    def step(self, nlaunches=1):
+        rc = lib().lb_batch_step(self._b, int(nlaunches))
+        if rc != LB_OK:
+            raise LBError(rc, lib().lb_batch_last_error(self._b).decode())
+
+    def close(self):
+        b = getattr(self, "_b", None)
+        if b is not None and b.value:
+            lib().lb_batch_destroy(b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(params, parts=None, precision="fp32", trial_steps=10):
+    """(kernel name, tile, ms per step) of the fastest sweep variant for this box (lb_autotune)."""
+    p = make_params(params, precision)
+    n, arr = _particle_array(parts) if parts is not None else (0, (Particle * 1)())
+    ms = ctypes.c_double()
+    rc = lib().lb_autotune(ctypes.byref(p), n, arr, int(trial_steps), ctypes.byref(ms))
+    if rc != LB_OK:
+        raise LBError(rc, "autotune found no runnable variant")
+    name = {v: k for k, v in KERNELS.items()}[p.kernel]
+    return name, (p.tile[0], p.tile[1], p.tile[2]), ms.value

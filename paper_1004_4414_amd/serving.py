@@ -1,0 +1,164 @@
+"""A request loop that serves simulation jobs with continuous batching.
+
+Jobs (a box, its spheres, a step count) arrive over time.  The server admits a
+waiting job as soon as its device footprint (lb_footprint_bytes) fits in the
+memory budget left by the resident jobs, keeps every admitted lattice resident
+on the GPU, and advances all resident jobs together: one graph launch of a
+batch (lb_batch_*) moves every member by ``steps_per_launch`` steps.  When a
+job has done its steps its result is read back, its lattice is freed and the
+batch is rebuilt with whatever is resident and admitted by then; jobs that
+arrive while others run join at the next launch.
+
+Each job's kernels are the ones it would run alone, so its result is bitwise
+the same alone and in the mix.
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import lbm
+
+
+@dataclass
+class Job:
+    params: dict
+    particles: dict
+    steps: int
+    arrival: float = 0.0
+    contact_angle: float = 90.0
+    name: str = ""
+
+
+@dataclass
+class Result:
+    name: str
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    sites: int
+    observables: dict
+    populations_digest: str
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def time_to_result(self):
+        return self.finished - self.arrival
+
+
+def coloured(job):
+    """the job's spheres with the particle colour of its contact angle"""
+    parts = {k: np.array(v, copy=True) for k, v in job.particles.items()}
+    parts["color"][:] = lbm.contact_angle_to_color(job.contact_angle)
+    return parts
+
+
+def digest(lat):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(lat.populations()).tobytes()).hexdigest()
+
+
+def _finish(lat, job, admitted, t0, clock, keep_digest):
+    lat.synchronize()
+    obs = lat.observables()
+    dg = digest(lat) if keep_digest else ""
+    return Result(job.name, job.arrival, admitted, clock() - t0, job.steps,
+                  job.params["nx"] * job.params["ny"] * job.params["nz"], obs, dg)
+
+
+class Server:
+    """Continuous-batching server on one GPU.
+
+    ``budget_bytes``: device memory the resident jobs may use (lb_footprint_bytes
+    per job); ``precision``: population storage of every job; ``steps_per_launch``:
+    steps per graph launch (every job's step count must be a multiple)."""
+
+    def __init__(self, budget_bytes, precision="bf16", steps_per_launch=10, keep_digest=False):
+        self.budget = int(budget_bytes)
+        self.precision = precision
+        self.k = int(steps_per_launch)
+        self.keep_digest = keep_digest
+        self.batch_rebuilds = 0
+
+    def footprint(self, job):
+        r = float(job.particles["radius"].max()) if len(job.particles["radius"]) else 0.0
+        return lbm.footprint_bytes(job.params, len(job.particles["radius"]), r, self.precision)
+
+    def run(self, jobs, clock=time.perf_counter):
+        for j in jobs:
+            if j.steps % self.k:
+                raise ValueError(f"job {j.name}: {j.steps} steps is not a multiple of {self.k}")
+            if self.footprint(j) > self.budget:
+                raise ValueError(f"job {j.name} does not fit the memory budget")
+        pending = sorted(jobs, key=lambda j: j.arrival)
+        active = []  # [job, lattice, remaining, admitted, bytes]
+        used = 0
+        batch = None
+        results = []
+        t0 = clock()
+        while pending or active:
+            now = clock() - t0
+            changed = False
+            # admission in arrival order while memory allows (no overtaking)
+            while pending and pending[0].arrival <= now and used + self.footprint(pending[0]) <= self.budget:
+                j = pending.pop(0)
+                lat = lbm.Lattice(j.params, precision=self.precision)
+                if len(j.particles["radius"]):
+                    lat.add_particles(coloured(j))
+                b = self.footprint(j)
+                used += b
+                active.append([j, lat, j.steps, clock() - t0, b])
+                changed = True
+            if not active:
+                time.sleep(max(0.0, min(pending[0].arrival - now, 0.05)))
+                continue
+            if changed or batch is None:
+                if batch is not None:
+                    batch.close()
+                batch = lbm.Batch([a[1] for a in active], steps_per_launch=self.k)
+                self.batch_rebuilds += 1
+            batch.step(1)
+            done = []
+            for a in active:
+                a[2] -= self.k
+                if a[2] == 0:
+                    done.append(a)
+            if done:
+                batch.close()
+                batch = None
+                for a in done:
+                    results.append(_finish(a[1], a[0], a[3], t0, clock, self.keep_digest))
+                    a[1].close()
+                    used -= a[4]
+                    active.remove(a)
+        return results
+
+
+def run_alone(jobs, precision="fp32", keep_digest=False, clock=time.perf_counter):
+    """One job at a time in arrival order, each stepped by lb_step alone (the
+    comparison point of the server)."""
+    results = []
+    t0 = clock()
+    for j in sorted(jobs, key=lambda j: j.arrival):
+        now = clock() - t0
+        if j.arrival > now:
+            time.sleep(j.arrival - now)
+        admitted = clock() - t0
+        lat = lbm.Lattice(j.params, precision=precision)
+        if len(j.particles["radius"]):
+            lat.add_particles(coloured(j))
+        lat.step(j.steps)
+        results.append(_finish(lat, j, admitted, t0, clock, keep_digest))
+        lat.close()
+    return results
+
+
+def summary(results):
+    """p50 / p99 time-to-result, jobs per hour over the whole run, site updates per second"""
+    ttr = np.array([r.time_to_result for r in results])
+    makespan = max(r.finished for r in results) - min(r.arrival for r in results)
+    updates = sum(r.sites * r.steps for r in results)
+    return dict(jobs=len(results), p50_s=float(np.percentile(ttr, 50)), p99_s=float(np.percentile(ttr, 99)),
+                makespan_s=float(makespan), jobs_per_hour=float(len(results) / makespan * 3600.0),
+                mlups=float(updates / makespan / 1e6))

@@ -123,3 +123,52 @@ def config(name):
         pos = random_sphere_positions(box, n, 5.0, seed=1003)
         return p, make_particles(pos, 5.0), 10000, "fp32"
     raise KeyError(name)
+
+
+def _job(rng, edge, ratio_red, fraction, radius, theta, steps, seed, total=0.7):
+    """one box of an ensemble: periodic cube, solvent ratio red:blue, spheres
+    at the volume fraction, contact angle theta (degrees; the caller converts
+    it to a particle colour)"""
+    box = (edge, edge, edge)
+    p = params(nx=edge, ny=edge, nz=edge, rho_init=(total * ratio_red, total * (1.0 - ratio_red)),
+               noise_amp=0.01, g_br=0.08, seed=seed)
+    n = max(1, sphere_count(box, fraction, radius))
+    # dense packings (up to 0.3) leave a smaller gap so that random addition
+    # does not jam
+    pos = random_sphere_positions(box, n, radius, seed=seed, min_gap=1.0 if fraction <= 0.2 else 0.1)
+    return dict(params=p, particles=make_particles(pos, radius), steps=int(steps), contact_angle=float(theta))
+
+
+def ensemble(n_boxes=64, seed=1004, steps=2000):
+    """Batched ensemble: ``n_boxes`` independent periodic boxes with edges drawn
+    from {32, 48, 64, 96}, solvent ratios 50:50 to 80:20, particle volume
+    fractions 0.05-0.25, radii 4-6 and contact angles 60-120 degrees, FP32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for k in range(n_boxes):
+        edge = int(rng.choice([32, 48, 64, 96]))
+        jobs.append(_job(rng, edge, float(rng.uniform(0.5, 0.8)), float(rng.uniform(0.05, 0.25)),
+                         float(rng.uniform(4.0, 6.0)), float(rng.uniform(60.0, 120.0)), steps, seed * 1000 + k))
+    return jobs
+
+
+def serving_trace(n_jobs=40, seed=1005, rate_per_min=20.0, time_scale=1.0, step_scale=1.0, step_quantum=2):
+    """Serving trace: Poisson arrivals at ``rate_per_min`` jobs per minute of
+    periodic boxes with edges 48-192, radii 4-8 at volume fractions 0.05-0.3,
+    contact angles 45-135 degrees and 2000-20000 steps.  ``time_scale`` divides
+    the arrival times and ``step_scale`` multiplies the step counts (a
+    compressed trace keeps the mix and shortens the run); step counts are
+    rounded to multiples of ``step_quantum``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    jobs = []
+    for k in range(n_jobs):
+        t += float(rng.exponential(60.0 / rate_per_min)) / time_scale
+        edge = int(rng.integers(48, 193))
+        steps = float(rng.uniform(2000, 20000)) * step_scale
+        steps = max(step_quantum, int(round(steps / step_quantum)) * step_quantum)
+        job = _job(rng, edge, float(rng.uniform(0.5, 0.8)), float(rng.uniform(0.05, 0.3)),
+                   float(rng.uniform(4.0, 8.0)), float(rng.uniform(45.0, 135.0)), steps, seed * 1000 + k)
+        job["arrival"] = t
+        jobs.append(job)
+    return jobs

@@ -1,0 +1,120 @@
+"""Batches (one graph launch advancing several lattices), the autotuner and the
+continuous-batching server, on the GPU through the C interface.
+
+Graph replays are checked against eager stepping of identical lattices after
+every replay, with the program's own eager work and synchronisations between
+the replays; every comparison is bitwise (the batch runs the same kernels)."""
+import numpy as np
+import pytest
+
+from paper_1004_4414_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def lbm():
+    from paper_1004_4414_amd import lbm as _lbm
+    return _lbm
+
+
+def _members():
+    """three uneven boxes: spheres with colours, a sphere-free box, a 16-bit box"""
+    out = []
+    p = W.params(nx=32, ny=32, nz=32, rho_init=(0.4, 0.3), noise_amp=0.02, g_br=0.08, seed=21)
+    rng = np.random.default_rng(21)
+    pos = W.random_sphere_positions((32, 32, 32), 3, 4.0, seed=21)
+    parts = W.make_particles(pos, 4.0, vel=rng.uniform(-0.02, 0.02, (3, 3)), color=[0.05, -0.05, 0.0])
+    out.append((p, parts, "fp32"))
+    out.append((W.params(nx=40, ny=24, nz=20, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.09, seed=22),
+                None, "fp32"))
+    p3 = W.params(nx=36, ny=36, nz=28, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.08, seed=23)
+    pos3 = W.random_sphere_positions((36, 36, 28), 2, 5.0, seed=23)
+    out.append((p3, W.make_particles(pos3, 5.0), "bf16"))
+    return out
+
+
+def _make(spec):
+    p, parts, prec = spec
+    lat = lbm().Lattice(p, precision=prec)
+    if parts is not None:
+        lat.add_particles(parts)
+    return lat
+
+
+def _same(a, b):
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.owner(), b.owner())
+    if a.num_particles:
+        pa, pb = a.particles(), b.particles()
+        for k in ("R", "U", "W"):
+            assert np.array_equal(pa[k], pb[k]), k
+
+
+def test_batch_replays_match_eager_stepping():
+    specs = _members()
+    batched = [_make(s) for s in specs]
+    eager = [_make(s) for s in specs]
+    batch = lbm().Batch(batched, steps_per_launch=4)
+    assert batch.steps_per_launch == 4
+    done = 0
+    for nl in (1, 2, 1):
+        batch.step(nl)
+        for e in eager:
+            e.step(4 * nl)
+        done += 4 * nl
+        # eager work of the program itself between replays
+        obs = batched[0].observables()
+        assert obs["step"] == done
+        for b, e in zip(batched, eager):
+            _same(b, e)
+    batch.close()
+    for b, e in zip(batched, eager):
+        b.step(2)
+        e.step(2)
+        _same(b, e)
+
+
+def test_batch_membership_rules():
+    L = lbm()
+    a = _make(_members()[1])
+    batch = L.Batch([a], steps_per_launch=2)
+    with pytest.raises(L.LBError):
+        L.Batch([a], steps_per_launch=2)  # already in a batch
+    assert a.add_particles(W.make_particles([[5, 5, 5]], 3.0), check=False) == L.LB_ESTATE
+    batch.close()
+    with pytest.raises(L.LBError):
+        L.Batch([a], steps_per_launch=3)  # odd step count
+
+
+def test_autotune_returns_a_runnable_variant():
+    L = lbm()
+    p = W.params(nx=48, ny=40, nz=36, seed=31)
+    parts = W.make_particles(W.random_sphere_positions((48, 40, 36), 4, 4.0, seed=31), 4.0)
+    kernel, tile, ms = L.autotune(p, parts, "fp32", trial_steps=3)
+    assert kernel in ("fused", "twopass") and ms > 0.0
+    lat = L.Lattice(p, precision="fp32", kernel=kernel, tile=tile)
+    lat.add_particles(parts)
+    lat.step(2)
+    lat.synchronize()
+
+
+def test_served_results_equal_results_alone():
+    from paper_1004_4414_amd import serving as S
+    trace = W.serving_trace(5, seed=41, rate_per_min=600.0, step_scale=0.004, step_quantum=4)
+    jobs = []
+    for k, t in enumerate(trace):
+        edge = 24 + 4 * k  # small boxes for the test, the trace's mix otherwise
+        p = dict(t["params"], nx=edge, ny=edge, nz=edge)
+        pos = W.random_sphere_positions((edge, edge, edge), 1 + k % 3, 4.0, seed=41 + k)
+        jobs.append(S.Job(p, W.make_particles(pos, 4.0), t["steps"], arrival=t["arrival"],
+                          contact_angle=t["contact_angle"], name=f"job{k}"))
+    # a budget that holds about two jobs forces admission by footprint
+    fp = S.Server(1, precision="fp32").footprint
+    srv = S.Server(budget_bytes=2.2 * max(fp(j) for j in jobs), precision="fp32", steps_per_launch=4,
+                   keep_digest=True)
+    served = {r.name: r for r in srv.run(jobs)}
+    alone = {r.name: r for r in S.run_alone(jobs, precision="fp32", keep_digest=True)}
+    assert srv.batch_rebuilds >= 2
+    for name, r in alone.items():
+        assert served[name].populations_digest == r.populations_digest, name
+        assert served[name].observables["step"] == r.observables["step"] == r.steps

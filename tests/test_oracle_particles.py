@@ -240,3 +240,49 @@ def test_lubrication_acts_only_below_the_cutoff_and_is_clamped():
         f.append(F[0, 0])
     assert f[0] == f[1]  # clamped at h_min = 0.1
     assert abs(f[2]) < abs(f[1])
+
+
+def _row_of_spheres(n, gap, vel, density, r=3.0):
+    """spheres of radius r on a line along x in an empty lattice (no fluid)"""
+    nx = int(math.ceil(n * (2 * r + gap))) + 8
+    orc = O.Oracle(W.params(nx=nx, ny=16, nz=16, rho_init=(0.0, 0.0), noise_amp=0.0, g_br=0.0))
+    xs = [4.0 + r + k * (2 * r + gap) for k in range(n)]
+    assert orc.add_particles(W.make_particles([[x, 8.0, 8.0] for x in xs], r, vel=vel, density=density)) == 0
+    return orc
+
+
+def test_lubrication_of_an_isolated_pair_is_backward_euler():
+    """Eq. (22) taken implicitly: for one pair the approach speed after a step
+    is w / (1 + c (1/m_1 + 1/m_2)) (closed form), even where the explicit
+    update c (1/m_1 + 1/m_2) > 2 would reverse and amplify it."""
+    r, gap, v, rho_p = 3.0, 0.1, 0.002, 0.05
+    orc = _row_of_spheres(2, gap, [[v, 0, 0], [-v, 0, 0]], rho_p, r)
+    m = rho_p * 4.0 / 3.0 * math.pi * r ** 3
+    nu = (1.0 - 0.5) / 3.0
+    c = 6.0 * math.pi * nu * 1.0 * (r * r / (2 * r)) ** 2 * (1.0 / 0.1 - 1.0 / (2.0 / 3.0))
+    assert c * 2.0 / m > 2.0  # stiff: the explicit update would be unstable
+    orc.step(1)
+    U = orc.particles()["U"]
+    w_after = U[0, 0] - U[1, 0]
+    assert abs(w_after - 2 * v / (1.0 + 2.0 * c / m)) < 1e-15
+    assert U[0, 0] == -U[1, 0] and U[0, 0] > 0.0
+
+
+def test_stiff_lubrication_network_dissipates_and_conserves_momentum():
+    """A packed row of light spheres with alternating velocities (stiff: the
+    explicit update would grow them geometrically): the shared-mass pair
+    impulses only remove kinetic energy, and momentum is exact."""
+    vel = [[0.002 * (-1) ** k, 0.0005 * k, 0.0] for k in range(6)]
+    orc = _row_of_spheres(6, 0.05, vel, 0.05)
+    p0 = orc.particles()
+    m = 0.05 * 4.0 / 3.0 * math.pi * 27
+    mom0 = (m * p0["U"]).sum(axis=0)
+    ke = 0.5 * m * (p0["U"] ** 2).sum()
+    for _ in range(10):
+        orc.step(1)
+        P = orc.particles()
+        ke_new = 0.5 * m * (P["U"] ** 2).sum()
+        assert ke_new <= ke * (1 + 1e-12)
+        ke = ke_new
+        assert np.allclose((m * P["U"]).sum(axis=0), mom0, rtol=0, atol=1e-16)
+    assert np.abs(orc.particles()["U"][:, 0]).max() < 0.002
