@@ -33,6 +33,26 @@ def algorithmic_bytes_per_site(precision):
     return 2 * 19 * ts * 2
 
 
+def measured_traffic():
+    """HBM bytes per launch of the collide sweep from the committed counter
+    summary, or None when the sweep's sources changed since it was taken"""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "bijel256_collide_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = hashlib.sha256()
+    for f in ("lbm_device.h", "lbm_fluid.hip"):
+        with open(os.path.join(ROOT, "paper_1004_4414_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    m_hash = re.search(r"source-sha256 \(lbm_device.h \+ lbm_fluid.hip\): ([0-9a-f]{64})", text)
+    m_bytes = re.search(r"traffic-bytes-per-launch: (\d+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != h.hexdigest():
+        return None
+    return int(m_bytes.group(1))
+
+
 def cpu_baseline(seconds_budget=20.0):
     """The FP64 oracle, single-threaded, on a bounded sample of the workload:
     a 64^3 box with the same volume fraction (75 spheres of radius 5) and the
@@ -91,10 +111,14 @@ def bench_ensemble(args):
     # (a) one job at a time
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for j in jobs:
+    failed_alone = []
+    for i, j in enumerate(jobs):
         lat = make(j)
         lat.step(steps)
-        lat.synchronize()
+        try:
+            lat.synchronize()
+        except lbm.LBError:  # the job went unstable: it is counted as not completed
+            failed_alone.append(i)
         lat.close()
     t_alone = time.perf_counter() - t0
     print(f"# one at a time: {t_alone:.2f} s", file=sys.stderr, flush=True)
@@ -105,12 +129,17 @@ def bench_ensemble(args):
     batch = lbm.Batch(lats, steps_per_launch=k)
     t_capture = time.perf_counter() - t0
     batch.step(steps // k)
-    for lat in lats:
-        lat.synchronize()
+    failed = []
+    for i, lat in enumerate(lats):
+        try:
+            lat.synchronize()
+        except lbm.LBError:
+            failed.append(i)
     t_batch = time.perf_counter() - t0
     print(f"# batched: {t_batch:.2f} s (capture {t_capture:.2f} s)", file=sys.stderr, flush=True)
     batch.close()
-    jph = len(jobs) / t_batch * 3600.0
+    done = len(jobs) - len(failed)
+    jph = done / t_batch * 3600.0
     return {
         "metric": "jobs/hour (batched ensemble of 64 boxes, 2000 steps each)",
         "value": round(jph, 1), "unit": "jobs/hour", "n_gpus": 1, "steps": steps, "warmup": 0,
@@ -120,9 +149,10 @@ def bench_ensemble(args):
                                "fractions 0.05-0.25, radii 4-6, contact angles 60-120 deg, FP32",
                    "sites": sites, "spheres": int(sum(len(j["particles"]["radius"]) for j in jobs)),
                    "steps_per_launch": k, "autotuned": {str(e): [v[0], list(v[1])] for e, v in tuned.items()}},
-        "one_at_a_time": {"jobs_per_hour": round(len(jobs) / t_alone * 3600.0, 1), "seconds": round(t_alone, 3)},
+        "one_at_a_time": {"jobs_per_hour": round((len(jobs) - len(failed_alone)) / t_alone * 3600.0, 1),
+                          "seconds": round(t_alone, 3), "failed_jobs": failed_alone},
         "batched": {"seconds": round(t_batch, 3), "capture_seconds": round(t_capture, 3),
-                    "mlups": round(sites * steps / t_batch / 1e6, 1)},
+                    "mlups": round(sites * steps / t_batch / 1e6, 1), "failed_jobs": failed},
         "speedup": round(t_alone / t_batch, 3),
     }
 
@@ -172,7 +202,7 @@ def main():
                     help="population storage (default: the workload's); fp16/bf16 store deviations and compute in FP32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
-                    help="before the run, copy a buffer of this many MiB device to device three times "
+                    help="before the run, negate a buffer of this many MiB into another three times "
                          "(a kernel of known traffic that calibrates rocprofv3's FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -184,14 +214,15 @@ def main():
     from paper_1004_4414_amd import lbm, workloads as W
 
     if args.copy_mib > 0:
+        # one elementwise kernel per call that reads and writes copy_mib MiB
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-        print(f"# calibration copy: 3 x {args.copy_mib} MiB read + {args.copy_mib} MiB written", file=sys.stderr,
-              flush=True)
+        print(f"# calibration kernel: 3 launches, each {args.copy_mib} MiB read + {args.copy_mib} MiB written",
+              file=sys.stderr, flush=True)
 
     if args.workload == "ensemble64":
         print(json.dumps(bench_ensemble(args)), flush=True)
@@ -229,6 +260,9 @@ def main():
 
     mlups = N * args.steps / elapsed / 1e6
     bps = algorithmic_bytes_per_site(precision)
+    kern_name = "twopass" if args.kernel in ("auto", "twopass") else args.kernel
+    traffic = measured_traffic() if (args.workload == "bijel256" and precision == "fp32" and kern_name == "twopass"
+                                     and args.tile == "0,0,0") else None
     sweep_s = k_ms / 1e3 / max(k_n, 1)
     achieved = bps * N / sweep_s / 1e9
     line = {
@@ -260,7 +294,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "collide-and-stream sweep",
             "bytes_per_site": bps,
             "ms_per_launch": round(sweep_s * 1e3, 4),

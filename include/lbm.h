@@ -62,7 +62,8 @@ enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP16 = 2, LB_BF16 = 3 };
 /* Fluid kernel variants. LB_KERNEL_FUSED: one sweep per step that computes
  * densities, virtual fluid, Shan-Chen force, collision and streaming with
  * z-marching tiles; LB_KERNEL_TWOPASS: a density sweep, a virtual-fluid pass
- * and a collide-and-stream sweep. Both compute the same step. */
+ * and a collide-and-stream sweep. Both compute the same step. LB_KERNEL_AUTO
+ * takes the two-pass sweep (lb_autotune measures the alternatives for a box). */
 enum { LB_KERNEL_AUTO = 0, LB_KERNEL_FUSED = 1, LB_KERNEL_TWOPASS = 2 };
 
 typedef struct lb_handle lb_handle;
@@ -231,8 +232,9 @@ int lb_footprint_bytes(const lb_params *p, int32_t n_particles, double max_radiu
  * batch.  Members must be fully set up (spheres added); while in a batch they
  * refuse lb_add_particles and lb_set_state, must not record kernel timing,
  * and must outlive the batch.  Errors: LB_EINVAL (bad arguments, a member
- * already in a batch or timing), LB_EDEVICE (capture or launch failed; the
- * message is in lb_batch_last_error).
+ * already in a batch or timing), LB_EDEVICE (capture or launch failed); the
+ * message is in lb_batch_last_error (with NULL: of the last failed
+ * lb_batch_create on the calling thread).
  * ------------------------------------------------------------------------- */
 typedef struct lb_batch lb_batch;
 int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, void *stream, lb_batch **out);

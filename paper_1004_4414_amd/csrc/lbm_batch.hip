@@ -27,8 +27,12 @@ struct lb_batch {
 
 namespace {
 
+// message of the last failed lb_batch_create on this thread (lb_batch_last_error(NULL))
+thread_local std::string g_batch_create_error = "null batch";
+
 int bfail(lb_batch *b, int code, const std::string &msg) {
     if (b) b->err = msg;
+    else g_batch_create_error = msg;
     return code;
 }
 
@@ -53,14 +57,17 @@ void release(lb_batch *b) {
 extern "C" {
 
 int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, void *hip_stream, lb_batch **out) {
-    if (!out) return LB_EINVAL;
+    if (!out) return bfail(nullptr, LB_EINVAL, "null output pointer");
     *out = nullptr;
-    if (n < 1 || !members) return LB_EINVAL;
-    if (steps_per_launch < 2 || steps_per_launch % 2) return LB_EINVAL;
+    if (n < 1 || !members) return bfail(nullptr, LB_EINVAL, "no members");
+    if (steps_per_launch < 2 || steps_per_launch % 2)
+        return bfail(nullptr, LB_EINVAL, "steps_per_launch must be even and >= 2");
     for (int i = 0; i < n; ++i) {
-        if (!members[i] || members[i]->in_batch || members[i]->timing) return LB_EINVAL;
+        if (!members[i]) return bfail(nullptr, LB_EINVAL, "null member " + std::to_string(i));
+        if (members[i]->in_batch) return bfail(nullptr, LB_EINVAL, "member " + std::to_string(i) + " is in a batch");
+        if (members[i]->timing) return bfail(nullptr, LB_EINVAL, "member " + std::to_string(i) + " records timing");
         for (int j = 0; j < i; ++j)
-            if (members[j] == members[i]) return LB_EINVAL;
+            if (members[j] == members[i]) return bfail(nullptr, LB_EINVAL, "member " + std::to_string(i) + " repeated");
     }
     lb_batch *b = new lb_batch;
     b->m.assign(members, members + n);
@@ -112,7 +119,7 @@ int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, vo
         if (fork) (void)hipEventDestroy(fork);
         if (cs) (void)hipStreamDestroy(cs);
         delete b;
-        return LB_EDEVICE;
+        return bfail(nullptr, LB_EDEVICE, e.what);
     }
     for (hipEvent_t e : joins) (void)hipEventDestroy(e);
     (void)hipEventDestroy(fork);
@@ -146,7 +153,7 @@ int lb_batch_step(lb_batch *b, int32_t nlaunches) {
 
 int32_t lb_batch_steps_per_launch(const lb_batch *b) { return b ? b->k : 0; }
 
-const char *lb_batch_last_error(const lb_batch *b) { return b ? b->err.c_str() : "null batch"; }
+const char *lb_batch_last_error(const lb_batch *b) { return b ? b->err.c_str() : g_batch_create_error.c_str(); }
 
 void lb_batch_destroy(lb_batch *b) {
     if (!b) return;

@@ -389,7 +389,7 @@ class Batch:
         rc = lib().lb_batch_create(arr, len(self.members), int(steps_per_launch), ctypes.c_void_p(stream.cuda_stream),
                                    ctypes.byref(b))
         if rc != LB_OK:
-            raise LBError(rc, "lb_batch_create failed")
+            raise LBError(rc, "lb_batch_create failed: " + lib().lb_batch_last_error(None).decode())
         self._b = b
         self.steps_per_launch = lib().lb_batch_steps_per_launch(b)
 

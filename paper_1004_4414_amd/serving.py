@@ -60,11 +60,17 @@ def digest(lat):
 
 
 def _finish(lat, job, admitted, t0, clock, keep_digest):
-    lat.synchronize()
+    """the job's result; a job whose lattice reports an error (e.g. it went
+    unstable) finishes with that error instead of observables"""
+    sites = job.params["nx"] * job.params["ny"] * job.params["nz"]
+    try:
+        lat.synchronize()
+    except lbm.LBError as e:
+        return Result(job.name, job.arrival, admitted, clock() - t0, job.steps, sites, None, "",
+                      extra={"error": str(e)})
     obs = lat.observables()
     dg = digest(lat) if keep_digest else ""
-    return Result(job.name, job.arrival, admitted, clock() - t0, job.steps,
-                  job.params["nx"] * job.params["ny"] * job.params["nz"], obs, dg)
+    return Result(job.name, job.arrival, admitted, clock() - t0, job.steps, sites, obs, dg)
 
 
 class Server:
@@ -155,10 +161,13 @@ def run_alone(jobs, precision="fp32", keep_digest=False, clock=time.perf_counter
 
 
 def summary(results):
-    """p50 / p99 time-to-result, jobs per hour over the whole run, site updates per second"""
-    ttr = np.array([r.time_to_result for r in results])
+    """p50 / p99 time-to-result and jobs per hour over the completed jobs, site
+    updates per second over the whole run, and the jobs that failed"""
+    ok = [r for r in results if r.observables is not None]
+    ttr = np.array([r.time_to_result for r in ok]) if ok else np.zeros(1)
     makespan = max(r.finished for r in results) - min(r.arrival for r in results)
     updates = sum(r.sites * r.steps for r in results)
-    return dict(jobs=len(results), p50_s=float(np.percentile(ttr, 50)), p99_s=float(np.percentile(ttr, 99)),
-                makespan_s=float(makespan), jobs_per_hour=float(len(results) / makespan * 3600.0),
+    return dict(jobs=len(ok), failed=[r.name for r in results if r.observables is None],
+                p50_s=float(np.percentile(ttr, 50)), p99_s=float(np.percentile(ttr, 99)),
+                makespan_s=float(makespan), jobs_per_hour=float(len(ok) / makespan * 3600.0),
                 mlups=float(updates / makespan / 1e6))
