@@ -221,6 +221,28 @@ int lb_kernel_timing(lb_handle *h, int32_t which, double *ms, int64_t *launches)
 int lb_footprint_bytes(const lb_params *p, int32_t n_particles, double max_radius, size_t *bytes);
 
 /* ---------------------------------------------------------------------------
+ * Analysis observables (off the time-step path; both wait for the handle's
+ * stream and copy the result to host memory owned by the caller).
+ *
+ * lb_domain_size: the lateral domain sizes L_i = 2 pi / sqrt(<k_i^2>) of
+ * Sec. VI, Eqs. (33)-(35), with <k_i^2> the second moment along axis i of the
+ * structure function S(k) = |phi'_k|^2 / N of the order-parameter fluctuations
+ * phi' = phi - <phi>, phi = rho_r - rho_b on fluid sites and 0 on solid ones;
+ * k_i = 2 pi m / n_i with |m| <= n_i / 2.  L_out[0..2] (x, y, z), +inf along
+ * an axis with no power (phi' constant along it).  Every axis must be at most
+ * 2048 (else LB_EINVAL).
+ * lb_order_parameter_profile: out[0 .. n_axis-1] = plane averages of phi over
+ * the planes normal to `axis` (0 = x, 1 = y, 2 = z), solid sites counted as 0;
+ * the zero of this profile locates a flat interface (the contact angle of
+ * Sec. V, Eq. (32)).
+ * The first call allocates 8 bytes per site of device memory for phi (kept
+ * until lb_destroy; not counted by lb_footprint_bytes).  Errors: LB_EINVAL,
+ * LB_ENOMEM, LB_EDEVICE (message in lb_last_error).
+ * ------------------------------------------------------------------------- */
+int lb_domain_size(lb_handle *h, double L_out[3]);
+int lb_order_parameter_profile(lb_handle *h, int32_t axis, double *out);
+
+/* ---------------------------------------------------------------------------
  * Batches: many lattices advanced by one graph launch.
  *
  * lb_batch_create captures steps_per_launch (even, >= 2) time steps of every

@@ -267,3 +267,39 @@ def cs2():
 
 def uniform01(seed, k):
     return lib().orc_uniform01(int(seed) & (2 ** 64 - 1), int(k))
+
+
+# ---------------------------------------------------------------------------
+# Analysis observables of the oracle state (Sec. V, Eq. (32); Sec. VI,
+# Eqs. (33)-(35)), from the order parameter phi = rho_r - rho_b on fluid sites
+# (0 on solid ones).  The structure function is taken from the full 3-D FFT
+# of the fluctuations, as the equations define it.
+# ---------------------------------------------------------------------------
+def order_parameter(orc):
+    """phi = rho_r - rho_b on fluid sites, 0 on solid ones; indexed [z, y, x]"""
+    rho = orc.fields()["rho"]
+    return np.where(orc.owner() == -1, rho[0] - rho[1], 0.0)
+
+
+def domain_size(phi):
+    """(L_x, L_y, L_z) = 2 pi / sqrt(<k_i^2>) with <k_i^2> the S(k)-weighted
+    mean of k_i^2, S(k) = |phi'_k|^2 / N; phi indexed [z, y, x]"""
+    phi = np.asarray(phi, dtype=np.float64)
+    N = phi.size
+    S = np.abs(np.fft.fftn(phi - phi.mean())) ** 2 / N
+    nz, ny, nx = phi.shape
+    k = [2.0 * np.pi * np.fft.fftfreq(n) for n in (nx, ny, nz)]  # |m| <= n/2 as 2 pi m / n
+    kz, ky, kx = np.meshgrid(k[2], k[1], k[0], indexing="ij")
+    tot = S.sum()
+    out = []
+    for ki in (kx, ky, kz):
+        m2 = (ki ** 2 * S).sum() / tot if tot > 0 else 0.0
+        out.append(2.0 * np.pi / np.sqrt(m2) if m2 > 0 else np.inf)
+    return np.array(out)
+
+
+def order_parameter_profile(phi, axis=2):
+    """plane averages of phi along axis (0 = x, 1 = y, 2 = z); phi indexed [z, y, x]"""
+    phi = np.asarray(phi, dtype=np.float64)
+    other = {0: (0, 1), 1: (0, 2), 2: (1, 2)}[axis]  # array axes averaged over
+    return phi.mean(axis=other)

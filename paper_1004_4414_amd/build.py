@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_fluid.hip", "lbm_fused.hip", "lbm_particles.hip", "lbm_batch.hip"]
+SOURCES = ["lbm_api.hip", "lbm_fluid.hip", "lbm_fused.hip", "lbm_particles.hip", "lbm_batch.hip", "lbm_observe.hip"]
 HEADERS = ["lbm_device.h", "lbm_handle.h", "../../include/lbm.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -33,6 +33,7 @@ struct lb_handle {
     int n_partial = 0;
     lbm::DevState *dstate = nullptr;
     double *fields = nullptr;  // lazily allocated output staging of lb_get_fields
+    double *phi = nullptr;     // lazily allocated order parameter of the observables
 
     // particles
     int np = 0;

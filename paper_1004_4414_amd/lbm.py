@@ -29,7 +29,7 @@ ENTRY_POINTS = [
     "lb_get_state", "lb_set_state", "lb_contact_angle_to_color", "lb_footprint_bytes",
     "lb_enable_timing", "lb_kernel_timing",
     "lb_batch_create", "lb_batch_step", "lb_batch_steps_per_launch", "lb_batch_last_error", "lb_batch_destroy",
-    "lb_autotune",
+    "lb_autotune", "lb_domain_size", "lb_order_parameter_profile",
 ]
 
 
@@ -131,6 +131,8 @@ def lib():
             "lb_batch_destroy": (None, [vp]),
             "lb_autotune": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(Particle),
                                            ctypes.c_int32, dp]),
+            "lb_domain_size": (ctypes.c_int, [vp, dp]),
+            "lb_order_parameter_profile": (ctypes.c_int, [vp, ctypes.c_int32, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -257,6 +259,8 @@ class Lattice:
     def add_particles(self, parts, check=True):
         n, arr = _particle_array(parts)
         rc = lib().lb_add_particles(self._h, n, arr)
+        if rc == LB_OK:
+            self.radii = np.concatenate([getattr(self, "radii", np.zeros(0)), np.asarray(parts["radius"], float)])
         if check:
             self._check(rc)
         return rc
@@ -343,6 +347,20 @@ class Lattice:
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._check(lib().lb_set_state(self._h, buf, len(blob)))
 
+
+    # -- observables ---------------------------------------------------------
+    def domain_size(self):
+        """(L_x, L_y, L_z) of Sec. VI from the order-parameter structure function"""
+        out = np.zeros(3)
+        self._check(lib().lb_domain_size(self._h, _dp(out)))
+        return out
+
+    def order_parameter_profile(self, axis=2):
+        """plane averages of phi = rho_r - rho_b along axis (0 = x, 1 = y, 2 = z)"""
+        n = (self.shape[2], self.shape[1], self.shape[0])[axis]
+        out = np.zeros(n)
+        self._check(lib().lb_order_parameter_profile(self._h, int(axis), _dp(out)))
+        return out
 
     # -- measurement ---------------------------------------------------------
     def enable_timing(self, on=True):

@@ -172,3 +172,18 @@ def serving_trace(n_jobs=40, seed=1005, rate_per_min=20.0, time_scale=1.0, step_
         job["arrival"] = t
         jobs.append(job)
     return jobs
+
+
+def slab_populations(shape, rho_major, rho_minor, z0, z1):
+    """Populations (2, 19, nz, ny, nx) of fluid at rest with a red slab
+    z0 <= z < z1 (red density rho_major, blue rho_minor) in blue fluid of the
+    opposite composition: the flat-interface start of the contact-angle runs
+    (Sec. V).  At rest each population is its lattice weight times the density
+    (1/3 for the rest direction, 1/18 for the 6 faces, 1/36 for the 12 edges,
+    in the library's direction order: rest, faces, edges)."""
+    nz, ny, nx = shape
+    z = np.arange(nz)[:, None, None]
+    red = np.broadcast_to((z >= z0) & (z < z1), shape)
+    rho = np.stack([np.where(red, rho_major, rho_minor), np.where(red, rho_minor, rho_major)])
+    w = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
+    return rho[:, None] * w[None, :, None, None, None]
