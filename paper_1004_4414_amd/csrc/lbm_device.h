@@ -259,6 +259,24 @@ __device__ __forceinline__ bool dense_site(const DevParams &P, unsigned &n, int 
     z = (int)zq;
     return true;
 }
+// dense_site for boxes whose nx is a multiple of 64: a wavefront's 64 sites
+// then lie in one row, so y and z are computed once per wavefront (scalar
+// registers) from its first site; x = x0 + lane.
+__device__ __forceinline__ bool dense_site_rows(const DevParams &P, unsigned &n, int &x, int &y, int &z) {
+    const unsigned nb = gridDim.x;
+    unsigned b = blockIdx.x;
+    if (nb % 8u == 0) b = (b % 8u) * (nb / 8u) + b / 8u;
+    n = b * 256u + threadIdx.x;
+    if (n >= (unsigned)P.N) return false;
+    const unsigned n0 = __builtin_amdgcn_readfirstlane(n & ~63u);
+    const unsigned zq = fast_div(n0, P.div_nxy);
+    const unsigned r = n0 - zq * P.div_nxy.d;
+    const unsigned yq = fast_div(r, P.div_nx);
+    x = (int)(r - yq * P.div_nx.d + (n & 63u));
+    y = (int)yq;
+    z = (int)zq;
+    return true;
+}
 __device__ __forceinline__ int wrapany(int a, int n) { a %= n; return a < 0 ? a + n : a; }
 
 // equilibrium of Eq. (3) with c_s^2 = 1/3 for one direction
@@ -519,11 +537,14 @@ __device__ __forceinline__ void psi_force_sum(const DevParams &P, const T (&pn)[
 // ---------------------------------------------------------------------------
 // Population storage (pull form).  Slot (c, i, z) of a buffer holds the value
 // that site z + c_i receives in direction i: the post-streaming population of
-// a fluid site x is f_i(x) = slot (i, x - c_i).  A step reads those slots,
-// collides and writes its own slots (i, x) with aligned, full-line stores;
-// when x + c_i is solid the bounced population is written once more into the
-// unused slot (opp(i), x + c_i), which is exactly where x reads direction
-// opp(i) at the next step.
+// a fluid site x is f_i(x) = slot (i, x - c_i).  The sweep reads those slots,
+// collides and writes the own slots (i, x) of every site, solid ones included
+// (zeros), so that every store instruction covers whole 512-byte runs: stores
+// with lanes masked off leave partly written lines that HBM writes back far
+// more slowly.  When x + c_i is solid, f*_i(x) in slot (i, x) is read by the
+// link kernels after the sweep, which write the bounced population (with the
+// moving-wall term) into the solid site's slot (opp(i), x + c_i), exactly
+// where x reads direction opp(i) at the next step.
 // ---------------------------------------------------------------------------
 
 // signed offsets from a site to its 18 neighbours with the periodic wrap folded
@@ -557,6 +578,78 @@ __device__ __forceinline__ void pull_load(const S *__restrict__ fin, unsigned n,
         const Pair<T> v = load_pop(fin, pidx(0, i, src));
         f[0][i] = v.x;
         f[1][i] = v.y;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Row-aligned addressing (nx a multiple of 64, sites from dense_site_rows).
+// Every row that a wavefront's pulls, Psi reads and own stores touch is the
+// same for all of its lanes, so the row's byte offset is wavefront-uniform
+// (scalar arithmetic) and a lane adds a 32-bit offset that depends only on
+// its x and the direction's x step.  The addresses are those of pidx / sidx:
+// with m = R nx + x (R the row), m / 64 = R nx/64 + x/64 and m % 64 = x % 64.
+// ---------------------------------------------------------------------------
+template <typename S>
+struct RowView {
+    using T = Cmp<S>;
+    static constexpr uint32_t PB = 2 * sizeof(S);           // a component pair
+    static constexpr uint32_t DB = 2 * VB * sizeof(S);      // one direction of a storage block
+    static constexpr uint32_t BB = 2 * Q * VB * sizeof(S);  // a storage block
+    static constexpr uint32_t FB = 2 * sizeof(T);           // a pair of a two-component field
+    int ys[3], zs[3];  // y - 1, y, y + 1 and z - 1, z, z + 1, wrapped (wavefront-uniform)
+    uint32_t po[3];    // byte offset within a row of the storage of x + dx, dx = -1, 0, 1
+    uint32_t fo[3];    // byte offset within a row of a field pair of x + dx
+    uint64_t prow, frow;
+    int ny;
+    __device__ __forceinline__ RowView(const DevParams &P, int x, int y, int z) {
+        const int nx = P.nx;
+        ny = P.ny;
+        ys[1] = y;
+        ys[0] = y == 0 ? P.ny - 1 : y - 1;
+        ys[2] = y == P.ny - 1 ? 0 : y + 1;
+        zs[1] = z;
+        zs[0] = z == 0 ? P.nz - 1 : z - 1;
+        zs[2] = z == P.nz - 1 ? 0 : z + 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            int xs = x + k - 1;
+            xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+            po[k] = (uint32_t)(xs / (int)VB) * BB + (uint32_t)(xs % (int)VB) * PB;
+            fo[k] = (uint32_t)xs * FB;
+        }
+        prow = (uint64_t)(nx / (int)VB) * BB;
+        frow = (uint64_t)nx * FB;
+    }
+    __device__ __forceinline__ uint64_t row(int dy, int dz) const {
+        return (uint64_t)(uint32_t)(zs[dz + 1] * ny + ys[dy + 1]);
+    }
+};
+
+// f_i(x) = slot (i, x - c_i), row-aligned addressing
+template <typename S, typename T = Cmp<S>>
+__device__ __forceinline__ void pull_load_rows(const S *__restrict__ fin, const RowView<S> &rv, T (&f)[2][Q]) {
+    const char *base = reinterpret_cast<const char *>(fin);
+    Unroll<Q>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const char *row = base + rv.row(-cy(i), -cz(i)) * rv.prow + (size_t)i * RowView<S>::DB;
+        const Pair<T> v = load_pop(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]), 0);
+        f[0][i] = v.x;
+        f[1][i] = v.y;
+    });
+}
+
+// sum_i f_i(x) of both components, row-aligned addressing
+template <typename S, typename T = Cmp<S>>
+__device__ __forceinline__ void pull_sum_rows(const S *__restrict__ fin, const RowView<S> &rv, T &s0, T &s1) {
+    const char *base = reinterpret_cast<const char *>(fin);
+    s0 = 0;
+    s1 = 0;
+    Unroll<Q>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const char *row = base + rv.row(-cy(i), -cz(i)) * rv.prow + (size_t)i * RowView<S>::DB;
+        const Pair<T> v = load_pop(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]), 0);
+        s0 += v.x;
+        s1 += v.y;
     });
 }
 
@@ -597,19 +690,16 @@ __device__ __forceinline__ void pull_sum(const S *__restrict__ fin, unsigned n, 
 
 // ---------------------------------------------------------------------------
 // The site update shared by both fluid kernels: BGK collision with the
-// velocity shift, Eqs. (2), (3), (6), and streaming with bounce-back, Eqs.
-// (11), (12), (16), for a fluid site x (linear index n) whose populations are
-// in f and whose neighbour sum of Eq. (4) is acc.  A population bounced at a
-// solid neighbour x + c_i is stored as f*_i(x) in slot (opp(i), x + c_i); the
-// moving-wall term of Eq. (16) is subtracted from it by the link kernels
-// (spheres: the link force sum; walls: the wall-plane kernel), which need
-// the density of x and therefore find it in rho_out at boundary sites.
+// velocity shift, Eqs. (2), (3), (6), of a fluid site x (linear index n) whose
+// populations are in f and whose neighbour sum of Eq. (4) is acc; f is
+// replaced by f*.  Streaming, Eqs. (11), (12), is the caller's store of f*_i
+// into slot (i, x); bounce-back at solid neighbours, Eq. (16), is done by the
+// link kernels (spheres: the link force sum; walls: the wall-plane kernel),
+// which need the density of x and find it in rho_out at boundary sites.
 // ---------------------------------------------------------------------------
-template <typename S, typename M, typename T = Cmp<S>>
-__device__ __forceinline__ void collide_and_store(const DevParams &P, T (&f)[2][Q], const T (&acc)[2][3],
-                                                  uint32_t inf, unsigned n, const NbrOffsets &o,
-                                                  S *__restrict__ fout, T *__restrict__ rho_out, double &mass0,
-                                                  double &mass1) {
+template <typename M, typename T>
+__device__ __forceinline__ void collide_site(const DevParams &P, T (&f)[2][Q], const T (&acc)[2][3], uint32_t inf,
+                                             unsigned n, T *__restrict__ rho_out, double &mass0, double &mass1) {
     const T rho0 = (T)P.rho0, irho0 = (T)P.inv_rho0, g = (T)P.g;
     T dr[2], r[2], j[2][3], F[2][3];
     moments(f[0], (T)P.rho_ref[0], dr[0], r[0], j[0][0], j[0][1], j[0][2]);
@@ -628,12 +718,6 @@ __device__ __forceinline__ void collide_and_store(const DevParams &P, T (&f)[2][
         store_pair(rho_out, sidx(0, n), dr[0], dr[1]);
     relax<T, M::eq_order>(f[0], dr[0], r[0], ueq[0][0], ueq[0][1], ueq[0][2], (T)P.inv_tau[0]);
     relax<T, M::eq_order>(f[1], dr[1], r[1], ueq[1][0], ueq[1][1], ueq[1][2], (T)P.inv_tau[1]);
-    Unroll<Q>::run([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        store_pop(fout, pidx(0, i, n), f[0][i], f[1][i]);
-        if (i != 0 && (inf & (1u << i)))
-            store_pop(fout, pidx(0, opp(i), (unsigned)((int)n + o.template off<i>())), f[0][i], f[1][i]);
-    });
 }
 
 // ---------------------------------------------------------------------------

@@ -1,12 +1,12 @@
 // Fluid kernels for gfx950: initial state, densities, virtual fluid,
-// Shan-Chen force, BGK collision with the velocity shift and push streaming
-// with moving bounce-back (Secs. II-IV of Jansen & Harting), plus the field
+// Shan-Chen force, BGK collision with the velocity shift and pull streaming
+// (Secs. II-IV of Jansen & Harting), bounce-back at the walls, plus the field
 // and sum kernels behind the observables.
 //
-// Storage: populations SoA, one plane per component and direction (site
-// index n = (z*ny + y)*nx + x), so a wavefront's 64 lanes touch 64
-// consecutive sites of a plane, in the pull form described in lbm_device.h:
-// slot (i, z) holds what site z + c_i receives in direction i.
+// Storage: populations in storage blocks of 64 consecutive sites (site index
+// n = (z*ny + y)*nx + x), both components of a direction side by side, so a
+// wavefront's 64 lanes read or write one aligned 512-byte run per direction;
+// slot (i, z) holds what site z + c_i receives in direction i (lbm_device.h).
 #include "lbm_handle.h"
 
 namespace lbm {
@@ -87,7 +87,8 @@ __global__ void k_fill_int(int32_t *p, long long n, int32_t v) {
 // on fluid sites (rho = 0 elsewhere), optionally with per-block FP64 partial
 // sums of the fluid mass
 // ---------------------------------------------------------------------------
-template <typename S, typename T = Cmp<S>>
+// ROWS: row-aligned addressing (nx a multiple of 64)
+template <typename S, bool ROWS, typename T = Cmp<S>>
 __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restrict__ f,
                                                    const uint32_t *__restrict__ info, T *__restrict__ rho,
                                                    T *__restrict__ psi, double *__restrict__ partial) {
@@ -95,13 +96,18 @@ __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restr
     double m[2] = {0.0, 0.0};
     unsigned n;
     int x, y, z;
-    if (dense_site(P, n, x, y, z)) {
+    if (ROWS ? dense_site_rows(P, n, x, y, z) : dense_site(P, n, x, y, z)) {
         const bool fluid = site_class(info[n]) == CLS_FLUID;
-        const NbrOffsets o(P, x, y, z);
         const T irho0 = (T)P.inv_rho0;
         T dr[2] = {-(T)P.rho_ref[0], -(T)P.rho_ref[1]};
         if (fluid) {
-            pull_sum(f, n, o, dr[0], dr[1]);
+            if constexpr (ROWS) {
+                const RowView<S> rv(P, x, y, z);
+                pull_sum_rows(f, rv, dr[0], dr[1]);
+            } else {
+                const NbrOffsets o(P, x, y, z);
+                pull_sum(f, n, o, dr[0], dr[1]);
+            }
             m[0] = (double)dr[0] + P.rho_ref[0];
             m[1] = (double)dr[1] + P.rho_ref[1];
         }
@@ -201,10 +207,15 @@ __global__ __launch_bounds__(BLOCK) void k_shell_fill(DevParams P, DevParticles 
     }
 }
 
-// Psi^c(x + c_i) - Psi^c(rho_ref) of the 18 neighbours (pn[c][i-1])
+// Psi^c(x + c_i) - Psi^c(rho_ref) of the 18 neighbours (pn[c][i-1]) and of
+// the site itself (own[c]; on a virtual-fluid site it gives the site's Psi
+// without a second round trip to memory)
 template <typename T>
 __device__ __forceinline__ void load_psi_neighbours(const T *__restrict__ psi, unsigned n, const NbrOffsets &o,
-                                                    T (&pn)[2][Q - 1]) {
+                                                    T (&pn)[2][Q - 1], T (&own)[2]) {
+    const Pair<T> v0 = load_pair(psi, sidx(0, n));
+    own[0] = v0.x;
+    own[1] = v0.y;
     Unroll<Q - 1>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value + 1;
         const unsigned m = (unsigned)((int)n + o.template off<i>());
@@ -214,54 +225,107 @@ __device__ __forceinline__ void load_psi_neighbours(const T *__restrict__ psi, u
     });
 }
 
+// the same with row-aligned addressing
+template <typename S, typename T = Cmp<S>>
+__device__ __forceinline__ void load_psi_neighbours_rows(const T *__restrict__ psi, const RowView<S> &rv,
+                                                         T (&pn)[2][Q - 1], T (&own)[2]) {
+    const char *base = reinterpret_cast<const char *>(psi);
+    const Pair<T> v0 = *reinterpret_cast<const Pair<T> *>(base + rv.row(0, 0) * rv.frow + rv.fo[1]);
+    own[0] = v0.x;
+    own[1] = v0.y;
+    Unroll<Q - 1>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value + 1;
+        const char *row = base + rv.row(cy(i), cz(i)) * rv.frow;
+        const Pair<T> v = *reinterpret_cast<const Pair<T> *>(row + rv.fo[1 + cx(i)]);
+        pn[0][i - 1] = v.x;
+        pn[1][i - 1] = v.y;
+    });
+}
+
+// Shan-Chen force of Eq. (4) on a virtual-fluid site, kept for the particle
+// sums: Psi of the site is its stored deviation plus Psi(rho_ref) = rho0 - psi_e
+template <typename T>
+__device__ __forceinline__ void store_shell_force(const DevParams &P, const T (&own)[2], const T (&acc)[2][3],
+                                                  unsigned n, T *__restrict__ fsc) {
+    const T g = (T)P.g;
+    const T ps0 = own[0] + (T)(P.rho0 - P.psi_e[0]);
+    const T ps1 = own[1] + (T)(P.rho0 - P.psi_e[1]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fsc[vidx(a, n)] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
+}
+
 // ---------------------------------------------------------------------------
 // collide and stream (two-pass variant, second sweep): populations of the
 // site, Psi of the neighbours from the Psi array.  On shell sites it stores
 // the Shan-Chen force for the particle sums.  Every load of a site is issued
 // before its classification is known (all addresses lie in the box), so a
-// wavefront has its whole working set in flight at once.
+// wavefront has its whole working set in flight at once.  Every site stores
+// its 19 own slots (f* on fluid sites, zeros elsewhere) with the wavefront's
+// full lane mask; ROWS selects row-aligned addressing (nx a multiple of 64).
 // ---------------------------------------------------------------------------
-template <typename S, typename M, typename T = Cmp<S>>
+template <typename S, typename M, bool ROWS, typename T = Cmp<S>>
 __global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevParams P, const S *__restrict__ fin,
-                                                                          S *__restrict__ fout, const T *__restrict__ rho,
+                                                                          S *__restrict__ fout,
                                                                           const T *__restrict__ psi,
                                                                           const uint32_t *__restrict__ info,
                                                                           T *__restrict__ fsc) {
     unsigned n;
     int x, y, z;
-    if (!dense_site(P, n, x, y, z)) return;
-    const NbrOffsets o(P, x, y, z);
+    if (!(ROWS ? dense_site_rows(P, n, x, y, z) : dense_site(P, n, x, y, z))) return;
     T f[2][Q];
-    pull_load(fin, n, o, f);
-    T pn[2][Q - 1];
-    load_psi_neighbours(psi, n, o, pn);
+    T pn[2][Q - 1], own_psi[2];
+    if constexpr (ROWS) {
+        const RowView<S> rv(P, x, y, z);
+        pull_load_rows(fin, rv, f);
+        load_psi_neighbours_rows(psi, rv, pn, own_psi);
+    } else {
+        const NbrOffsets o(P, x, y, z);
+        pull_load(fin, n, o, f);
+        load_psi_neighbours(psi, n, o, pn, own_psi);
+    }
     const uint32_t inf = info[n];
     hold_loads(f[0]);
     hold_loads(f[1]);
     hold_loads(pn[0]);
     hold_loads(pn[1]);
+    hold_loads(own_psi);
     const uint32_t cls = site_class(inf);
-    if (cls == CLS_SOLID || cls == CLS_WALL) return;
-    T acc[2][3];
-    psi_force_sum(P, pn, acc);
-    if (cls == CLS_SHELL) {
-        const T g = (T)P.g, rho0 = (T)P.rho0, irho0 = (T)P.inv_rho0;
-        const T ps0 = psi_of(rho[sidx(0, n)] + (T)P.rho_ref[0], rho0, irho0);
-        const T ps1 = psi_of(rho[sidx(1, n)] + (T)P.rho_ref[1], rho0, irho0);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) fsc[vidx(a, n)] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
-        return;
+    if (cls == CLS_FLUID || cls == CLS_SHELL) {
+        T acc[2][3];
+        psi_force_sum(P, pn, acc);
+        if (cls == CLS_SHELL) {
+            store_shell_force(P, own_psi, acc, n, fsc);
+        } else {
+            double m0 = 0.0, m1 = 0.0;
+            collide_site<M>(P, f, acc, inf, n, (T *)nullptr, m0, m1);
+        }
     }
-    double m0 = 0.0, m1 = 0.0;
-    collide_and_store<S, M>(P, f, acc, inf, n, o, fout, (T *)nullptr, m0, m1);
+    if (cls != CLS_FLUID) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[0][i] = f[1][i] = (T)0;
+    }
+    if constexpr (ROWS) {
+        const RowView<S> rv(P, x, y, z);
+        char *own = reinterpret_cast<char *>(fout) + rv.row(0, 0) * rv.prow + rv.po[1];
+        Unroll<Q>::run([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            store_pop(reinterpret_cast<S *>(own + (size_t)i * RowView<S>::DB), 0, f[0][i], f[1][i]);
+        });
+    } else {
+        Unroll<Q>::run([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            store_pop(fout, pidx(0, i, n), f[0][i], f[1][i]);
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------
-// moving-wall term of Eq. (16) on the links into the two walls: for a fluid
-// site x next to a wall and a direction i with x + c_i in the wall, the
-// bounced population in slot (opp(i), x + c_i) loses 6 zeta_i rho^c(x)
-// (c_i . u_wall).  Only the planes next to the walls hold such links; the
-// grid covers both (one thread per site of the two planes).
+// bounce-back at the two walls, Eq. (16): for a fluid site x next to a wall
+// and a direction i with x + c_i in the wall, f*_i(x) (slot (i, x), written by
+// the sweep) is reflected into slot (opp(i), x + c_i) less the moving-wall
+// term 6 zeta_i rho^c(x) (c_i . u_wall).  Only the planes next to the walls
+// hold such links; the grid covers both (one thread per site of the two
+// planes).
 // ---------------------------------------------------------------------------
 template <typename S, typename T = Cmp<S>>
 __global__ __launch_bounds__(BLOCK) void k_wall_links(DevParams P, S *__restrict__ fout, const T *__restrict__ rho,
@@ -294,10 +358,13 @@ __global__ __launch_bounds__(BLOCK) void k_wall_links(DevParams P, S *__restrict
         if (cx(i)) cub += cx(i) * (lo ? P.wall_vel[0][0] : P.wall_vel[1][0]);
         if (cy(i)) cub += cy(i) * (lo ? P.wall_vel[0][1] : P.wall_vel[1][1]);
         if (cz(i)) cub += cz(i) * (lo ? P.wall_vel[0][2] : P.wall_vel[1][2]);
-        if (cub == 0.0) continue;
+        const Pair<T> ff = load_pop(fout, pidx(0, i, n));  // f*_i(x), stored by the sweep in slot (i, x)
+        if (cub == 0.0) {
+            store_pop(fout, pidx(0, opp(i), m), ff.x, ff.y);
+            continue;
+        }
         const T wz = (T)(6.0 * zeta(i) * cub);
         const Pair<T> rr = load_pair(rho, sidx(0, n));
-        const Pair<T> ff = load_pop(fout, pidx(0, opp(i), m));
         store_pop(fout, pidx(0, opp(i), m), ff.x - wz * (rr.x + (T)P.rho_ref[0]), ff.y - wz * (rr.y + (T)P.rho_ref[1]));
     }
 }
@@ -327,8 +394,8 @@ __global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const S *__restri
     if (cls == CLS_SOLID || cls == CLS_WALL) return;
     const NbrOffsets o(P, x, y, z);
     const T g = (T)P.g, rho0 = (T)P.rho0, irho0 = (T)P.inv_rho0;
-    T acc[2][3], pn[2][Q - 1];
-    load_psi_neighbours(psi, n, o, pn);
+    T acc[2][3], pn[2][Q - 1], own_psi[2];
+    load_psi_neighbours(psi, n, o, pn, own_psi);
     psi_force_sum(P, pn, acc);
     if (cls == CLS_SHELL) {
         const T ps0 = psi_of(rho[sidx(0, n)] + (T)P.rho_ref[0], rho0, irho0);
@@ -431,7 +498,11 @@ void launch_density(lb_handle *h, const void *f, bool partial_sums) {
     with_storage(h->prm, [&](auto tag) {
         using S = typename decltype(tag)::type;
         using T = Cmp<S>;
-        k_density<S><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho, (T *)h->psi, part);
+        if (h->prm.nx % (int)VB == 0)
+            k_density<S, true><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho, (T *)h->psi, part);
+        else
+            k_density<S, false><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho, (T *)h->psi,
+                                                             part);
     });
     LB_HIP_CHECK(hipGetLastError());
 }
@@ -455,12 +526,17 @@ void launch_shell_fill(lb_handle *h) {
 
 void launch_collide_stream(lb_handle *h, const void *fin, void *fout) {
     const unsigned nb = dense_blocks(h);
+    const bool rows = h->prm.nx % (int)VB == 0;
     with_storage(h->prm, [&](auto tag) {
         using S = typename decltype(tag)::type;
         using T = Cmp<S>;
         with_model(h->prm, [&](auto m) {
-            k_collide_stream<S, decltype(m)><<<nb, BLOCK, 0, h->stream>>>(
-                h->dp, (const S *)fin, (S *)fout, (const T *)h->rho, (const T *)h->psi, h->info, (T *)h->fsc);
+            if (rows)
+                k_collide_stream<S, decltype(m), true><<<nb, BLOCK, 0, h->stream>>>(
+                    h->dp, (const S *)fin, (S *)fout, (const T *)h->psi, h->info, (T *)h->fsc);
+            else
+                k_collide_stream<S, decltype(m), false><<<nb, BLOCK, 0, h->stream>>>(
+                    h->dp, (const S *)fin, (S *)fout, (const T *)h->psi, h->info, (T *)h->fsc);
         });
     });
     LB_HIP_CHECK(hipGetLastError());

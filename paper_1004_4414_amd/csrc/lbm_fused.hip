@@ -1,7 +1,7 @@
 // Single-sweep fluid step for gfx950: densities, virtual fluid, Shan-Chen
-// force, collision with the velocity shift and push streaming with moving
-// bounce-back for one time step (Secs. II-IV of Jansen & Harting) in one
-// kernel that reads and writes each population once from HBM.
+// force, collision with the velocity shift and pull streaming for one time
+// step (Secs. II-IV of Jansen & Harting) in one kernel that reads and writes
+// each population once from HBM.
 //
 // A workgroup owns a TX x TY column of sites and marches in z over TZ planes.
 // Per plane it runs three stages separated by barriers:
@@ -14,7 +14,8 @@
 //   C (plane z):   each thread re-reads its site's populations (still in
 //      L2 / the Infinity Cache from stage A two planes earlier), forms the
 //      Shan-Chen force from the Psi ring, collides and stores f* in its own
-//      slots (aligned), plus the bounced populations of solid neighbours.
+//      slots (aligned; zeros on non-fluid sites); the link kernels bounce
+//      the populations at solid neighbours afterwards.
 // The halo is recomputed instead of exchanged, so no workgroup waits for
 // another.  Tiles that share an XCD are spatial neighbours (blockIdx is
 // remapped so each XCD walks a contiguous range of tiles), which keeps halo
@@ -152,6 +153,9 @@ __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles
             const uint32_t inf = sm.info[sl_0][as];
             const uint32_t cls = site_class(inf);
             const long long n = ((long long)zc * ny + ys) * nx + xs;
+            T f[2][Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[0][i] = f[1][i] = (T)0;  // the own slots of a non-fluid site
             if (cls == CLS_FLUID || cls == CLS_SHELL) {
                 // Eq. (4) from the Psi ring
                 T pn[2][Q - 1], acc[2][3];
@@ -170,11 +174,14 @@ __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles
                     for (int a = 0; a < 3; ++a) fsc[vidx(a, (unsigned)n)] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
                 } else {
                     const NbrOffsets o(P, xs, ys, zc);
-                    T f[2][Q];
                     pull_load(fin, (unsigned)n, o, f);
-                    collide_and_store<T, M>(P, f, acc, inf, (unsigned)n, o, fout, rho, mass0, mass1);
+                    collide_site<M>(P, f, acc, inf, (unsigned)n, rho, mass0, mass1);
                 }
             }
+            Unroll<Q>::run([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                store_pop(fout, pidx(0, i, (unsigned)n), f[0][i], f[1][i]);
+            });
         }
     }
     // per-block fluid mass (fixed order: lanes, then waves)

@@ -128,11 +128,11 @@ __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &
 // and the Shan-Chen force on its virtual fluid, Eq. (28).
 // The links of sphere p are found from its virtual-fluid sites s: a link
 // (x, i) has x = s - c_i fluid (bit opp(i) of the class word of s clear).
-// The streaming kernel stored the bounced population f*_i(x) in slot
-// (opp(i), s); this kernel completes Eq. (16) there, f_opp(i)(x) = f*_i(x) -
-// w^c with w^c = 6 zeta_i rho^c(x) (c_i . u_b) (each link is visited once, by
-// the sphere that owns s), and adds the momentum given to the sphere,
-// c_i sum_c (2 f*_i - w^c).
+// The sweep stored f*_i(x) in the own slot (i, x); this kernel bounces it
+// back, Eq. (16): slot (opp(i), s), which x reads as direction opp(i) at the
+// next step, receives f_opp(i)(x) = f*_i(x) - w^c with w^c = 6 zeta_i
+// rho^c(x) (c_i . u_b) (each link is visited once, by the sphere that owns
+// s), and the sphere gains the momentum c_i sum_c (2 f*_i - w^c).
 // ---------------------------------------------------------------------------
 // The virtual-fluid sites are taken in chunks of BLOCK, one per thread; the
 // links of a chunk are numbered by a block scan of their counts and then
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
 #pragma unroll
             for (int u = 0; u < LINKS_PER_PASS; ++u) {
                 const Pair<T> rr = load_pair(rho, sidx(0, ml[u]));
-                const Pair<T> ff = load_pop(fout, pidx(0, jl[u], sl[u]));
+                const Pair<T> ff = load_pop(fout, pidx(0, opp(jl[u]), ml[u]));  // f*_i(x) in slot (i, x)
                 r0[u] = rr.x;
                 r1[u] = rr.y;
                 raw0[u] = ff.x;
@@ -240,7 +240,8 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
 #pragma unroll
             for (int u = 0; u < LINKS_PER_PASS; ++u) {
                 if (!ok[u]) continue;
-                // link (x, i) with x = s + c_j fluid, i = opp(j); the stored f*_i(x) sits in slot (j, s)
+                // link (x, i) with x = s + c_j fluid, i = opp(j): f*_i(x), read from slot (i, x), bounces
+                // into slot (j, s), where x reads direction j at the next step
                 const int j = jl[u], i = opp(j);
                 const unsigned ss = sl[u];
                 int x, y, z;
