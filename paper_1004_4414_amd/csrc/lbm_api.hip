@@ -162,14 +162,16 @@ size_t fluid_bytes(const lb_params *p) {
     b += 2 * (size_t)(2 * Q) * Np * ts;  // two population buffers
     b += 8 * Np * tc;                    // densities, Psi, shell force (padded to 4)
     b += 3 * (size_t)N * 4;             // info, owner, stage
-    b += 5 * (size_t)nblk(N) * 8 + 4096;
+    b += 8 * (size_t)nblk(N) * 8 + 4096;
     return b;
 }
 
 size_t particle_bytes(const lb_params *p, int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
     const size_t cells = (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
-    size_t b = (size_t)np * (37 * 8 + (17 + MAX_LUB_CONTACTS) * 4 + MAX_LUB_CONTACTS * 32) + 4 * cells;
+    size_t b = (size_t)np * (37 * 8 + (19 + MAX_LUB_CONTACTS) * 4 + MAX_LUB_CONTACTS * 32) + 4 * cells;
+    const double reach = 2.0 * max_r + std::max(p->lub_hc, 0.0);  // cell list of the pair search
+    if (reach > 0.0) b += 8 * (size_t)(p->nx / reach + 1) * (size_t)(p->ny / reach + 1) * (size_t)(p->nz / reach + 1);
     b += (size_t)np * sc * (4 + 2 * 4);  // virtual-fluid sites, covered and uncovered sites
     return b + 4096;
 }
@@ -428,7 +430,7 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         h->n_partial = (int)nblk(h->N);
         const long long nfused = (long long)((p->nx + h->fused_tx - 1) / h->fused_tx) *
                                  ((p->ny + h->fused_ty - 1) / h->fused_ty) * ((p->nz + h->fused_tz - 1) / h->fused_tz);
-        h->partial = (double *)dev_alloc(h, (size_t)std::max(5LL * h->n_partial, 2 * nfused + 16) * 8);
+        h->partial = (double *)dev_alloc(h, (size_t)std::max(8LL * h->n_partial, 2 * nfused + 16) * 8);
         h->dstate = (DevState *)dev_alloc(h, sizeof(DevState));
         LB_HIP_CHECK(hipMemsetAsync(h->dstate, 0, sizeof(DevState), h->stream));
         LB_HIP_CHECK(hipMemsetAsync(h->f[1], 0, fsz, h->stream));
@@ -599,6 +601,30 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     h->part_allocs.push_back(D.ncont);
     h->part_allocs.push_back(D.cont);
     h->part_allocs.push_back(D.vs);
+    {  // cell list of the pair search: cells at least 2 r_max + h_c wide
+        const double rmax = *std::max_element(rad.begin(), rad.end());
+        const double reach = 2.0 * rmax + std::max(h->prm.lub_hc, 0.0);
+        int pg[3];
+        for (int a = 0; a < 3; ++a) pg[a] = reach > 0.0 ? (int)(L[a] / reach) : 1;
+        if (pg[0] >= 3 && pg[1] >= 3 && pg[2] >= 3 && (long long)pg[0] * pg[1] * pg[2] <= (1 << 22)) {
+            D.pgx = pg[0];
+            D.pgy = pg[1];
+            D.pgz = pg[2];
+            const size_t nc = (size_t)pg[0] * pg[1] * pg[2];
+            D.pc_cnt = (int32_t *)dev_alloc(h, sizeof(int32_t) * nc);
+            D.pc_start = (int32_t *)dev_alloc(h, sizeof(int32_t) * (nc + 1));
+            D.pc_items = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+            D.pc_of = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+            LB_HIP_CHECK(hipMemsetAsync(D.pc_cnt, 0, sizeof(int32_t) * nc, h->stream));
+            h->part_allocs.push_back(D.pc_cnt);
+            h->part_allocs.push_back(D.pc_start);
+            h->part_allocs.push_back(D.pc_items);
+            h->part_allocs.push_back(D.pc_of);
+        } else {
+            D.pgx = D.pgy = D.pgz = 0;
+            D.pc_cnt = D.pc_start = D.pc_items = D.pc_of = nullptr;
+        }
+    }
     D.shell = (int32_t *)dev_alloc(h, sizeof(int32_t) * ssum);
     D.cov = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.unc = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);

@@ -204,6 +204,7 @@ struct DevParams {
 };
 
 // device-resident scalars of a handle
+constexpr int FIN_BLOCKS = 64;  // blocks of the fixed-order mass reduction
 struct DevState {
     double M0[2];      // fluid mass at the start of the first step
     double Mstep[2];   // fluid mass at the start of the current step
@@ -212,6 +213,9 @@ struct DevState {
     int32_t overflow;  // bit 1 shell list, bit 2 event lists, bit 3 a sphere moved >= 1 site, bit 4 contacts
     int32_t pad;
     unsigned long long covered_total, uncovered_total, refill_fallback;
+    double fin_part[2 * FIN_BLOCKS];  // per-block masses of the reduction (scratch)
+    uint32_t fin_count;               // blocks done; back to 0 after every reduction
+    uint32_t pad2;
 };
 
 // per-particle arrays (FP64), each np*3 unless noted
@@ -239,6 +243,11 @@ struct DevParticles {
     double *cont_c, *cont_n;  // coefficient c and unit vector (lower to higher index) of each contact
     double *vs;               // np x 3
     int cgx, cgy, cgz;
+    // cell list of the pair search (cells at least the interaction reach wide,
+    // >= 3 per axis; pgx == 0: all pairs): counts (zero between steps), starts,
+    // sphere indices grouped by cell, and the cell of each sphere
+    int32_t *pc_cnt, *pc_start, *pc_items, *pc_of;
+    int pgx, pgy, pgz;
 };
 constexpr int CELL_SHIFT = 3;  // coarse cells of 8^3 sites
 constexpr int MAX_LUB_CONTACTS = 32;
@@ -344,6 +353,29 @@ __device__ __forceinline__ bool inside_sphere(int x, int y, int z, const long lo
     return d2 < r2q;
 }
 
+// The same test on unwrapped box coordinates u (u = x mod L): equal to
+// inside_sphere when every coordinate of the box lies within half a period
+// of the centre, which near_box checks once per box.
+__device__ __forceinline__ bool inside_unwrapped(const int u[3], const long long cq[3], long long r2q) {
+    long long d2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long d = ((long long)u[a] << 20) - cq[a];
+        d2 += d * d;
+    }
+    return d2 < r2q;
+}
+__device__ __forceinline__ bool near_box(const int lo[3], const int ext[3], const long long cq[3], const DevParams &P) {
+    const int L[3] = {P.nx, P.ny, P.nz};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long h = ((long long)L[a] << 20) / 2;
+        ok = ok && (((long long)lo[a] << 20) - cq[a] > -h) && (((long long)(lo[a] + ext[a] - 1) << 20) - cq[a] <= h);
+    }
+    return ok;
+}
+
 // inclusive integer bounding box that contains every site inside the sphere;
 // empty (hi < lo) for a centre that is not finite or far outside the box
 __device__ __forceinline__ void sphere_box(const double R[3], double r, int lo[3], int hi[3]) {
@@ -376,14 +408,20 @@ __device__ __forceinline__ void site_xyz(long long n, const DevParams &P, int &x
 }
 
 __device__ __forceinline__ long long site_of(int x, int y, int z, const DevParams &P) {
-    return ((long long)z * P.ny + y) * P.nx + x;
+    return (long long)(((unsigned)z * (unsigned)P.ny + (unsigned)y) * (unsigned)P.nx + (unsigned)x);  // < N < 2^32
 }
 
 // the site's class word from the owner map: bounce-back directions of a
 // fluid site, or shell / interior / wall for the others
+__device__ __forceinline__ uint32_t compute_info_at(long long n, int x, int y, int z, const DevParams &P,
+                                                    const int32_t *__restrict__ owner);
 __device__ __forceinline__ uint32_t compute_info(long long n, const DevParams &P, const int32_t *__restrict__ owner) {
     int x, y, z;
     site_xyz(n, P, x, y, z);
+    return compute_info_at(n, x, y, z, P, owner);
+}
+__device__ __forceinline__ uint32_t compute_info_at(long long n, int x, int y, int z, const DevParams &P,
+                                                    const int32_t *__restrict__ owner) {
     const int32_t own = owner[n];
     if (own == OWN_WALL_LO || own == OWN_WALL_HI) return (uint32_t)CLS_WALL << CLS_SHIFT;
     uint32_t mask = 0;

@@ -84,15 +84,15 @@ __global__ void k_fill_int(int32_t *p, long long n, int32_t v) {
 
 // ---------------------------------------------------------------------------
 // density deviations rho^c - rho_ref^c = sum_i d_i^c and Psi^c - Psi^c(rho_ref)
-// on fluid sites (rho = 0 elsewhere), optionally with per-block FP64 partial
-// sums of the fluid mass
+// on fluid sites (rho = 0 elsewhere), optionally with per-wavefront FP64
+// partial sums of the fluid mass (a shuffle tree, no barrier, so no
+// wavefront waits for the others of its block)
 // ---------------------------------------------------------------------------
 // ROWS: row-aligned addressing (nx a multiple of 64)
 template <typename S, bool ROWS, typename T = Cmp<S>>
 __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restrict__ f,
                                                    const uint32_t *__restrict__ info, T *__restrict__ rho,
                                                    T *__restrict__ psi, double *__restrict__ partial) {
-    __shared__ double lds[2 * (BLOCK / 64)];
     double m[2] = {0.0, 0.0};
     unsigned n;
     int x, y, z;
@@ -115,30 +115,38 @@ __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restr
         store_pair(psi, sidx(0, n), psi_dev(dr[0], (T)P.psi_e[0], irho0), psi_dev(dr[1], (T)P.psi_e[1], irho0));
     }
     if (partial) {
-        block_sum<2>(m, lds);
-        if (threadIdx.x == 0) {
-            partial[2 * blockIdx.x + 0] = m[0];
-            partial[2 * blockIdx.x + 1] = m[1];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            for (int off = 32; off > 0; off >>= 1) m[c] += __shfl_down(m[c], off, 64);
+        if ((threadIdx.x & 63) == 0) {
+            const unsigned w = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+            partial[2 * w + 0] = m[0];
+            partial[2 * w + 1] = m[1];
         }
     }
 }
 
 // fixed-order sum of the per-block masses: M(t), baseline M(0), sentinel.
-// One block of FIN_THREADS; each thread keeps 8 independent partial sums so
-// that its loads are in flight together, then a fixed tree combines them.
-constexpr int FIN_THREADS = 1024;
+// FIN_BLOCKS blocks each sum a contiguous range of the partials (8
+// independent sums per thread, then a fixed tree); the last block to finish
+// (an integer counter) sums their results in block order and resets the
+// counter, so the total does not depend on which block finishes last.
+constexpr int FIN_THREADS = 256;
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__restrict__ partial, int nb,
                                                                DevState *st) {
     __shared__ double lds[2][FIN_THREADS];
+    __shared__ int last;
     const int t = threadIdx.x;
+    const int chunk = (nb + FIN_BLOCKS - 1) / FIN_BLOCKS;
+    const int b_lo = blockIdx.x * chunk, b_hi = min(nb, b_lo + chunk);
     double a[2][8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) a[0][j] = a[1][j] = 0.0;
-    for (int b0 = t; b0 < nb; b0 += 8 * FIN_THREADS) {
+    for (int b0 = b_lo + t; b0 < b_hi; b0 += 8 * FIN_THREADS) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int b = b0 + j * FIN_THREADS;
-            if (b < nb) {
+            if (b < b_hi) {
                 a[0][j] += partial[2 * b];
                 a[1][j] += partial[2 * b + 1];
             }
@@ -156,6 +164,25 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
         __syncthreads();
     }
     if (t == 0) {
+        st->fin_part[2 * blockIdx.x] = lds[0][0];
+        st->fin_part[2 * blockIdx.x + 1] = lds[1][0];
+        __threadfence();
+        last = atomicAdd(&st->fin_count, 1u) == FIN_BLOCKS - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const volatile double *fp = st->fin_part;
+    for (int c = 0; c < 2; ++c) lds[c][t] = t < FIN_BLOCKS ? fp[2 * t + c] : 0.0;
+    __syncthreads();
+    for (int s = FIN_BLOCKS / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            lds[0][t] += lds[0][t + s];
+            lds[1][t] += lds[1][t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
         const double m0 = lds[0][0], m1 = lds[1][0];
         st->Mstep[0] = m0;
         st->Mstep[1] = m1;
@@ -165,6 +192,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
             st->have_M0 = 1;
         }
         if (!isfinite(m0) || !isfinite(m1)) st->unstable = 1;
+        st->fin_count = 0;
     }
 }
 
@@ -173,26 +201,29 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
 // of rho^c over its fluid 18-neighbours plus |colour| on the preferred
 // component; written into the density-deviation and Psi arrays in place.
 // ---------------------------------------------------------------------------
+constexpr int SHELL_THREADS = 64;  // one wavefront per sphere (a few hundred shell sites each)
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_shell_fill(DevParams P, DevParticles D, const uint32_t *__restrict__ info,
+__global__ __launch_bounds__(SHELL_THREADS) void k_shell_fill(DevParams P, DevParticles D, const uint32_t *__restrict__ info,
                                                       T *__restrict__ rho, T *__restrict__ psi) {
     const int p = blockIdx.x;
     const int cnt = min(D.shell_cnt[p], D.shell_cap[p]), off = D.shell_off[p];
     const double col = D.color[p];
     const T irho0 = (T)P.inv_rho0;
-    for (int k = threadIdx.x; k < cnt; k += BLOCK) {
+    for (int k = threadIdx.x; k < cnt; k += SHELL_THREADS) {
         const long long s = D.shell[off + k];
         int x, y, z;
         site_xyz(s, P, x, y, z);
-        // every neighbour's density is loaded (the addresses are in the box)
-        // and masked afterwards, so the loads of a site are in flight together
+        // the class word of a shell site flags its non-fluid neighbours; every
+        // neighbour's density is loaded (the addresses are in the box) and
+        // masked afterwards, so the loads of a site are in flight together
+        const uint32_t inf = info[s];
         T sum0 = 0, sum1 = 0;
         int nf = 0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const unsigned m =
                 (unsigned)site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
-            const bool fl = site_class(info[m]) == CLS_FLUID;
+            const bool fl = !((inf >> i) & 1u);
             const Pair<T> a = load_pair(rho, sidx(0, m));
             const T a0 = a.x, a1 = a.y;
             sum0 += fl ? a0 : (T)0;
@@ -507,20 +538,22 @@ void launch_density(lb_handle *h, const void *f, bool partial_sums) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
-void launch_finalize_mass(lb_handle *h) { launch_finalize_mass_n(h, (int)dense_blocks(h)); }
+// the density pass leaves one partial mass per wavefront
+void launch_finalize_mass(lb_handle *h) { launch_finalize_mass_n(h, (int)dense_blocks(h) * (BLOCK / 64)); }
 
 void launch_finalize_mass_n(lb_handle *h, int nb) {
-    k_finalize_mass<<<1, FIN_THREADS, 0, h->stream>>>(h->partial, nb, h->dstate);
+    k_finalize_mass<<<FIN_BLOCKS, FIN_THREADS, 0, h->stream>>>(h->partial, nb, h->dstate);
     LB_HIP_CHECK(hipGetLastError());
 }
 
 void launch_shell_fill(lb_handle *h) {
     if (h->np == 0) return;
     if (h->prm.precision == LB_FP64)
-        k_shell_fill<double><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->info, (double *)h->rho,
+        k_shell_fill<double><<<h->np, SHELL_THREADS, 0, h->stream>>>(h->dp, h->dpart, h->info, (double *)h->rho,
                                                              (double *)h->psi);
     else
-        k_shell_fill<float><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->info, (float *)h->rho, (float *)h->psi);
+        k_shell_fill<float><<<h->np, SHELL_THREADS, 0, h->stream>>>(h->dp, h->dpart, h->info, (float *)h->rho,
+                                                                    (float *)h->psi);
     LB_HIP_CHECK(hipGetLastError());
 }
 

@@ -31,6 +31,71 @@ __device__ __forceinline__ void box_site(int k, const int lo[3], const int ext[3
     z = wrapany(lo[2] + dz, P.nz);
 }
 
+// The sites of a box lo[a] .. lo[a] + ext[a] - 1, numbered k = dx + ext0 (dy
+// + ext1 dz), without integer division: the quotients come from FP32
+// reciprocals with one correction step (exact below 2^24 sites) and the
+// periodic wrap is a conditional add, valid when the box lies within one
+// period on either side of [0, L).  Other boxes (tiny lattices) fall back to
+// box_site.  `fast` is uniform over the block.
+struct BoxWalk {
+    int lo[3], ext[3], L[3];
+    int e01;
+    float r0, r01;
+    bool fast;
+    __device__ __forceinline__ BoxWalk(const DevParams &P, const int lo_[3], const int ext_[3]) {
+        L[0] = P.nx;
+        L[1] = P.ny;
+        L[2] = P.nz;
+        fast = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = lo_[a];
+            ext[a] = ext_[a];
+            fast = fast && lo[a] >= -L[a] && lo[a] + ext[a] <= 2 * L[a];
+        }
+        e01 = ext[0] * ext[1];
+        fast = fast && (long long)e01 * ext[2] < (1 << 24);
+        r0 = ext[0] > 0 ? 1.0f / (float)ext[0] : 0.0f;
+        r01 = e01 > 0 ? 1.0f / (float)e01 : 0.0f;
+    }
+    __device__ __forceinline__ int size() const { return e01 * ext[2]; }
+    static __device__ __forceinline__ int qdiv(int k, int d, float r, int &rem) {
+        int q = (int)((float)k * r);
+        int m = k - q * d;
+        if (m < 0) {
+            --q;
+            m += d;
+        } else if (m >= d) {
+            ++q;
+            m -= d;
+        }
+        rem = m;
+        return q;
+    }
+    // unwrapped coordinates u and wrapped site coordinates of site k
+    __device__ __forceinline__ void site(int k, const DevParams &P, int u[3], int &x, int &y, int &z) const {
+        if (!fast) {
+            const int dx = k % ext[0], t = k / ext[0];
+            u[0] = lo[0] + dx;
+            u[1] = lo[1] + t % ext[1];
+            u[2] = lo[2] + t / ext[1];
+            x = wrapany(u[0], L[0]);
+            y = wrapany(u[1], L[1]);
+            z = wrapany(u[2], L[2]);
+            return;
+        }
+        int rem, dx;
+        const int dz = qdiv(k, e01, r01, rem);
+        const int dy = qdiv(rem, ext[0], r0, dx);
+        u[0] = lo[0] + dx;
+        u[1] = lo[1] + dy;
+        u[2] = lo[2] + dz;
+        x = wrapc(u[0], L[0]);
+        y = wrapc(u[1], L[1]);
+        z = wrapc(u[2], L[2]);
+    }
+};
+
 // box holding the sphere at its previous and its new position (the new one
 // unwrapped next to the previous), optionally grown by g sites
 __device__ __forceinline__ void union_box(const DevParams &P, const DevParticles &D, int p, int g, int lo[3],
@@ -355,6 +420,190 @@ __global__ __launch_bounds__(BLOCK) void k_pair_forces(DevParams P, DevParticles
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same pair forces from a cell list (cells at least 2 r_max + h_c wide, at
+// least 3 per axis, so every partner within reach lies in the 27 cells around
+// a sphere and no cell is visited twice).  The list is a counting sort with
+// integer atomics; the candidates of a sphere are sorted by index before use,
+// so contacts are listed in index order and the force sums run in a fixed
+// order whatever the order inside a cell.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pair_cell(const DevParams &P, const DevParticles &D, int p) {
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    const int g[3] = {D.pgx, D.pgy, D.pgz};
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double r = D.R[3 * p + a];
+        int k = isfinite(r) ? (int)(r / L[a] * g[a]) : 0;
+        c[a] = k < 0 ? 0 : (k >= g[a] ? g[a] - 1 : k);
+    }
+    return (c[2] * g[1] + c[1]) * g[0] + c[0];
+}
+
+__global__ void k_pcell_count(DevParams P, DevParticles D) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= P.np) return;
+    const int c = pair_cell(P, D, p);
+    D.pc_of[p] = c;
+    atomicAdd(&D.pc_cnt[c], 1);
+}
+
+// exclusive scan of the cell counts (one block: contiguous runs per thread,
+// then a scan of the run totals)
+constexpr int PCS_THREADS = 1024;
+__global__ __launch_bounds__(PCS_THREADS) void k_pcell_scan(DevParticles D) {
+    __shared__ int tot[PCS_THREADS];
+    const int nc = D.pgx * D.pgy * D.pgz;
+    const int t = threadIdx.x;
+    const int run = (nc + PCS_THREADS - 1) / PCS_THREADS;
+    const int a = min(nc, t * run), b = min(nc, a + run);
+    int sum = 0;
+    for (int k = a; k < b; ++k) sum += D.pc_cnt[k];
+    tot[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < PCS_THREADS; o <<= 1) {
+        const int v = t >= o ? tot[t - o] : 0;
+        __syncthreads();
+        tot[t] += v;
+        __syncthreads();
+    }
+    int base = tot[t] - sum;
+    for (int k = a; k < b; ++k) {
+        D.pc_start[k] = base;
+        base += D.pc_cnt[k];
+    }
+    if (t == PCS_THREADS - 1) D.pc_start[nc] = tot[t];
+}
+
+// scatter into the cells; counting down leaves the counts at zero for the next step
+__global__ void k_pcell_fill(DevParams P, DevParticles D) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= P.np) return;
+    const int c = D.pc_of[p];
+    const int k = atomicSub(&D.pc_cnt[c], 1) - 1;
+    D.pc_items[D.pc_start[c] + k] = p;
+}
+
+constexpr int PAIR_MAX_CAND = 512;  // partners within the 27 cells of one sphere
+__global__ __launch_bounds__(64) void k_pair_forces_cells(DevParams P, DevParticles D, DevState *st) {
+    __shared__ int cand[PAIR_MAX_CAND];
+    __shared__ int cstart[27], ccount[27], coff[28];
+    const int p = blockIdx.x, t = threadIdx.x;
+    double Rp[3];
+    load3(D.R, p, Rp);
+    const double rp = D.rad[p];
+    const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
+    double nu = 0.0;  // mean kinematic viscosity of the two components
+    for (int c = 0; c < 2; ++c) nu += (1.0 / 3.0) * (P.tau[c] - 0.5);
+    nu /= 2.0;
+    // the 27 cells around the sphere's cell and their runs
+    const int c0 = D.pc_of[p];
+    const int gx = D.pgx, gy = D.pgy, gz = D.pgz;
+    if (t < 27) {
+        const int cx0 = c0 % gx, cy0 = (c0 / gx) % gy, cz0 = c0 / (gx * gy);
+        const int ux = wrapc(cx0 + t % 3 - 1, gx), uy = wrapc(cy0 + (t / 3) % 3 - 1, gy), uz = wrapc(cz0 + t / 9 - 1, gz);
+        const int c = (uz * gy + uy) * gx + ux;
+        cstart[t] = D.pc_start[c];
+        ccount[t] = D.pc_start[c + 1] - D.pc_start[c];
+    }
+    __syncthreads();
+    if (t == 0) {
+        coff[0] = 0;
+        for (int k = 0; k < 27; ++k) coff[k + 1] = coff[k] + ccount[k];
+    }
+    __syncthreads();
+    const int K = coff[27];
+    if (K > PAIR_MAX_CAND) {
+        if (t == 0) {
+            D.ncont[p] = 0;
+            atomicOr(&st->overflow, 16);
+        }
+        return;
+    }
+    for (int k = 0; k < 27; ++k)
+        for (int j = t; j < ccount[k]; j += 64) cand[coff[k] + j] = D.pc_items[cstart[k] + j];
+    // pad to a power of two and sort ascending (bitonic)
+    int n2 = 1;
+    while (n2 < K) n2 <<= 1;
+    for (int j = K + t; j < n2; j += 64) cand[j] = 0x7fffffff;
+    __syncthreads();
+    for (int size = 2; size <= n2; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int j = t; j < n2; j += 64) {
+                const int partner = j ^ stride;
+                if (partner > j) {
+                    const bool up = (j & size) == 0;
+                    const int a = cand[j], b = cand[partner];
+                    if ((a > b) == up) {
+                        cand[j] = b;
+                        cand[partner] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    double F[3] = {0, 0, 0};
+    int ncont = 0;
+    for (int j0 = 0; j0 < K; j0 += 64) {
+        const int j = j0 + t;
+        const int q = j < K ? cand[j] : -1;
+        bool lub = false;
+        if (q >= 0 && q != p) {
+            double d[3], dist2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = minimg(D.R[3 * q + a] - Rp[a], L[a]);
+                dist2 += d[a] * d[a];
+            }
+            const double rsum = rp + D.rad[q];
+            const double reach = rsum + (P.lub_hc > 0.0 ? P.lub_hc : 0.0);
+            if (dist2 < reach * reach) {
+                const double dist = sqrt(dist2);
+                if (dist > 0.0) {
+                    if (dist < rsum) {
+                        const double fh = 2.5 * P.k_hertz * pow(rsum - dist, 1.5);
+                        for (int a = 0; a < 3; ++a) F[a] -= fh * d[a] / dist;
+                    }
+                    lub = P.lub_hc > 0.0 && dist - rsum < P.lub_hc;
+                }
+            }
+        }
+        const unsigned long long ball = __ballot(lub);
+        const int slot = ncont + __popcll(ball & ((t == 0) ? 0ull : (~0ull >> (64 - t))));
+        ncont += __popcll(ball);
+        if (lub && slot < MAX_LUB_CONTACTS) {
+            // the pair's geometry as both ends compute it: from the lower index to the higher
+            const int lo = min(p, q), hi = max(p, q);
+            double d[3], dist2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = minimg(D.R[3 * hi + a] - D.R[3 * lo + a], L[a]);
+                dist2 += d[a] * d[a];
+            }
+            const double dist = sqrt(dist2);
+            const double rsum = D.rad[lo] + D.rad[hi];
+            const double h = dist - rsum;
+            const double hh = h < P.lub_hmin ? P.lub_hmin : h;
+            const double ared = D.rad[lo] * D.rad[hi] / rsum;
+            const size_t e = (size_t)p * MAX_LUB_CONTACTS + slot;
+            D.cont[e] = q;
+            D.cont_c[e] = 6.0 * M_PI * nu * P.rho0 * ared * ared * (1.0 / hh - 1.0 / P.lub_hc);
+            for (int a = 0; a < 3; ++a) D.cont_n[3 * e + a] = d[a] / dist;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        for (int off = 32; off > 0; off >>= 1) F[a] += __shfl_down(F[a], off, 64);
+    if (t == 0) {
+        D.ncont[p] = min(ncont, MAX_LUB_CONTACTS);
+        if (ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
+        for (int a = 0; a < 3; ++a) {
+            D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + F[a];
+            D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
+            D.vs[3 * p + a] = D.U[3 * p + a] + (D.prescribed[p] ? 0.0 : D.Ftot[3 * p + a] / D.mass[p]);
+        }
+    }
+}
+
 // lubrication impulses, then the leap-frog of Eqs. (9), (10):
 // U(t+1/2) = v* + impulses / m, R(t+1) = R(t) + U, Omega(t+1/2) = Omega(t-1/2)
 // + D/J; the pending impulses are consumed
@@ -409,11 +658,14 @@ __global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D,
     for (int a = 0; a < 3; ++a) cq[a] = fixed20(D.R[3 * p + a]);
     const long long rq = fixed20(D.rad[p]);
     const long long r2q = rq * rq;
-    const int V = ext[0] * ext[1] * ext[2];
+    const BoxWalk bw(P, lo, ext);
+    const bool near = near_box(lo, ext, cq, P);
+    const int V = bw.size();
     for (int k = threadIdx.x; k < V; k += BLOCK) {
-        int x, y, z;
-        box_site(k, lo, ext, P, x, y, z);
-        if (inside_sphere(x, y, z, cq, r2q, P.nx, P.ny, P.nz)) atomicMin(&stage[site_of(x, y, z, P)], p);
+        int u[3], x, y, z;
+        bw.site(k, P, u, x, y, z);
+        const bool in = near ? inside_unwrapped(u, cq, r2q) : inside_sphere(x, y, z, cq, r2q, P.nx, P.ny, P.nz);
+        if (in) atomicMin(&stage[site_of(x, y, z, P)], p);
     }
 }
 
@@ -425,34 +677,28 @@ __global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles 
     const int p = blockIdx.x;
     int lo[3], ext[3];
     union_box(P, D, p, 0, lo, ext);
-    const int V = ext[0] * ext[1] * ext[2];
+    const BoxWalk bw(P, lo, ext);
+    const int V = bw.size();
     const int off = D.ev_off[p], cap = D.ev_cap[p];
     int ncov = 0, nunc = 0;
+    int moved = 0;  // a site passing between two spheres is no event but changes both maps
     for (int start = 0; start < V; start += BLOCK) {
         const int k = start + threadIdx.x;
         bool cov = false, unc = false;
         long long n = 0;
         if (k < V) {
-            int x, y, z;
-            box_site(k, lo, ext, P, x, y, z);
+            int u[3], x, y, z;
+            bw.site(k, P, u, x, y, z);
             n = site_of(x, y, z, P);
             const int32_t o = owner[n], s = stage[n];
             cov = (o == OWN_FLUID && s == p);
             unc = (o == p && s == STAGE_NONE);
+            moved |= (o >= 0 && o != p && s == p) || (o == p && s != STAGE_NONE && s != p);
         }
         int slot = block_compact(cov, ncov, lds);
         if (cov && slot < cap) D.cov[off + slot] = (int32_t)n;
         slot = block_compact(unc, nunc, lds);
         if (unc && slot < cap) D.unc[off + slot] = (int32_t)n;
-    }
-    // a site passing between two spheres is no event but changes both maps
-    int moved = 0;
-    for (int k = threadIdx.x; k < V; k += BLOCK) {
-        int x, y, z;
-        box_site(k, lo, ext, P, x, y, z);
-        const long long n = site_of(x, y, z, P);
-        const int32_t o = owner[n], s = stage[n];
-        moved |= (o >= 0 && o != p && s == p) || (o == p && s != STAGE_NONE && s != p);
     }
     const bool changed = __syncthreads_or(moved) != 0 || ncov > 0 || nunc > 0;
     if (changed) {
@@ -599,10 +845,11 @@ __global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles 
     if (!full && !D.changed[p]) return;
     int lo[3], ext[3];
     union_box(P, D, p, 0, lo, ext);
-    const int V = ext[0] * ext[1] * ext[2];
+    const BoxWalk bw(P, lo, ext);
+    const int V = bw.size();
     for (int k = threadIdx.x; k < V; k += BLOCK) {
-        int x, y, z;
-        box_site(k, lo, ext, P, x, y, z);
+        int u[3], x, y, z;
+        bw.site(k, P, u, x, y, z);
         const long long n = site_of(x, y, z, P);
         const int32_t s = stage[n];
         owner[n] = s == STAGE_NONE ? OWN_FLUID : s;
@@ -617,19 +864,21 @@ __global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D,
     int V;
     if (D.changed[p]) {
         union_box(P, D, p, 1, lo, ext);
-        V = ext[0] * ext[1] * ext[2];
+        const BoxWalk bw(P, lo, ext);
+        V = bw.size();
         for (int k = threadIdx.x; k < V; k += BLOCK) {
-            int x, y, z;
-            box_site(k, lo, ext, P, x, y, z);
+            int u[3], x, y, z;
+            bw.site(k, P, u, x, y, z);
             const long long n = site_of(x, y, z, P);
-            info[n] = compute_info(n, P, owner);
+            info[n] = compute_info_at(n, x, y, z, P, owner);
         }
     }
     new_box(P, D, p, lo, ext);
-    V = ext[0] * ext[1] * ext[2];
+    const BoxWalk bw(P, lo, ext);
+    V = bw.size();
     for (int k = threadIdx.x; k < V; k += BLOCK) {
-        int x, y, z;
-        box_site(k, lo, ext, P, x, y, z);
+        int u[3], x, y, z;
+        bw.site(k, P, u, x, y, z);
         stage[site_of(x, y, z, P)] = STAGE_NONE;
     }
 }
@@ -660,7 +909,8 @@ __global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles
         lb[threadIdx.x] = lo[threadIdx.x];
         lb[3 + threadIdx.x] = ext[threadIdx.x];
     }
-    const int V = ext[0] * ext[1] * ext[2];
+    const BoxWalk bw(P, lo, ext);
+    const int V = bw.size();
     const int soff = D.shell_off[p], scap = D.shell_cap[p];
     int nshell = 0, nlink = 0;
     for (int start = 0; start < V; start += BLOCK) {
@@ -668,8 +918,8 @@ __global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles
         bool sh = false;
         long long n = 0;
         if (k < V) {
-            int x, y, z;
-            box_site(k, lo, ext, P, x, y, z);
+            int u[3], x, y, z;
+            bw.site(k, P, u, x, y, z);
             n = site_of(x, y, z, P);
             const uint32_t inf = info[n];
             sh = owner[n] == p && site_class(inf) == CLS_SHELL;
@@ -703,7 +953,15 @@ void launch_particle_fluid_force(lb_handle *h, void *fout) {
 
 void launch_pair_forces(lb_handle *h) {
     if (!h->np) return;
-    k_pair_forces<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->dstate);
+    if (h->dpart.pgx > 0) {
+        const unsigned nb = (unsigned)((h->np + BLOCK - 1) / BLOCK);
+        k_pcell_count<<<nb, BLOCK, 0, h->stream>>>(h->dp, h->dpart);
+        k_pcell_scan<<<1, PCS_THREADS, 0, h->stream>>>(h->dpart);
+        k_pcell_fill<<<nb, BLOCK, 0, h->stream>>>(h->dp, h->dpart);
+        k_pair_forces_cells<<<h->np, 64, 0, h->stream>>>(h->dp, h->dpart, h->dstate);
+    } else {
+        k_pair_forces<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->dstate);
+    }
     LB_HIP_CHECK(hipGetLastError());
 }
 
