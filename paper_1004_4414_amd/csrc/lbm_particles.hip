@@ -695,10 +695,13 @@ __global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles 
             unc = (o == p && s == STAGE_NONE);
             moved |= (o >= 0 && o != p && s == p) || (o == p && s != STAGE_NONE && s != p);
         }
-        int slot = block_compact(cov, ncov, lds);
-        if (cov && slot < cap) D.cov[off + slot] = (int32_t)n;
-        slot = block_compact(unc, nunc, lds);
-        if (unc && slot < cap) D.unc[off + slot] = (int32_t)n;
+        // events are rare: most chunks have none and skip the two compactions
+        if (__syncthreads_or(cov || unc)) {
+            int slot = block_compact(cov, ncov, lds);
+            if (cov && slot < cap) D.cov[off + slot] = (int32_t)n;
+            slot = block_compact(unc, nunc, lds);
+            if (unc && slot < cap) D.unc[off + slot] = (int32_t)n;
+        }
     }
     const bool changed = __syncthreads_or(moved) != 0 || ncov > 0 || nunc > 0;
     if (changed) {

@@ -419,3 +419,28 @@ def test_bijel256_full_size_crops_and_invariants():
             Pr = ref.particles()
             for key in ("Ffluid", "Tfluid"):
                 assert np.abs(P1[key][q] - Pr[key][k]).max() <= 1e-5 * scale, key
+
+
+@pytest.mark.parametrize("edge", [40, 18])
+def test_lubrication_cluster_both_pair_searches(edge):
+    """A cluster of four spheres (r = 3) with gaps of 0.3 < h_c closing in:
+    lubrication contacts and pair impulses from the start.  At edge 40 the
+    pair search uses the cell list (5 cells per axis), at edge 18 all pairs;
+    both are compared with the oracle end to end in FP64."""
+    p = W.params(nx=edge, ny=edge, nz=edge, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=21)
+    c = edge / 2.0
+    s = 6.3 / 2.0
+    pos = [[c - s, c - s * 0.6, c], [c + s, c - s * 0.6, c], [c, c + s * 1.1, c], [c, c, c + 6.3]]
+    vel = [[0.01, 0.0, 0.0], [-0.01, 0.0, 0.0], [0.0, -0.01, 0.0], [0.0, 0.0, -0.01]]
+    parts = W.make_particles(pos, 3.0, vel=vel, density=1.0)
+    gpu = lbm().Lattice(p, precision="fp64")
+    assert gpu.add_particles(parts, check=False) == 0
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    gpu.step(40)
+    ref.step(40)
+    compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
+    compare_bookkeeping(gpu, ref)
+    Pg, Pr = gpu.particles(), ref.particles()
+    for k in ("R", "U", "W", "Ffluid", "Tfluid", "P", "PT"):
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
