@@ -305,8 +305,7 @@ void enqueue_step(lb_handle *h) {
         launch_particle_fluid_force(h, fout);
         launch_pair_forces(h);
         launch_integrate(h);
-        launch_fill_int(h, h->dpart.dirty, (long long)h->dpart.cgx * h->dpart.cgy * h->dpart.cgz, 0);
-        launch_map_mark(h, true);
+        launch_map_mark(h, true);  // also clears the dirty cells
         launch_map_events(h);
         launch_cover_refill(h, fout);
         launch_map_commit(h, false);

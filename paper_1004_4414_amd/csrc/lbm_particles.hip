@@ -652,6 +652,11 @@ __global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage) {
     const int p = blockIdx.x;
+    {  // the blocks also clear the coarse dirty cells of the previous step, a slice each
+        const int ncell = D.cgx * D.cgy * D.cgz;
+        const int per = (ncell + (int)gridDim.x - 1) / (int)gridDim.x;
+        for (int c = p * per + threadIdx.x; c < min(ncell, (p + 1) * per); c += BLOCK) D.dirty[c] = 0;
+    }
     int lo[3], ext[3];
     new_box(P, D, p, lo, ext);
     long long cq[3];
@@ -954,9 +959,13 @@ void launch_particle_fluid_force(lb_handle *h, void *fout) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
+// the cell list pays off from about a thousand spheres; fewer take the
+// all-pairs kernel (one launch instead of four)
+constexpr int PAIR_CELLS_MIN_SPHERES = 1024;
+
 void launch_pair_forces(lb_handle *h) {
     if (!h->np) return;
-    if (h->dpart.pgx > 0) {
+    if (h->dpart.pgx > 0 && h->np >= PAIR_CELLS_MIN_SPHERES) {
         const unsigned nb = (unsigned)((h->np + BLOCK - 1) / BLOCK);
         k_pcell_count<<<nb, BLOCK, 0, h->stream>>>(h->dp, h->dpart);
         k_pcell_scan<<<1, PCS_THREADS, 0, h->stream>>>(h->dpart);

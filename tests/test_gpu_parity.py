@@ -422,11 +422,10 @@ def test_bijel256_full_size_crops_and_invariants():
 
 
 @pytest.mark.parametrize("edge", [40, 18])
-def test_lubrication_cluster_both_pair_searches(edge):
+def test_lubrication_cluster(edge):
     """A cluster of four spheres (r = 3) with gaps of 0.3 < h_c closing in:
-    lubrication contacts and pair impulses from the start.  At edge 40 the
-    pair search uses the cell list (5 cells per axis), at edge 18 all pairs;
-    both are compared with the oracle end to end in FP64."""
+    lubrication contacts and pair impulses from the start, compared with the
+    oracle end to end in FP64 (the all-pairs search)."""
     p = W.params(nx=edge, ny=edge, nz=edge, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=21)
     c = edge / 2.0
     s = 6.3 / 2.0
@@ -439,6 +438,27 @@ def test_lubrication_cluster_both_pair_searches(edge):
     assert ref.add_particles(parts) == 0
     gpu.step(40)
     ref.step(40)
+    compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
+    compare_bookkeeping(gpu, ref)
+    Pg, Pr = gpu.particles(), ref.particles()
+    for k in ("R", "U", "W", "Ffluid", "Tfluid", "P", "PT"):
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+
+
+def test_dense_suspension_cell_list_pair_search():
+    """1200 small spheres (r = 1.5, gaps from 0.15) in a 64^3 box: enough for
+    the cell-list pair search (17 cells per axis), with lubrication contacts
+    from the start; FP64 end to end against the oracle's all-pairs search."""
+    p = W.params(nx=64, ny=64, nz=64, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=77)
+    pos = W.random_sphere_positions((64, 64, 64), 1200, 1.5, seed=77, min_gap=0.15)
+    rng = np.random.default_rng(77)
+    parts = W.make_particles(pos, 1.5, vel=rng.uniform(-0.02, 0.02, (1200, 3)), density=1.0)
+    gpu = lbm().Lattice(p, precision="fp64")
+    gpu.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    gpu.step(12)
+    ref.step(12)
     compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
     compare_bookkeeping(gpu, ref)
     Pg, Pr = gpu.particles(), ref.particles()
