@@ -246,10 +246,12 @@ int lb_order_parameter_profile(lb_handle *h, int32_t axis, double *out);
  * Batches: many lattices advanced by one graph launch.
  *
  * lb_batch_create captures steps_per_launch (even, >= 2) time steps of every
- * member into one HIP graph, each member's kernels on a branch of its own so
- * that the members run concurrently; lb_batch_step replays it nlaunches
- * times on `stream` (ordered after the members' pending work, and the
- * members' later calls are ordered after it).  The kernels are exactly those
+ * member into one HIP graph: members with the same precision and collision
+ * model, the two-pass sweep and no walls as one launch per stage over all of
+ * them, others each on a branch of its own; lb_batch_step replays it
+ * nlaunches times on `stream` (ordered after the members' pending work, and
+ * the members' later calls are ordered after it).  A member stepped an odd
+ * number of times outside the batch makes lb_batch_step fail (LB_ESTATE).  The kernels are exactly those
  * of lb_step, so every member's result is bitwise the same alone and in a
  * batch.  Members must be fully set up (spheres added); while in a batch they
  * refuse lb_add_particles and lb_set_state, must not record kernel timing,

@@ -1,13 +1,15 @@
 // Batched stepping of many lattices with one graph launch, and the tile /
 // kernel autotuner.
 //
-// A batch captures `k` time steps of every member into one HIP graph.  Each
-// member's kernels are captured from a stream of its own, forked from and
-// joined into the capture stream, so the graph holds independent branches
-// and the members' kernels overlap on the device; a replay advances every
-// member by k steps with one launch.  The kernels are the members' own
-// (identical launches to lb_step), so a member's result is bitwise the same
-// alone and in a batch.
+// A batch captures `k` time steps of every member into one HIP graph; a
+// replay advances every member by k steps with one launch.  Members that share
+// precision and collision model, use the two-pass sweep and have no walls are
+// captured as shared launches: every stage of a step is one kernel launch over
+// all members, each block finding its member from block maps in device memory
+// and running the same body as the single-lattice kernel.  Other batches
+// capture each member's own launches on a stream of its own, forked from and
+// joined into the capture stream (independent branches).  Either way a
+// member's result is bitwise the same alone and in a batch.
 #include <chrono>
 #include <cstring>
 
@@ -22,6 +24,9 @@ struct lb_batch {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev_done = nullptr;
     int k = 2;
+    bool shared = false;            // one launch per stage for all members
+    std::vector<int> cur0;          // the members' buffer parity the graph was captured with
+    void *tables = nullptr;         // device member tables and block maps (shared launches)
     std::string err;
 };
 
@@ -38,6 +43,8 @@ int bfail(lb_batch *b, int code, const std::string &msg) {
 
 void release(lb_batch *b) {
     for (lb_handle *h : b->m) h->in_batch = false;
+    if (b->tables) (void)hipFree(b->tables);
+    b->tables = nullptr;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (hipStream_t s : b->branch) (void)hipStreamDestroy(s);
@@ -51,6 +58,63 @@ void release(lb_batch *b) {
 }
 
 #define BATCH_CHECK(expr) LB_HIP_CHECK(expr)
+
+// Members that share precision and collision model, use the two-pass sweep
+// and have no walls are advanced by shared launches: the member tables (both
+// step parities) and the block maps go to the device once, and every stage of
+// a step is one launch over all members.
+bool shared_launches_fit(const std::vector<lb_handle *> &m) {
+    for (lb_handle *h : m) {
+        if (h->kernel != LB_KERNEL_TWOPASS || h->prm.wall_axis >= 0) return false;
+        if (h->prm.precision != m[0]->prm.precision || h->prm.velocity_mode != m[0]->prm.velocity_mode ||
+            h->prm.eq_order != m[0]->prm.eq_order)
+            return false;
+    }
+    return true;
+}
+
+void build_shared(lb_batch *b, lbm::BatchLaunch &L) {
+    using namespace lbm;
+    const int nm = (int)b->m.size();
+    std::vector<BatchMember> tab(2 * (size_t)nm);
+    std::vector<int32_t> start((size_t)BM_COUNT * (nm + 1), 0);
+    for (int i = 0; i < nm; ++i) {
+        lb_handle *h = b->m[i];
+        const bool cells = h->dpart.pgx > 0 && h->np >= PAIR_CELLS_MIN_SPHERES;
+        const int np = h->np, np256 = (h->np + BLOCK - 1) / BLOCK;
+        const int cnt[BM_COUNT] = {(int)((h->N + BLOCK - 1) / BLOCK), np, np256, cells ? np : 0,
+                                   cells ? np256 : 0, cells && np ? 1 : 0, cells ? 0 : np};
+        for (int k = 0; k < BM_COUNT; ++k) start[(size_t)k * (nm + 1) + i + 1] = start[(size_t)k * (nm + 1) + i] + cnt[k];
+        for (int par = 0; par < 2; ++par) {
+            BatchMember &M = tab[(size_t)par * nm + i];
+            const int c = h->cur ^ par;
+            M.P = h->dp;
+            M.D = h->dpart;
+            M.fin = h->f[c];
+            M.fout = h->f[1 - c];
+            M.rho = h->rho;
+            M.psi = h->psi;
+            M.fsc = h->fsc;
+            M.info = h->info;
+            M.owner = h->owner;
+            M.stage = h->stage;
+            M.partial = h->partial;
+            M.dstate = h->dstate;
+            M.rows = h->prm.nx % (int)VB == 0 ? 1 : 0;
+            M.cells = cells ? 1 : 0;
+        }
+    }
+    const size_t tb = sizeof(BatchMember) * tab.size(), sb = sizeof(int32_t) * start.size();
+    BATCH_CHECK(hipMalloc(&b->tables, tb + sb));
+    BATCH_CHECK(hipMemcpy(b->tables, tab.data(), tb, hipMemcpyHostToDevice));
+    BATCH_CHECK(hipMemcpy((char *)b->tables + tb, start.data(), sb, hipMemcpyHostToDevice));
+    const BatchMember *dt = (const BatchMember *)b->tables;
+    const int32_t *ds = (const int32_t *)((char *)b->tables + tb);
+    for (int par = 0; par < 2; ++par) L.plan[par] = BatchPlan{dt + (size_t)par * nm, ds, nm};
+    for (int k = 0; k < BM_COUNT; ++k) L.total[k] = start[(size_t)k * (nm + 1) + nm];
+    L.nm = nm;
+    L.prm = b->m[0]->prm;
+}
 
 }  // namespace
 
@@ -90,18 +154,28 @@ int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, vo
         BATCH_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
         joins.resize(n, nullptr);
         for (int i = 0; i < n; ++i) BATCH_CHECK(hipEventCreateWithFlags(&joins[i], hipEventDisableTiming));
+        b->shared = shared_launches_fit(b->m);
+        lbm::BatchLaunch L{};
+        if (b->shared) build_shared(b, L);
         BATCH_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        BATCH_CHECK(hipEventRecord(fork, cs));
-        for (int i = 0; i < n; ++i) {
-            lb_handle *h = b->m[i];
-            BATCH_CHECK(hipStreamWaitEvent(b->branch[i], fork, 0));
-            saved[i] = h->stream;
-            h->stream = b->branch[i];
-            for (int s = 0; s < b->k; ++s) lbm::one_step(h);
-            h->stream = saved[i];
-            h->step -= b->k;  // the capture only recorded the steps
-            BATCH_CHECK(hipEventRecord(joins[i], b->branch[i]));
-            BATCH_CHECK(hipStreamWaitEvent(cs, joins[i], 0));
+        if (b->shared) {
+            for (int s = 0; s < b->k; ++s) {
+                lbm::launch_batch_fluid(L, s & 1, cs);
+                lbm::launch_batch_particles(L, s & 1, cs);
+            }
+        } else {
+            BATCH_CHECK(hipEventRecord(fork, cs));
+            for (int i = 0; i < n; ++i) {
+                lb_handle *h = b->m[i];
+                BATCH_CHECK(hipStreamWaitEvent(b->branch[i], fork, 0));
+                saved[i] = h->stream;
+                h->stream = b->branch[i];
+                for (int s = 0; s < b->k; ++s) lbm::one_step(h);
+                h->stream = saved[i];
+                h->step -= b->k;  // the capture only recorded the steps
+                BATCH_CHECK(hipEventRecord(joins[i], b->branch[i]));
+                BATCH_CHECK(hipStreamWaitEvent(cs, joins[i], 0));
+            }
         }
         BATCH_CHECK(hipStreamEndCapture(cs, &b->graph));
         BATCH_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
@@ -124,7 +198,10 @@ int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, vo
     for (hipEvent_t e : joins) (void)hipEventDestroy(e);
     (void)hipEventDestroy(fork);
     (void)hipStreamDestroy(cs);
-    for (lb_handle *h : b->m) h->in_batch = true;
+    for (lb_handle *h : b->m) {
+        h->in_batch = true;
+        b->cur0.push_back(h->cur);
+    }
     *out = b;
     return LB_OK;
 }
@@ -134,6 +211,9 @@ int lb_batch_step(lb_batch *b, int32_t nlaunches) {
     if (nlaunches < 0) return bfail(b, LB_EINVAL, "nlaunches must be >= 0");
     if (nlaunches == 0) return LB_OK;
     const int n = (int)b->m.size();
+    for (int i = 0; i < n; ++i)  // the graph holds each member's buffers for its parity at capture
+        if (b->m[i]->cur != b->cur0[i])
+            return bfail(b, LB_ESTATE, "member " + std::to_string(i) + " was stepped an odd number of times outside the batch");
     try {
         // after whatever the members' own streams hold ...
         for (int i = 0; i < n; ++i) {

@@ -252,11 +252,20 @@ struct DevParticles {
 constexpr int CELL_SHIFT = 3;  // coarse cells of 8^3 sites
 constexpr int MAX_LUB_CONTACTS = 32;
 
+
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-__device__ __forceinline__ bool dense_site(const DevParams &P, unsigned &n, int &x, int &y, int &z) {
-    const unsigned nb = gridDim.x;
-    unsigned b = blockIdx.x;
+// The block a kernel body runs as and the number of blocks of its lattice:
+// blockIdx.x / gridDim.x for a launch over one lattice, or a block's range
+// within its member for a launch over a batch of lattices.
+struct Grid {
+    unsigned bid, nb;
+};
+__device__ __forceinline__ Grid own_grid() { return Grid{blockIdx.x, gridDim.x}; }
+
+__device__ __forceinline__ bool dense_site(const DevParams &P, const Grid &g, unsigned &n, int &x, int &y, int &z) {
+    const unsigned nb = g.nb;
+    unsigned b = g.bid;
     if (nb % 8u == 0) b = (b % 8u) * (nb / 8u) + b / 8u;
     n = b * 256u + threadIdx.x;
     if (n >= (unsigned)P.N) return false;
@@ -271,9 +280,13 @@ __device__ __forceinline__ bool dense_site(const DevParams &P, unsigned &n, int 
 // dense_site for boxes whose nx is a multiple of 64: a wavefront's 64 sites
 // then lie in one row, so y and z are computed once per wavefront (scalar
 // registers) from its first site; x = x0 + lane.
-__device__ __forceinline__ bool dense_site_rows(const DevParams &P, unsigned &n, int &x, int &y, int &z) {
-    const unsigned nb = gridDim.x;
-    unsigned b = blockIdx.x;
+__device__ __forceinline__ bool dense_site(const DevParams &P, unsigned &n, int &x, int &y, int &z) {
+    return dense_site(P, own_grid(), n, x, y, z);
+}
+__device__ __forceinline__ bool dense_site_rows(const DevParams &P, const Grid &g, unsigned &n, int &x, int &y,
+                                                int &z) {
+    const unsigned nb = g.nb;
+    unsigned b = g.bid;
     if (nb % 8u == 0) b = (b % 8u) * (nb / 8u) + b / 8u;
     n = b * 256u + threadIdx.x;
     if (n >= (unsigned)P.N) return false;
@@ -286,6 +299,56 @@ __device__ __forceinline__ bool dense_site_rows(const DevParams &P, unsigned &n,
     z = (int)zq;
     return true;
 }
+// One lattice of a batch advanced by shared launches (one launch per stage of
+// the step for all members): its parameters, sphere data and buffers for one
+// step parity (fin / fout swap between the two tables of a batch).
+struct BatchMember {
+    DevParams P;
+    DevParticles D;
+    const void *fin;
+    void *fout;
+    void *rho, *psi, *fsc;
+    uint32_t *info;
+    int32_t *owner, *stage;
+    double *partial;
+    DevState *dstate;
+    int rows;   // nx a multiple of 64: row-aligned addressing
+    int cells;  // pair search by cell list
+};
+// Blocks of each member in a batched launch, as cumulative counts (nm + 1
+// entries; a member with none has an empty range).
+enum BatchMap : int {
+    BM_DENSE = 0,    // blocks of the dense site grid
+    BM_SPHERE,       // one block per sphere
+    BM_SPHERE256,    // ceil(np / 256) blocks
+    BM_CELL_SPHERE,  // one block per sphere, members with a cell list
+    BM_CELL_SPH256,  // ceil(np / 256) blocks, members with a cell list
+    BM_CELL_ONE,     // one block, members with a cell list
+    BM_PAIR_SPHERE,  // one block per sphere, members with the all-pairs search
+    BM_COUNT
+};
+struct BatchPlan {
+    const BatchMember *m;
+    const int32_t *start;  // BM_COUNT x (nm + 1)
+    int nm;
+};
+// the member whose block range holds block b of a batched launch, and the
+// block's place in it (uniform over the block)
+__device__ __forceinline__ int batch_member(const BatchPlan &B, int map, Grid &g) {
+    const int32_t *st = B.start + map * (B.nm + 1);
+    const unsigned b = blockIdx.x;
+    int lo = 0, hi = B.nm - 1;
+    while (lo < hi) {  // last member whose start is <= b
+        const int mid = (lo + hi + 1) >> 1;
+        if ((unsigned)st[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const int m = __builtin_amdgcn_readfirstlane(lo);
+    g.bid = b - (unsigned)st[m];
+    g.nb = (unsigned)(st[m + 1] - st[m]);
+    return m;
+}
+
 __device__ __forceinline__ int wrapany(int a, int n) { a %= n; return a < 0 ? a + n : a; }
 
 // equilibrium of Eq. (3) with c_s^2 = 1/3 for one direction

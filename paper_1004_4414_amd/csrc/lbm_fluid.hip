@@ -90,13 +90,13 @@ __global__ void k_fill_int(int32_t *p, long long n, int32_t v) {
 // ---------------------------------------------------------------------------
 // ROWS: row-aligned addressing (nx a multiple of 64)
 template <typename S, bool ROWS, typename T = Cmp<S>>
-__global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restrict__ f,
-                                                   const uint32_t *__restrict__ info, T *__restrict__ rho,
-                                                   T *__restrict__ psi, double *__restrict__ partial) {
+__device__ __forceinline__ void density_body(const DevParams &P, const S *__restrict__ f,
+                                             const uint32_t *__restrict__ info, T *__restrict__ rho,
+                                             T *__restrict__ psi, double *__restrict__ partial, const Grid &g) {
     double m[2] = {0.0, 0.0};
     unsigned n;
     int x, y, z;
-    if (ROWS ? dense_site_rows(P, n, x, y, z) : dense_site(P, n, x, y, z)) {
+    if (ROWS ? dense_site_rows(P, g, n, x, y, z) : dense_site(P, g, n, x, y, z)) {
         const bool fluid = site_class(info[n]) == CLS_FLUID;
         const T irho0 = (T)P.inv_rho0;
         T dr[2] = {-(T)P.rho_ref[0], -(T)P.rho_ref[1]};
@@ -119,11 +119,17 @@ __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restr
         for (int c = 0; c < 2; ++c)
             for (int off = 32; off > 0; off >>= 1) m[c] += __shfl_down(m[c], off, 64);
         if ((threadIdx.x & 63) == 0) {
-            const unsigned w = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+            const unsigned w = g.bid * (BLOCK / 64) + (threadIdx.x >> 6);
             partial[2 * w + 0] = m[0];
             partial[2 * w + 1] = m[1];
         }
     }
+}
+template <typename S, bool ROWS, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restrict__ f,
+                                                   const uint32_t *__restrict__ info, T *__restrict__ rho,
+                                                   T *__restrict__ psi, double *__restrict__ partial) {
+    density_body<S, ROWS>(P, f, info, rho, psi, partial, own_grid());
 }
 
 // fixed-order sum of the per-block masses: M(t), baseline M(0), sentinel.
@@ -132,13 +138,13 @@ __global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restr
 // (an integer counter) sums their results in block order and resets the
 // counter, so the total does not depend on which block finishes last.
 constexpr int FIN_THREADS = 256;
-__global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__restrict__ partial, int nb,
-                                                               DevState *st) {
+__device__ __forceinline__ void finalize_body(const double *__restrict__ partial, int nb, DevState *st,
+                                              unsigned bid) {
     __shared__ double lds[2][FIN_THREADS];
     __shared__ int last;
     const int t = threadIdx.x;
     const int chunk = (nb + FIN_BLOCKS - 1) / FIN_BLOCKS;
-    const int b_lo = blockIdx.x * chunk, b_hi = min(nb, b_lo + chunk);
+    const int b_lo = (int)bid * chunk, b_hi = min(nb, b_lo + chunk);
     double a[2][8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) a[0][j] = a[1][j] = 0.0;
@@ -164,8 +170,8 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
         __syncthreads();
     }
     if (t == 0) {
-        st->fin_part[2 * blockIdx.x] = lds[0][0];
-        st->fin_part[2 * blockIdx.x + 1] = lds[1][0];
+        st->fin_part[2 * bid] = lds[0][0];
+        st->fin_part[2 * bid + 1] = lds[1][0];
         __threadfence();
         last = atomicAdd(&st->fin_count, 1u) == FIN_BLOCKS - 1;
     }
@@ -195,6 +201,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
         st->fin_count = 0;
     }
 }
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__restrict__ partial, int nb,
+                                                               DevState *st) {
+    finalize_body(partial, nb, st, blockIdx.x);
+}
 
 // ---------------------------------------------------------------------------
 // virtual fluid (Sec. IV): on every shell site of particle p, rho^c is the mean
@@ -203,9 +213,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
 // ---------------------------------------------------------------------------
 constexpr int SHELL_THREADS = 64;  // one wavefront per sphere (a few hundred shell sites each)
 template <typename T>
-__global__ __launch_bounds__(SHELL_THREADS) void k_shell_fill(DevParams P, DevParticles D, const uint32_t *__restrict__ info,
-                                                      T *__restrict__ rho, T *__restrict__ psi) {
-    const int p = blockIdx.x;
+__device__ __forceinline__ void shell_fill_body(const DevParams &P, const DevParticles &D,
+                                                const uint32_t *__restrict__ info, T *__restrict__ rho,
+                                                T *__restrict__ psi, const Grid &g) {
+    const int p = (int)g.bid;
     const int cnt = min(D.shell_cnt[p], D.shell_cap[p]), off = D.shell_off[p];
     const double col = D.color[p];
     const T irho0 = (T)P.inv_rho0;
@@ -236,6 +247,12 @@ __global__ __launch_bounds__(SHELL_THREADS) void k_shell_fill(DevParams P, DevPa
         store_pair(rho, sidx(0, (unsigned)s), r0, r1);
         store_pair(psi, sidx(0, (unsigned)s), psi_dev(r0, (T)P.psi_e[0], irho0), psi_dev(r1, (T)P.psi_e[1], irho0));
     }
+}
+template <typename T>
+__global__ __launch_bounds__(SHELL_THREADS) void k_shell_fill(DevParams P, DevParticles D,
+                                                              const uint32_t *__restrict__ info, T *__restrict__ rho,
+                                                              T *__restrict__ psi) {
+    shell_fill_body(P, D, info, rho, psi, own_grid());
 }
 
 // Psi^c(x + c_i) - Psi^c(rho_ref) of the 18 neighbours (pn[c][i-1]) and of
@@ -295,14 +312,12 @@ __device__ __forceinline__ void store_shell_force(const DevParams &P, const T (&
 // full lane mask; ROWS selects row-aligned addressing (nx a multiple of 64).
 // ---------------------------------------------------------------------------
 template <typename S, typename M, bool ROWS, typename T = Cmp<S>>
-__global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevParams P, const S *__restrict__ fin,
-                                                                          S *__restrict__ fout,
-                                                                          const T *__restrict__ psi,
-                                                                          const uint32_t *__restrict__ info,
-                                                                          T *__restrict__ fsc) {
+__device__ __forceinline__ void collide_body(const DevParams &P, const S *__restrict__ fin, S *__restrict__ fout,
+                                             const T *__restrict__ psi, const uint32_t *__restrict__ info,
+                                             T *__restrict__ fsc, const Grid &g) {
     unsigned n;
     int x, y, z;
-    if (!(ROWS ? dense_site_rows(P, n, x, y, z) : dense_site(P, n, x, y, z))) return;
+    if (!(ROWS ? dense_site_rows(P, g, n, x, y, z) : dense_site(P, g, n, x, y, z))) return;
     T f[2][Q];
     T pn[2][Q - 1], own_psi[2];
     if constexpr (ROWS) {
@@ -348,6 +363,14 @@ __global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevPa
             store_pop(fout, pidx(0, i, n), f[0][i], f[1][i]);
         });
     }
+}
+template <typename S, typename M, bool ROWS, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void k_collide_stream(DevParams P, const S *__restrict__ fin,
+                                                                          S *__restrict__ fout,
+                                                                          const T *__restrict__ psi,
+                                                                          const uint32_t *__restrict__ info,
+                                                                          T *__restrict__ fsc) {
+    collide_body<S, M, ROWS>(P, fin, fout, psi, info, fsc, own_grid());
 }
 
 // ---------------------------------------------------------------------------
@@ -605,6 +628,57 @@ void launch_sums(lb_handle *h, const void *f) {
     with_storage(h->prm, [&](auto tag) {
         using S = typename decltype(tag)::type;
         k_sums<S><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, h->partial);
+    });
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches of the fluid stages (see lbm_particles.hip)
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void kb_density(BatchPlan B) {
+    using T = Cmp<S>;
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_DENSE, g)];
+    if (M.rows)
+        density_body<S, true>(M.P, (const S *)M.fin, M.info, (T *)M.rho, (T *)M.psi, M.partial, g);
+    else
+        density_body<S, false>(M.P, (const S *)M.fin, M.info, (T *)M.rho, (T *)M.psi, M.partial, g);
+}
+__global__ __launch_bounds__(FIN_THREADS) void kb_finalize_mass(BatchPlan B) {
+    const int m = (int)(blockIdx.x / FIN_BLOCKS);
+    const BatchMember &M = B.m[m];
+    const int *st = B.start + BM_DENSE * (B.nm + 1);
+    finalize_body(M.partial, (st[m + 1] - st[m]) * (BLOCK / 64), M.dstate, blockIdx.x % FIN_BLOCKS);
+}
+template <typename T>
+__global__ __launch_bounds__(SHELL_THREADS) void kb_shell_fill(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
+    shell_fill_body(M.P, M.D, M.info, (T *)M.rho, (T *)M.psi, g);
+}
+template <typename S, typename Mo>
+__global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void kb_collide_stream(BatchPlan B) {
+    using T = Cmp<S>;
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_DENSE, g)];
+    if (M.rows)
+        collide_body<S, Mo, true>(M.P, (const S *)M.fin, (S *)M.fout, (const T *)M.psi, M.info, (T *)M.fsc, g);
+    else
+        collide_body<S, Mo, false>(M.P, (const S *)M.fin, (S *)M.fout, (const T *)M.psi, M.info, (T *)M.fsc, g);
+}
+
+// density, mass total, virtual fluid and collide sweep of every member
+void launch_batch_fluid(const BatchLaunch &L, int parity, hipStream_t s) {
+    const BatchPlan &B = L.plan[parity];
+    const unsigned nd = (unsigned)L.total[BM_DENSE];
+    with_storage(L.prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        using T = Cmp<S>;
+        kb_density<S><<<nd, BLOCK, 0, s>>>(B);
+        kb_finalize_mass<<<(unsigned)(L.nm * FIN_BLOCKS), FIN_THREADS, 0, s>>>(B);
+        if (L.total[BM_SPHERE] > 0) kb_shell_fill<T><<<(unsigned)L.total[BM_SPHERE], SHELL_THREADS, 0, s>>>(B);
+        with_model(L.prm, [&](auto m) { kb_collide_stream<S, decltype(m)><<<nd, BLOCK, 0, s>>>(B); });
     });
     LB_HIP_CHECK(hipGetLastError());
 }

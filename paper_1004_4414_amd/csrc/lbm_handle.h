@@ -119,6 +119,19 @@ void launch_map_commit(lb_handle *h, bool full);
 void launch_map_info(lb_handle *h);
 void launch_build_lists(lb_handle *h, bool full);
 
+// a batch advanced by shared launches: one launch per stage of the step for
+// all members (lbm_batch.hip builds it; the launchers are in lbm_fluid.hip and
+// lbm_particles.hip)
+constexpr int PAIR_CELLS_MIN_SPHERES = 1024;  // the cell-list pair search from this many spheres
+struct BatchLaunch {
+    BatchPlan plan[2];       // device tables for the two step parities (fin / fout swapped)
+    int total[BM_COUNT];     // blocks of each map over all members
+    int nm;
+    lb_params prm;           // precision and collision model shared by the members
+};
+void launch_batch_fluid(const BatchLaunch &L, int parity, hipStream_t s);
+void launch_batch_particles(const BatchLaunch &L, int parity, hipStream_t s);
+
 }  // namespace lbm
 
 #define LB_HIP_CHECK(expr)                                                            \

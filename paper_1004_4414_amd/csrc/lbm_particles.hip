@@ -205,15 +205,15 @@ __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &
 constexpr int LINKS_PER_PASS = 4;
 
 template <typename S, typename T = Cmp<S>>
-__global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, S *__restrict__ fout,
+__device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevParticles D, S *__restrict__ fout,
                                                                 const T *__restrict__ rho, const T *__restrict__ fsc,
-                                                                const uint32_t *__restrict__ info) {
+                                                                const uint32_t *__restrict__ info, const Grid &g) {
     __shared__ double lds[6 * (BLOCK / 64)];
     __shared__ int pre[BLOCK + 1];     // exclusive prefix of the link counts of the chunk's sites
     __shared__ uint32_t fmask[BLOCK];  // fluid-neighbour masks of the chunk's sites
     __shared__ unsigned sites[BLOCK];
     __shared__ int wtot[BLOCK / 64];
-    const int p = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int p = g.bid, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double v[6] = {0, 0, 0, 0, 0, 0};
     double R[3], U[3], W[3];
     load3(D.R, p, R);
@@ -341,6 +341,13 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
         }
 }
 
+template <typename S, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, DevParticles D, S *__restrict__ fout,
+                                                                const T *__restrict__ rho, const T *__restrict__ fsc,
+                                                                const uint32_t *__restrict__ info) {
+    particle_fluid_force_body<S>(P, D, fout, rho, fsc, info, own_grid());
+}
+
 // ---------------------------------------------------------------------------
 // pair forces, Eqs. (21) and (22), then the total force and torque: Hertz
 // repulsion (5/2) K (r_a + r_b - d)^(3/2) along the centre line, and the
@@ -353,10 +360,10 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
 // backward-Euler solution for an isolated pair; sharing a sphere's mass among
 // its contacts keeps simultaneous impulses from overshooting).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_pair_forces(DevParams P, DevParticles D, DevState *st) {
+__device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, DevState *st, const Grid &g) {
     __shared__ double lds[3 * (BLOCK / 64)];
     __shared__ int clds[8];
-    const int p = blockIdx.x;
+    const int p = g.bid;
     double Rp[3];
     load3(D.R, p, Rp);
     const double rp = D.rad[p];
@@ -420,6 +427,10 @@ __global__ __launch_bounds__(BLOCK) void k_pair_forces(DevParams P, DevParticles
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_pair_forces(DevParams P, DevParticles D, DevState *st) {
+    pair_forces_body(P, D, st, own_grid());
+}
+
 // ---------------------------------------------------------------------------
 // The same pair forces from a cell list (cells at least 2 r_max + h_c wide, at
 // least 3 per axis, so every partner within reach lies in the 27 cells around
@@ -441,18 +452,22 @@ __device__ __forceinline__ int pair_cell(const DevParams &P, const DevParticles 
     return (c[2] * g[1] + c[1]) * g[0] + c[0];
 }
 
-__global__ void k_pcell_count(DevParams P, DevParticles D) {
-    const int p = blockIdx.x * BLOCK + threadIdx.x;
+__device__ __forceinline__ void pcell_count_body(DevParams P, DevParticles D, const Grid &g) {
+    const int p = g.bid * BLOCK + threadIdx.x;
     if (p >= P.np) return;
     const int c = pair_cell(P, D, p);
     D.pc_of[p] = c;
     atomicAdd(&D.pc_cnt[c], 1);
 }
 
+__global__ void k_pcell_count(DevParams P, DevParticles D) {
+    pcell_count_body(P, D, own_grid());
+}
+
 // exclusive scan of the cell counts (one block: contiguous runs per thread,
 // then a scan of the run totals)
 constexpr int PCS_THREADS = 1024;
-__global__ __launch_bounds__(PCS_THREADS) void k_pcell_scan(DevParticles D) {
+__device__ __forceinline__ void pcell_scan_body(DevParticles D, const Grid &g) {
     __shared__ int tot[PCS_THREADS];
     const int nc = D.pgx * D.pgy * D.pgz;
     const int t = threadIdx.x;
@@ -476,20 +491,28 @@ __global__ __launch_bounds__(PCS_THREADS) void k_pcell_scan(DevParticles D) {
     if (t == PCS_THREADS - 1) D.pc_start[nc] = tot[t];
 }
 
+__global__ __launch_bounds__(PCS_THREADS) void k_pcell_scan(DevParticles D) {
+    pcell_scan_body(D, own_grid());
+}
+
 // scatter into the cells; counting down leaves the counts at zero for the next step
-__global__ void k_pcell_fill(DevParams P, DevParticles D) {
-    const int p = blockIdx.x * BLOCK + threadIdx.x;
+__device__ __forceinline__ void pcell_fill_body(DevParams P, DevParticles D, const Grid &g) {
+    const int p = g.bid * BLOCK + threadIdx.x;
     if (p >= P.np) return;
     const int c = D.pc_of[p];
     const int k = atomicSub(&D.pc_cnt[c], 1) - 1;
     D.pc_items[D.pc_start[c] + k] = p;
 }
 
+__global__ void k_pcell_fill(DevParams P, DevParticles D) {
+    pcell_fill_body(P, D, own_grid());
+}
+
 constexpr int PAIR_MAX_CAND = 512;  // partners within the 27 cells of one sphere
-__global__ __launch_bounds__(64) void k_pair_forces_cells(DevParams P, DevParticles D, DevState *st) {
+__device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles D, DevState *st, const Grid &g) {
     __shared__ int cand[PAIR_MAX_CAND];
     __shared__ int cstart[27], ccount[27], coff[28];
-    const int p = blockIdx.x, t = threadIdx.x;
+    const int p = g.bid, t = threadIdx.x;
     double Rp[3];
     load3(D.R, p, Rp);
     const double rp = D.rad[p];
@@ -604,11 +627,15 @@ __global__ __launch_bounds__(64) void k_pair_forces_cells(DevParams P, DevPartic
     }
 }
 
+__global__ __launch_bounds__(64) void k_pair_forces_cells(DevParams P, DevParticles D, DevState *st) {
+    pair_forces_cells_body(P, D, st, own_grid());
+}
+
 // lubrication impulses, then the leap-frog of Eqs. (9), (10):
 // U(t+1/2) = v* + impulses / m, R(t+1) = R(t) + U, Omega(t+1/2) = Omega(t-1/2)
 // + D/J; the pending impulses are consumed
-__global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
-    const int p = blockIdx.x * BLOCK + threadIdx.x;
+__device__ __forceinline__ void integrate_body(DevParams P, DevParticles D, DevState *st, const Grid &g) {
+    const int p = g.bid * BLOCK + threadIdx.x;
     if (p >= P.np) return;
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
     double imp[3] = {0, 0, 0};
@@ -646,15 +673,19 @@ __global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
     if (!(step2 < 1.0)) atomicOr(&st->overflow, 8);
 }
 
+__global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
+    integrate_body(P, D, st, own_grid());
+}
+
 // ---------------------------------------------------------------------------
 // solid map: every site inside sphere p (at its current position) proposes p;
 // the lowest index wins.  stage[] holds STAGE_NONE everywhere else.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage) {
-    const int p = blockIdx.x;
+__device__ __forceinline__ void map_mark_body(DevParams P, DevParticles D, int32_t *__restrict__ stage, const Grid &g) {
+    const int p = g.bid;
     {  // the blocks also clear the coarse dirty cells of the previous step, a slice each
         const int ncell = D.cgx * D.cgy * D.cgz;
-        const int per = (ncell + (int)gridDim.x - 1) / (int)gridDim.x;
+        const int per = (ncell + (int)g.nb - 1) / (int)g.nb;
         for (int c = p * per + threadIdx.x; c < min(ncell, (p + 1) * per); c += BLOCK) D.dirty[c] = 0;
     }
     int lo[3], ext[3];
@@ -674,12 +705,16 @@ __global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D,
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage) {
+    map_mark_body(P, D, stage, own_grid());
+}
+
 // covered (fluid -> inside p) and uncovered (inside p -> fluid) sites of
 // sphere p, listed in scan order of its box
-__global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                                      const int32_t *__restrict__ stage, DevState *st) {
+__device__ __forceinline__ void map_events_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                      const int32_t *__restrict__ stage, DevState *st, const Grid &g) {
     __shared__ int lds[8];
-    const int p = blockIdx.x;
+    const int p = g.bid;
     int lo[3], ext[3];
     union_box(P, D, p, 0, lo, ext);
     const BoxWalk bw(P, lo, ext);
@@ -723,6 +758,11 @@ __global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles 
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                      const int32_t *__restrict__ stage, DevState *st) {
+    map_events_body(P, D, owner, stage, st, own_grid());
+}
+
 // Covering, Eq. (18): the fluid of a covered site is removed and its momentum
 // goes to the sphere.  Refilling, Eqs. (23)-(26), (31): an uncovered site gets
 // f^eq(rho_new, u_surf) with rho_new^c the mean of rho^c(t+1) over its
@@ -730,11 +770,11 @@ __global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles 
 // correction; the sphere loses the created momentum.  Both impulses are
 // applied in the next step's integration.
 template <typename S>
-__global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticles D, S *__restrict__ f,
+__device__ __forceinline__ void cover_refill_body(DevParams P, DevParticles D, S *__restrict__ f,
                                                         const int32_t *__restrict__ owner,
-                                                        const int32_t *__restrict__ stage, DevState *st) {
+                                                        const int32_t *__restrict__ stage, DevState *st, const Grid &g) {
     __shared__ double lds[6 * (BLOCK / 64)];
-    const int p = blockIdx.x;
+    const int p = g.bid;
     const long long N = P.N;
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
     double R[3], U[3], W[3];
@@ -844,10 +884,17 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
     }
 }
 
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticles D, S *__restrict__ f,
+                                                        const int32_t *__restrict__ owner,
+                                                        const int32_t *__restrict__ stage, DevState *st) {
+    cover_refill_body<S>(P, D, f, owner, stage, st, own_grid());
+}
+
 // new owners of the sites in the box (identical values from every block)
-__global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles D, int32_t *__restrict__ owner,
-                                                      const int32_t *__restrict__ stage, int full) {
-    const int p = blockIdx.x;
+__device__ __forceinline__ void map_commit_body(DevParams P, DevParticles D, int32_t *__restrict__ owner,
+                                                      const int32_t *__restrict__ stage, int full, const Grid &g) {
+    const int p = g.bid;
     // an unchanged sphere's box holds no change of its own; changes of other
     // spheres inside it are written by their blocks
     if (!full && !D.changed[p]) return;
@@ -864,10 +911,15 @@ __global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles 
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles D, int32_t *__restrict__ owner,
+                                                      const int32_t *__restrict__ stage, int full) {
+    map_commit_body(P, D, owner, stage, full, own_grid());
+}
+
 // class words around the moved sphere; clears its marks in stage[]
-__global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                                    uint32_t *__restrict__ info, int32_t *__restrict__ stage) {
-    const int p = blockIdx.x;
+__device__ __forceinline__ void map_info_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                    uint32_t *__restrict__ info, int32_t *__restrict__ stage, const Grid &g) {
+    const int p = g.bid;
     int lo[3], ext[3];
     int V;
     if (D.changed[p]) {
@@ -891,14 +943,19 @@ __global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D,
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                    uint32_t *__restrict__ info, int32_t *__restrict__ stage) {
+    map_info_body(P, D, owner, info, stage, own_grid());
+}
+
 // virtual-fluid sites of sphere p on the new map, in scan order of its box,
 // and the number of its bounce-back links (fluid neighbours of those sites)
-__global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                                       const uint32_t *__restrict__ info, DevState *st, int full) {
+__device__ __forceinline__ void build_lists_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                       const uint32_t *__restrict__ info, DevState *st, int full, const Grid &g) {
     __shared__ int lds[8];
     __shared__ int nlink_block;
     __shared__ AxisCells ac;
-    const int p = blockIdx.x;
+    const int p = g.bid;
     if (threadIdx.x == 0) nlink_block = 0;
     int lo[3], ext[3];
     new_box(P, D, p, lo, ext);
@@ -945,6 +1002,11 @@ __global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_build_lists(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                       const uint32_t *__restrict__ info, DevState *st, int full) {
+    build_lists_body(P, D, owner, info, st, full, own_grid());
+}
+
 // ---------------------------------------------------------------------------
 // launchers (one block per sphere unless noted)
 // ---------------------------------------------------------------------------
@@ -959,10 +1021,8 @@ void launch_particle_fluid_force(lb_handle *h, void *fout) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
-// the cell list pays off from about a thousand spheres; fewer take the
-// all-pairs kernel (one launch instead of four)
-constexpr int PAIR_CELLS_MIN_SPHERES = 1024;
-
+// the cell list (PAIR_CELLS_MIN_SPHERES) pays off from about a thousand
+// spheres; fewer take the all-pairs kernel (one launch instead of four)
 void launch_pair_forces(lb_handle *h) {
     if (!h->np) return;
     if (h->dpart.pgx > 0 && h->np >= PAIR_CELLS_MIN_SPHERES) {
@@ -1019,6 +1079,110 @@ void launch_map_info(lb_handle *h) {
 void launch_build_lists(lb_handle *h, bool full) {
     if (!h->np) return;
     k_build_lists<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->info, h->dstate, full ? 1 : 0);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: each block finds its member and its place in the member's
+// range and runs the same body as the single-lattice kernel, so every member
+// computes exactly what it computes alone.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void kb_particle_fluid_force(BatchPlan B) {
+    using T = Cmp<S>;
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
+    particle_fluid_force_body<S>(M.P, M.D, (S *)M.fout, (const T *)M.rho, (const T *)M.fsc, M.info, g);
+}
+__global__ void kb_pcell_count(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_CELL_SPH256, g)];
+    pcell_count_body(M.P, M.D, g);
+}
+__global__ __launch_bounds__(PCS_THREADS) void kb_pcell_scan(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_CELL_ONE, g)];
+    pcell_scan_body(M.D, g);
+}
+__global__ void kb_pcell_fill(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_CELL_SPH256, g)];
+    pcell_fill_body(M.P, M.D, g);
+}
+__global__ __launch_bounds__(64) void kb_pair_forces_cells(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_CELL_SPHERE, g)];
+    pair_forces_cells_body(M.P, M.D, M.dstate, g);
+}
+__global__ __launch_bounds__(BLOCK) void kb_pair_forces(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_PAIR_SPHERE, g)];
+    pair_forces_body(M.P, M.D, M.dstate, g);
+}
+__global__ void kb_integrate(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE256, g)];
+    integrate_body(M.P, M.D, M.dstate, g);
+}
+__global__ __launch_bounds__(BLOCK) void kb_map_mark(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
+    map_mark_body(M.P, M.D, M.stage, g);
+}
+__global__ __launch_bounds__(BLOCK) void kb_map_events(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
+    map_events_body(M.P, M.D, M.owner, M.stage, M.dstate, g);
+}
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void kb_cover_refill(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
+    cover_refill_body<S>(M.P, M.D, (S *)M.fout, M.owner, M.stage, M.dstate, g);
+}
+__global__ __launch_bounds__(BLOCK) void kb_map_commit(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
+    map_commit_body(M.P, M.D, M.owner, M.stage, 0, g);
+}
+__global__ __launch_bounds__(BLOCK) void kb_map_info(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
+    map_info_body(M.P, M.D, M.owner, M.info, M.stage, g);
+}
+__global__ __launch_bounds__(BLOCK) void kb_build_lists(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
+    build_lists_body(M.P, M.D, M.owner, M.info, M.dstate, 0, g);
+}
+
+// the particle stages of one step of every member, in the order of a single
+// lattice's step (link sums, pair search, integration, map update)
+void launch_batch_particles(const BatchLaunch &L, int parity, hipStream_t s) {
+    const BatchPlan &B = L.plan[parity];
+    const unsigned nsph = (unsigned)L.total[BM_SPHERE];
+    if (nsph == 0) return;
+    with_storage(L.prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        kb_particle_fluid_force<S><<<nsph, BLOCK, 0, s>>>(B);
+    });
+    if (L.total[BM_CELL_SPHERE] > 0) {
+        kb_pcell_count<<<(unsigned)L.total[BM_CELL_SPH256], BLOCK, 0, s>>>(B);
+        kb_pcell_scan<<<(unsigned)L.total[BM_CELL_ONE], PCS_THREADS, 0, s>>>(B);
+        kb_pcell_fill<<<(unsigned)L.total[BM_CELL_SPH256], BLOCK, 0, s>>>(B);
+        kb_pair_forces_cells<<<(unsigned)L.total[BM_CELL_SPHERE], 64, 0, s>>>(B);
+    }
+    if (L.total[BM_PAIR_SPHERE] > 0) kb_pair_forces<<<(unsigned)L.total[BM_PAIR_SPHERE], BLOCK, 0, s>>>(B);
+    kb_integrate<<<(unsigned)L.total[BM_SPHERE256], BLOCK, 0, s>>>(B);
+    kb_map_mark<<<nsph, BLOCK, 0, s>>>(B);
+    kb_map_events<<<nsph, BLOCK, 0, s>>>(B);
+    with_storage(L.prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        kb_cover_refill<S><<<nsph, BLOCK, 0, s>>>(B);
+    });
+    kb_map_commit<<<nsph, BLOCK, 0, s>>>(B);
+    kb_map_info<<<nsph, BLOCK, 0, s>>>(B);
+    kb_build_lists<<<nsph, BLOCK, 0, s>>>(B);
     LB_HIP_CHECK(hipGetLastError());
 }
 

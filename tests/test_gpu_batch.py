@@ -74,6 +74,46 @@ def test_batch_replays_match_eager_stepping():
         _same(b, e)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_shared_launch_batch_matches_eager_stepping(precision):
+    """Members of one precision and model are advanced by one launch per stage
+    over all of them; uneven boxes (row-aligned 64 x 36 x 20 with spheres,
+    ragged 40 x 24 x 20 without, 36^3 with spheres) stay bitwise equal to
+    eager stepping."""
+    specs = []
+    p1 = W.params(nx=64, ny=36, nz=20, rho_init=(0.4, 0.3), noise_amp=0.02, g_br=0.08, seed=51)
+    rng = np.random.default_rng(51)
+    pos1 = W.random_sphere_positions((64, 36, 20), 4, 4.0, seed=51)
+    specs.append((p1, W.make_particles(pos1, 4.0, vel=rng.uniform(-0.02, 0.02, (4, 3)), color=[0.05, 0, -0.05, 0]),
+                  precision))
+    specs.append((W.params(nx=40, ny=24, nz=20, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.09, seed=52),
+                  None, precision))
+    p3 = W.params(nx=36, ny=36, nz=36, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.08, seed=53)
+    pos3 = W.random_sphere_positions((36, 36, 36), 3, 5.0, seed=53)
+    specs.append((p3, W.make_particles(pos3, 5.0, vel=rng.uniform(-0.02, 0.02, (3, 3))), precision))
+    batched = [_make(s) for s in specs]
+    eager = [_make(s) for s in specs]
+    batch = lbm().Batch(batched, steps_per_launch=6)
+    for nl in (1, 3):
+        batch.step(nl)
+        for e in eager:
+            e.step(6 * nl)
+        for b, e in zip(batched, eager):
+            _same(b, e)
+    # a member stepped an odd number of times outside the batch is refused
+    batched[1].step(1)
+    with pytest.raises(lbm().LBError):
+        batch.step(1)
+    batched[1].step(1)
+    batch.step(1)
+    for e in eager:
+        e.step(6)
+    eager[1].step(2)
+    for b, e in zip(batched, eager):
+        _same(b, e)
+    batch.close()
+
+
 def test_batch_membership_rules():
     L = lbm()
     a = _make(_members()[1])
