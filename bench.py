@@ -8,10 +8,12 @@ Shan-Chen force, collision, streaming with moving bounce-back, link and
 virtual-fluid force sums, pair forces, leap-frog, map update with covering
 and refilling).  Inputs are resident in HBM when the timed region starts.
 
-Prints one JSON line: MLUPS over all lattice sites, the roofline of the
-dominant kernel (the sweep that collides and streams the populations, timed
-with HIP events on its stream inside the timed region) and the FP64 oracle
-timed on the host cores on a bounded sample.
+Prints one JSON line: MLUPS over all lattice sites (and MFLUPS over the fluid
+sites), the roofline of the dominant kernel (the sweep that collides and
+streams the populations, timed with HIP events on its stream inside the
+timed region), set beside the bandwidth a plain elementwise copy reaches on
+the same device, and the FP64 oracle timed on the host cores on a bounded
+sample.
 """
 import argparse
 import json
@@ -51,6 +53,23 @@ def measured_traffic():
     if not m_hash or not m_bytes or m_hash.group(1) != h.hexdigest():
         return None
     return int(m_bytes.group(1))
+
+
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """GB/s (read + write) of an elementwise kernel over `mib` MiB, timed with
+    events: what a plain streaming copy reaches on this device"""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(seconds_budget=20.0):
@@ -206,8 +225,8 @@ def main():
                          "(a kernel of known traffic that calibrates rocprofv3's FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs one GPU "
-              f"per lattice, independent boxes shard trivially)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: a lattice runs on one GPU "
+              f"and independent boxes shard trivially, one or more per GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -259,6 +278,8 @@ def main():
           f"step (events) {s_ms / max(s_n, 1):.3f} ms; links {obs['n_links']}", file=sys.stderr, flush=True)
 
     mlups = N * args.steps / elapsed / 1e6
+    fluid_sites = int((lat.owner() == -1).sum())
+    copy_gbs = copy_bandwidth(torch)
     bps = algorithmic_bytes_per_site(precision)
     kern_name = "twopass" if args.kernel in ("auto", "twopass") else args.kernel
     traffic = measured_traffic() if (args.workload == "bijel256" and precision == "fp32" and kern_name == "twopass"
@@ -298,7 +319,10 @@ def main():
             "kernel": "collide-and-stream sweep",
             "bytes_per_site": bps,
             "ms_per_launch": round(sweep_s * 1e3, 4),
+            "copy_reference_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
+        "mflups_fluid": round(mlups * fluid_sites / N, 1),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
