@@ -114,6 +114,27 @@ def test_shared_launch_batch_matches_eager_stepping(precision):
     batch.close()
 
 
+def test_shared_launch_batch_with_cell_list_member():
+    """A member with 1100 spheres takes the cell-list pair search inside the
+    shared launches; it and a small member stay bitwise equal to eager stepping."""
+    specs = []
+    p1 = W.params(nx=64, ny=64, nz=64, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=61)
+    pos1 = W.random_sphere_positions((64, 64, 64), 1100, 1.5, seed=61, min_gap=0.15)
+    rng = np.random.default_rng(61)
+    specs.append((p1, W.make_particles(pos1, 1.5, vel=rng.uniform(-0.02, 0.02, (1100, 3))), "fp32"))
+    p2 = W.params(nx=32, ny=32, nz=32, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.08, seed=62)
+    specs.append((p2, W.make_particles(W.random_sphere_positions((32, 32, 32), 3, 4.0, seed=62), 4.0), "fp32"))
+    batched = [_make(s) for s in specs]
+    eager = [_make(s) for s in specs]
+    batch = lbm().Batch(batched, steps_per_launch=4)
+    batch.step(3)
+    for e in eager:
+        e.step(12)
+    for b, e in zip(batched, eager):
+        _same(b, e)
+    batch.close()
+
+
 def test_batch_membership_rules():
     L = lbm()
     a = _make(_members()[1])
