@@ -464,3 +464,28 @@ def test_dense_suspension_cell_list_pair_search():
     Pg, Pr = gpu.particles(), ref.particles()
     for k in ("R", "U", "W", "Ffluid", "Tfluid", "P", "PT"):
         assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+
+
+def test_large_lattice_translation_invariance():
+    """512^3 in FP32: each population buffer is 20 GB, so slot offsets pass
+    2^32 bytes.  A prescribed sphere moving along x in a uniform fluid gives
+    the same forces, torques and link counts at z = 40.2 and at z = 424.2
+    (periodic box, a whole shift of 384 planes): an index that wrapped at 32
+    bits would read or write other sites in the upper run."""
+    out = []
+    for z in (40.2, 424.2):
+        p = W.params(nx=512, ny=512, nz=512, rho_init=(0.35, 0.35), noise_amp=0.0, g_br=0.02, seed=5)
+        gpu = lbm().Lattice(p, precision="fp32")
+        gpu.add_particles(W.make_particles([[100.3, 200.7, z]], 5.0, vel=[[0.03, 0.0, 0.0]], prescribed=1))
+        gpu.step(12)
+        o1 = gpu.observables()
+        P = gpu.particles()
+        out.append((P["Ffluid"][0].copy(), P["Tfluid"][0].copy(), o1["n_links"], o1["covered_total"],
+                    o1["uncovered_total"], o1["mass"].copy()))
+        assert np.all(np.isfinite(o1["fluid_momentum"]))
+        gpu.close()
+    (F0, T0, l0, c0, u0, m0), (F1, T1, l1, c1, u1, m1) = out
+    assert (l0, c0, u0) == (l1, c1, u1) and c0 > 0
+    assert np.abs(F1 - F0).max() <= 1e-9 * max(np.abs(F0).max(), 1e-12)
+    assert np.abs(T1 - T0).max() <= 1e-6 * max(np.abs(T0).max(), 1e-12)
+    assert np.abs(m1 - m0).max() <= 1e-9 * m0.max()
