@@ -821,6 +821,31 @@ __device__ __forceinline__ void collide_site(const DevParams &P, T (&f)[2][Q], c
     relax<T, M::eq_order>(f[1], dr[1], r[1], ueq[1][0], ueq[1][1], ueq[1][2], (T)P.inv_tau[1]);
 }
 
+// The Shan-Chen force F of a virtual-fluid site is kept for the link
+// kernel's sums in the site's own population slots, which carry nothing else
+// between the sweep and the link kernel: (Fx, Fy) in slot 0 and (Fz, 0) in
+// slot j0, the first direction whose neighbour is not fluid (no bounce-back
+// writes it).  This replaces three scattered partial-line stores into a force
+// array by values of the sweep's full-lane stores.  It needs the stored type
+// to be the arithmetic type (FP32, FP64) and such a direction to exist;
+// otherwise the force array is used.  Writer and reader decide alike.
+__device__ __forceinline__ int shell_force_slot(uint32_t inf) { return __ffs(inf & 0x7fffeu) - 1; }
+template <typename S>
+__device__ __forceinline__ bool shell_force_in_slots(uint32_t inf) {
+    return std::is_same<S, Cmp<S>>::value && shell_force_slot(inf) > 0;
+}
+template <typename T>
+__device__ __forceinline__ void put_shell_force(T (&f)[2][Q], const T (&F)[3], uint32_t inf) {
+    const int j0 = shell_force_slot(inf);
+    f[0][0] = F[0];
+    f[1][0] = F[1];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        f[0][i] = i == j0 ? F[2] : f[0][i];
+        f[1][i] = i == j0 ? (T)0 : f[1][i];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // deterministic block reductions (blockDim.x == BLOCK)
 // ---------------------------------------------------------------------------

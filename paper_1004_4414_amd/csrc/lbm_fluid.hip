@@ -293,13 +293,12 @@ __device__ __forceinline__ void load_psi_neighbours_rows(const T *__restrict__ p
 // Shan-Chen force of Eq. (4) on a virtual-fluid site, kept for the particle
 // sums: Psi of the site is its stored deviation plus Psi(rho_ref) = rho0 - psi_e
 template <typename T>
-__device__ __forceinline__ void store_shell_force(const DevParams &P, const T (&own)[2], const T (&acc)[2][3],
-                                                  unsigned n, T *__restrict__ fsc) {
+__device__ __forceinline__ void shell_force(const DevParams &P, const T (&own)[2], const T (&acc)[2][3], T (&F)[3]) {
     const T g = (T)P.g;
     const T ps0 = own[0] + (T)(P.rho0 - P.psi_e[0]);
     const T ps1 = own[1] + (T)(P.rho0 - P.psi_e[1]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) fsc[vidx(a, n)] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
+    for (int a = 0; a < 3; ++a) F[a] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
 }
 
 // ---------------------------------------------------------------------------
@@ -336,11 +335,12 @@ __device__ __forceinline__ void collide_body(const DevParams &P, const S *__rest
     hold_loads(pn[1]);
     hold_loads(own_psi);
     const uint32_t cls = site_class(inf);
+    T F[3] = {0, 0, 0};
     if (cls == CLS_FLUID || cls == CLS_SHELL) {
         T acc[2][3];
         psi_force_sum(P, pn, acc);
         if (cls == CLS_SHELL) {
-            store_shell_force(P, own_psi, acc, n, fsc);
+            shell_force(P, own_psi, acc, F);
         } else {
             double m0 = 0.0, m1 = 0.0;
             collide_site<M>(P, f, acc, inf, n, (T *)nullptr, m0, m1);
@@ -349,6 +349,14 @@ __device__ __forceinline__ void collide_body(const DevParams &P, const S *__rest
     if (cls != CLS_FLUID) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[0][i] = f[1][i] = (T)0;
+    }
+    if (cls == CLS_SHELL) {
+        if (shell_force_in_slots<S>(inf)) {
+            put_shell_force(f, F, inf);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fsc[vidx(a, n)] = F[a];
+        }
     }
     if constexpr (ROWS) {
         const RowView<S> rv(P, x, y, z);

@@ -170,8 +170,15 @@ __global__ __launch_bounds__(TX *TY) void k_fused_step(DevParams P, DevParticles
                 if (cls == CLS_SHELL) {
                     const T ps0 = psi_of(sm.drho[sl_0][0][as] + ref0, rho0, irho0);
                     const T ps1 = psi_of(sm.drho[sl_0][1][as] + ref1, rho0, irho0);
+                    T F[3];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) fsc[vidx(a, (unsigned)n)] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
+                    for (int a = 0; a < 3; ++a) F[a] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
+                    if (shell_force_in_slots<T>(inf)) {
+                        put_shell_force(f, F, inf);
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) fsc[vidx(a, (unsigned)n)] = F[a];
+                    }
                 } else {
                     const NbrOffsets o(P, xs, ys, zc);
                     pull_load(fin, (unsigned)n, o, f);

@@ -231,7 +231,15 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
             s = (unsigned)D.shell[soff + k];
             const uint32_t inf = info[s];
             double F[3];
-            for (int a = 0; a < 3; ++a) F[a] = (double)fsc[vidx(a, s)];
+            if (shell_force_in_slots<S>(inf)) {  // (Fx, Fy) in slot 0, (Fz, 0) in slot j0 of the sweep's output
+                const Pair<T> v0 = load_pop(fout, pidx(0, 0, s));
+                const Pair<T> v1 = load_pop(fout, pidx(0, shell_force_slot(inf), s));
+                F[0] = (double)v0.x;
+                F[1] = (double)v0.y;
+                F[2] = (double)v1.x;
+            } else {
+                for (int a = 0; a < 3; ++a) F[a] = (double)fsc[vidx(a, s)];
+            }
             int x, y, z;
             site_xyz(s, P, x, y, z);
             const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
