@@ -209,7 +209,8 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
 // ---------------------------------------------------------------------------
 // virtual fluid (Sec. IV): on every shell site of particle p, rho^c is the mean
 // of rho^c over its fluid 18-neighbours plus |colour| on the preferred
-// component; written into the density-deviation and Psi arrays in place.
+// component; only its Psi - Psi(rho_ref) is stored (in the Psi array), since
+// every later use of a shell site's density goes through Psi.
 // ---------------------------------------------------------------------------
 constexpr int SHELL_THREADS = 64;  // one wavefront per sphere (a few hundred shell sites each)
 template <typename T>
@@ -244,7 +245,6 @@ __device__ __forceinline__ void shell_fill_body(const DevParams &P, const DevPar
         T r0 = nf ? sum0 / (T)nf : (T)0, r1 = nf ? sum1 / (T)nf : (T)0;
         if (col > 0.0) r0 += (T)fabs(col);
         if (col < 0.0) r1 += (T)fabs(col);
-        store_pair(rho, sidx(0, (unsigned)s), r0, r1);
         store_pair(psi, sidx(0, (unsigned)s), psi_dev(r0, (T)P.psi_e[0], irho0), psi_dev(r1, (T)P.psi_e[1], irho0));
     }
 }
@@ -459,9 +459,9 @@ __global__ __launch_bounds__(BLOCK) void k_fields(DevParams P, const S *__restri
     T acc[2][3], pn[2][Q - 1], own_psi[2];
     load_psi_neighbours(psi, n, o, pn, own_psi);
     psi_force_sum(P, pn, acc);
-    if (cls == CLS_SHELL) {
-        const T ps0 = psi_of(rho[sidx(0, n)] + (T)P.rho_ref[0], rho0, irho0);
-        const T ps1 = psi_of(rho[sidx(1, n)] + (T)P.rho_ref[1], rho0, irho0);
+    if (cls == CLS_SHELL) {  // Psi of the site: its stored deviation plus Psi(rho_ref) = rho0 - psi_e
+        const T ps0 = own_psi[0] + (T)(P.rho0 - P.psi_e[0]);
+        const T ps1 = own_psi[1] + (T)(P.rho0 - P.psi_e[1]);
         for (int a = 0; a < 3; ++a) {
             oF[(0 * N + n) * 3 + a] = (double)(-ps0 * g * acc[1][a]);
             oF[(1 * N + n) * 3 + a] = (double)(-ps1 * g * acc[0][a]);
