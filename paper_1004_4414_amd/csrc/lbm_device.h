@@ -102,23 +102,34 @@ __device__ __forceinline__ void store_pair(T *__restrict__ a, size_t k, T v0, T 
 // arithmetic runs in: FP64 and FP32 store what they compute; FP16 and BF16
 // store the deviations f_i - zeta_i rho_ref rounded to nearest, and every
 // update runs in FP32.  Populations move as component pairs (4, 8 or 16 B).
+//
+// A population written in one step is read back only in the next one, long
+// after the caches have turned over, so every population store carries the
+// non-temporal hint: it does not displace the lines that the sweep still
+// reads (the x-shifted pulls and the Psi neighbours).
+typedef float NtF2 __attribute__((ext_vector_type(2)));
+typedef double NtD2 __attribute__((ext_vector_type(2)));
+template <typename V, typename P>
+__device__ __forceinline__ void nt_store(P *at, V v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<V *>(at));
+}
+// two 16-bit values as one 32-bit word, x in the low half (the order of the
+// pair types); composed with shifts because a bit copy of the pair type can
+// lose the non-temporal hint of the store that follows
+__device__ __forceinline__ uint32_t pack16(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
 template <typename S>
 struct Storage;
 template <>
 struct Storage<double> {
     using T = double;
     __device__ static double2 load(const double *a, size_t k) { return *reinterpret_cast<const double2 *>(a + k); }
-    __device__ static void store(double *a, size_t k, double x, double y) {
-        *reinterpret_cast<double2 *>(a + k) = make_double2(x, y);
-    }
+    __device__ static void store(double *a, size_t k, double x, double y) { nt_store(a + k, NtD2{x, y}); }
 };
 template <>
 struct Storage<float> {
     using T = float;
     __device__ static float2 load(const float *a, size_t k) { return *reinterpret_cast<const float2 *>(a + k); }
-    __device__ static void store(float *a, size_t k, float x, float y) {
-        *reinterpret_cast<float2 *>(a + k) = make_float2(x, y);
-    }
+    __device__ static void store(float *a, size_t k, float x, float y) { nt_store(a + k, NtF2{x, y}); }
 };
 template <>
 struct Storage<__half> {
@@ -127,7 +138,7 @@ struct Storage<__half> {
         return __half22float2(*reinterpret_cast<const __half2 *>(a + k));
     }
     __device__ static void store(__half *a, size_t k, float x, float y) {
-        *reinterpret_cast<__half2 *>(a + k) = __floats2half2_rn(x, y);
+        nt_store(a + k, pack16(__half_as_ushort(__float2half_rn(x)), __half_as_ushort(__float2half_rn(y))));
     }
 };
 template <>
@@ -137,7 +148,7 @@ struct Storage<__hip_bfloat16> {
         return __bfloat1622float2(*reinterpret_cast<const __hip_bfloat162 *>(a + k));
     }
     __device__ static void store(__hip_bfloat16 *a, size_t k, float x, float y) {
-        *reinterpret_cast<__hip_bfloat162 *>(a + k) = __float22bfloat162_rn(make_float2(x, y));
+        nt_store(a + k, pack16(__bfloat16_as_ushort(__float2bfloat16(x)), __bfloat16_as_ushort(__float2bfloat16(y))));
     }
 };
 template <typename S>
