@@ -106,12 +106,19 @@ __device__ __forceinline__ void store_pair(T *__restrict__ a, size_t k, T v0, T 
 // A population written in one step is read back only in the next one, long
 // after the caches have turned over, so every population store carries the
 // non-temporal hint: it does not displace the lines that the sweep still
-// reads (the x-shifted pulls and the Psi neighbours).
+// reads (the x-shifted pulls and the Psi neighbours).  load_stream is the
+// same hint on a load whose lines no other wavefront of the sweep reads.
 typedef float NtF2 __attribute__((ext_vector_type(2)));
 typedef double NtD2 __attribute__((ext_vector_type(2)));
 template <typename V, typename P>
 __device__ __forceinline__ void nt_store(P *at, V v) {
     __builtin_nontemporal_store(v, reinterpret_cast<V *>(at));
+}
+// a component pair of a field in the arithmetic type, with the same hint
+template <typename T>
+__device__ __forceinline__ void store_pair_stream(T *__restrict__ a, size_t k, T v0, T v1) {
+    typedef T V __attribute__((ext_vector_type(2)));
+    nt_store(a + k, V{v0, v1});
 }
 // two 16-bit values as one 32-bit word, x in the low half (the order of the
 // pair types); composed with shifts because a bit copy of the pair type can
@@ -123,12 +130,20 @@ template <>
 struct Storage<double> {
     using T = double;
     __device__ static double2 load(const double *a, size_t k) { return *reinterpret_cast<const double2 *>(a + k); }
+    __device__ static double2 load_stream(const double *a, size_t k) {
+        const NtD2 v = __builtin_nontemporal_load(reinterpret_cast<const NtD2 *>(a + k));
+        return make_double2(v.x, v.y);
+    }
     __device__ static void store(double *a, size_t k, double x, double y) { nt_store(a + k, NtD2{x, y}); }
 };
 template <>
 struct Storage<float> {
     using T = float;
     __device__ static float2 load(const float *a, size_t k) { return *reinterpret_cast<const float2 *>(a + k); }
+    __device__ static float2 load_stream(const float *a, size_t k) {
+        const NtF2 v = __builtin_nontemporal_load(reinterpret_cast<const NtF2 *>(a + k));
+        return make_float2(v.x, v.y);
+    }
     __device__ static void store(float *a, size_t k, float x, float y) { nt_store(a + k, NtF2{x, y}); }
 };
 template <>
@@ -136,6 +151,11 @@ struct Storage<__half> {
     using T = float;
     __device__ static float2 load(const __half *a, size_t k) {
         return __half22float2(*reinterpret_cast<const __half2 *>(a + k));
+    }
+    __device__ static float2 load_stream(const __half *a, size_t k) {
+        const uint32_t u = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(a + k));
+        return make_float2(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(u >> 16))));
     }
     __device__ static void store(__half *a, size_t k, float x, float y) {
         nt_store(a + k, pack16(__half_as_ushort(__float2half_rn(x)), __half_as_ushort(__float2half_rn(y))));
@@ -146,6 +166,11 @@ struct Storage<__hip_bfloat16> {
     using T = float;
     __device__ static float2 load(const __hip_bfloat16 *a, size_t k) {
         return __bfloat1622float2(*reinterpret_cast<const __hip_bfloat162 *>(a + k));
+    }
+    __device__ static float2 load_stream(const __hip_bfloat16 *a, size_t k) {
+        const uint32_t u = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(a + k));
+        return make_float2(__bfloat162float(__ushort_as_bfloat16((unsigned short)(u & 0xffffu))),
+                           __bfloat162float(__ushort_as_bfloat16((unsigned short)(u >> 16))));
     }
     __device__ static void store(__hip_bfloat16 *a, size_t k, float x, float y) {
         nt_store(a + k, pack16(__bfloat16_as_ushort(__float2bfloat16(x)), __bfloat16_as_ushort(__float2bfloat16(y))));
@@ -737,6 +762,18 @@ struct RowView {
     }
 };
 
+// One row-aligned pull of direction i by a wavefront.  With c_ix = 0 it reads
+// whole lines that no other wavefront reads in this sweep (every slot has
+// exactly one puller), so it streams past the caches; with c_ix != 0 the
+// run straddles a line that the neighbouring wavefront reads too.
+template <int I, typename S>
+__device__ __forceinline__ Pair<Cmp<S>> load_pull(const S *__restrict__ at) {
+    if constexpr (cx(I) == 0)
+        return Storage<S>::load_stream(at, 0);
+    else
+        return Storage<S>::load(at, 0);
+}
+
 // f_i(x) = slot (i, x - c_i), row-aligned addressing
 template <typename S, typename T = Cmp<S>>
 __device__ __forceinline__ void pull_load_rows(const S *__restrict__ fin, const RowView<S> &rv, T (&f)[2][Q]) {
@@ -744,7 +781,7 @@ __device__ __forceinline__ void pull_load_rows(const S *__restrict__ fin, const 
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const char *row = base + rv.row(-cy(i), -cz(i)) * rv.prow + (size_t)i * RowView<S>::DB;
-        const Pair<T> v = load_pop(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]), 0);
+        const Pair<T> v = load_pull<i>(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]));
         f[0][i] = v.x;
         f[1][i] = v.y;
     });
@@ -759,7 +796,7 @@ __device__ __forceinline__ void pull_sum_rows(const S *__restrict__ fin, const R
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const char *row = base + rv.row(-cy(i), -cz(i)) * rv.prow + (size_t)i * RowView<S>::DB;
-        const Pair<T> v = load_pop(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]), 0);
+        const Pair<T> v = load_pull<i>(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]));
         s0 += v.x;
         s1 += v.y;
     });

@@ -111,8 +111,10 @@ __device__ __forceinline__ void density_body(const DevParams &P, const S *__rest
             m[0] = (double)dr[0] + P.rho_ref[0];
             m[1] = (double)dr[1] + P.rho_ref[1];
         }
-        store_pair(rho, sidx(0, n), dr[0], dr[1]);
-        store_pair(psi, sidx(0, n), psi_dev(dr[0], (T)P.psi_e[0], irho0), psi_dev(dr[1], (T)P.psi_e[1], irho0));
+        // read back by the collide sweep, after the rest of this sweep
+        store_pair_stream(rho, sidx(0, n), dr[0], dr[1]);
+        store_pair_stream(psi, sidx(0, n), psi_dev(dr[0], (T)P.psi_e[0], irho0),
+                          psi_dev(dr[1], (T)P.psi_e[1], irho0));
     }
     if (partial) {
 #pragma unroll
