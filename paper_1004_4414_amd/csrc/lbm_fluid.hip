@@ -214,7 +214,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
 // component; only its Psi - Psi(rho_ref) is stored (in the Psi array), since
 // every later use of a shell site's density goes through Psi.
 // ---------------------------------------------------------------------------
-constexpr int SHELL_THREADS = 64;  // one wavefront per sphere (a few hundred shell sites each)
+constexpr int SHELL_THREADS = 256;  // one block per sphere, a virtual-fluid site per thread
 template <typename T>
 __device__ __forceinline__ void shell_fill_body(const DevParams &P, const DevParticles &D,
                                                 const uint32_t *__restrict__ info, T *__restrict__ rho,
