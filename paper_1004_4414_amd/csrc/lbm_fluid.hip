@@ -97,17 +97,22 @@ __device__ __forceinline__ void density_body(const DevParams &P, const S *__rest
     unsigned n;
     int x, y, z;
     if (ROWS ? dense_site_rows(P, g, n, x, y, z) : dense_site(P, g, n, x, y, z)) {
+        // the pulls are issued before the class word arrives (every address is
+        // in the lattice); non-fluid sites discard the sum
+        T s0, s1;
+        if constexpr (ROWS) {
+            const RowView<S> rv(P, x, y, z);
+            pull_sum_rows(f, rv, s0, s1);
+        } else {
+            const NbrOffsets o(P, x, y, z);
+            pull_sum(f, n, o, s0, s1);
+        }
         const bool fluid = site_class(info[n]) == CLS_FLUID;
         const T irho0 = (T)P.inv_rho0;
         T dr[2] = {-(T)P.rho_ref[0], -(T)P.rho_ref[1]};
         if (fluid) {
-            if constexpr (ROWS) {
-                const RowView<S> rv(P, x, y, z);
-                pull_sum_rows(f, rv, dr[0], dr[1]);
-            } else {
-                const NbrOffsets o(P, x, y, z);
-                pull_sum(f, n, o, dr[0], dr[1]);
-            }
+            dr[0] = s0;
+            dr[1] = s1;
             m[0] = (double)dr[0] + P.rho_ref[0];
             m[1] = (double)dr[1] + P.rho_ref[1];
         }
