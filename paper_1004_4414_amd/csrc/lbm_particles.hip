@@ -689,10 +689,13 @@ __global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
 // solid map: every site inside sphere p (at its current position) proposes p;
 // the lowest index wins.  stage[] holds STAGE_NONE everywhere else.
 // ---------------------------------------------------------------------------
-// visits the sites inside sphere p at its current position, the block's
-// threads taking its box in scan order
-template <typename F>
-__device__ __forceinline__ void for_inside_sites(const DevParams &P, const DevParticles &D, int p, F &&visit) {
+__device__ __forceinline__ void map_mark_body(DevParams P, DevParticles D, int32_t *__restrict__ stage, const Grid &g) {
+    const int p = g.bid;
+    {  // the blocks also clear the coarse dirty cells of the previous step, a slice each
+        const int ncell = D.cgx * D.cgy * D.cgz;
+        const int per = (ncell + (int)g.nb - 1) / (int)g.nb;
+        for (int c = p * per + threadIdx.x; c < min(ncell, (p + 1) * per); c += BLOCK) D.dirty[c] = 0;
+    }
     int lo[3], ext[3];
     new_box(P, D, p, lo, ext);
     long long cq[3];
@@ -706,18 +709,8 @@ __device__ __forceinline__ void for_inside_sites(const DevParams &P, const DevPa
         int u[3], x, y, z;
         bw.site(k, P, u, x, y, z);
         const bool in = near ? inside_unwrapped(u, cq, r2q) : inside_sphere(x, y, z, cq, r2q, P.nx, P.ny, P.nz);
-        if (in) visit(site_of(x, y, z, P));
+        if (in) atomicMin(&stage[site_of(x, y, z, P)], p);
     }
-}
-
-__device__ __forceinline__ void map_mark_body(DevParams P, DevParticles D, int32_t *__restrict__ stage, const Grid &g) {
-    const int p = g.bid;
-    {  // the blocks also clear the coarse dirty cells of the previous step, a slice each
-        const int ncell = D.cgx * D.cgy * D.cgz;
-        const int per = (ncell + (int)g.nb - 1) / (int)g.nb;
-        for (int c = p * per + threadIdx.x; c < min(ncell, (p + 1) * per); c += BLOCK) D.dirty[c] = 0;
-    }
-    for_inside_sites(P, D, p, [&](auto n) { atomicMin(&stage[n], p); });
 }
 
 __global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage) {
@@ -935,11 +928,12 @@ __global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles 
 __device__ __forceinline__ void map_info_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
                                                     uint32_t *__restrict__ info, int32_t *__restrict__ stage, const Grid &g) {
     const int p = g.bid;
+    int lo[3], ext[3];
+    int V;
     if (D.changed[p]) {
-        int lo[3], ext[3];
         union_box(P, D, p, 1, lo, ext);
         const BoxWalk bw(P, lo, ext);
-        const int V = bw.size();
+        V = bw.size();
         for (int k = threadIdx.x; k < V; k += BLOCK) {
             int u[3], x, y, z;
             bw.site(k, P, u, x, y, z);
@@ -947,10 +941,14 @@ __device__ __forceinline__ void map_info_body(DevParams P, DevParticles D, const
             info[n] = compute_info_at(n, x, y, z, P, owner);
         }
     }
-    // the marks of p are on the sites inside it (the positions have not
-    // changed since the marking), and every marked site is inside the sphere
-    // that marked it, so clearing those leaves STAGE_NONE everywhere
-    for_inside_sites(P, D, p, [&](auto n) { stage[n] = STAGE_NONE; });
+    new_box(P, D, p, lo, ext);
+    const BoxWalk bw(P, lo, ext);
+    V = bw.size();
+    for (int k = threadIdx.x; k < V; k += BLOCK) {
+        int u[3], x, y, z;
+        bw.site(k, P, u, x, y, z);
+        stage[site_of(x, y, z, P)] = STAGE_NONE;
+    }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
