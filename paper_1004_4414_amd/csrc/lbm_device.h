@@ -109,8 +109,9 @@ __device__ __forceinline__ void store_pair(T *__restrict__ a, size_t k, T v0, T 
 // reads (the x-shifted pulls and the Psi neighbours).  load_stream is the
 // same hint on a load whose lines no other wavefront of the sweep reads;
 // store_keep is a store with the default policy, for the scattered 8-byte
-// bounce-back writes, whose partly written lines are better left in the
-// caches until the next sweep reads them.
+// bounce-back writes of the sphere links, whose partly written lines are
+// better left in the caches until the next sweep reads them (wall links
+// fill whole planes and keep the hint).
 typedef float NtF2 __attribute__((ext_vector_type(2)));
 typedef double NtD2 __attribute__((ext_vector_type(2)));
 template <typename V, typename P>
