@@ -174,6 +174,59 @@ def test_reduced_precision_storage_error_bounds(precision):
         compare_fields(gpu, ref, p, tol_rho=b["rho10"], tol_u=b["u10"])
 
 
+_CROP = {}
+
+
+def bijel256_crop(w=64):
+    """The [0, w)^3 sub-box of the 256^3 workload's initial state and the spheres
+    lying wholly inside it (one site of margin): the populations come from the
+    oracle's own initialisation of the full box, run periodic at w^3."""
+    if w not in _CROP:
+        p, parts, _, _ = W.config("bijel256")
+        big = Oracle(p)
+        f = big.populations()
+        f0 = np.ascontiguousarray(f[:, :, :w, :w, :w])
+        del f, big
+        r = float(parts["radius"].max())
+        keep = np.all((parts["pos"] >= r + 1.0) & (parts["pos"] <= w - r - 1.0), axis=1)
+        sel = {k: np.ascontiguousarray(v[keep]) for k, v in parts.items()}
+        _CROP[w] = (dict(p, nx=w, ny=w, nz=w), sel, f0)
+    return _CROP[w]
+
+
+def test_bijel256_crop_every_precision_against_the_fp64_oracle():
+    """The 64^3 crop of the 256^3 workload, each storage started from the same
+    FP64 populations as the oracle (no shadowing, so the storage rounding of
+    the initial state is part of the error): FP32 within the FP32 bar, FP16
+    and BF16 within their stated bounds, bookkeeping exact, after 1 and 10
+    steps."""
+    pc, sel, f0 = bijel256_crop()
+    assert len(sel["radius"]) >= 20
+    ref = Oracle(pc)
+    assert ref.add_particles(sel) == 0
+    ref.set_populations(f0)
+    gpus = {}
+    for prec in ("fp32", "fp16", "bf16"):
+        g = lbm().Lattice(pc, precision=prec)
+        g.add_particles(sel)
+        g.set_populations(f0)
+        gpus[prec] = g
+    done = 0
+    for n, tag in ((1, "1"), (10, "10")):
+        ref.step(n - done)
+        for g in gpus.values():
+            g.step(n - done)
+        done = n
+        for prec, g in gpus.items():
+            if prec == "fp32":
+                tr, tu = 1e-5, 1e-5
+            else:
+                tr, tu = REDUCED_BOUNDS[prec]["rho" + tag], REDUCED_BOUNDS[prec]["u" + tag]
+            e_rho, e_u = compare_fields(g, ref, pc, tol_rho=tr, tol_u=tu)
+            compare_bookkeeping(g, ref)
+            print(f"crop64 {prec} after {n} steps: density {e_rho:.2e}, velocity {e_u:.2e}", flush=True)
+
+
 def test_reduced_precision_runs_only_the_two_pass_sweep():
     L = lbm()
     p = W.params(nx=32, ny=32, nz=32)
