@@ -107,7 +107,11 @@ __device__ __forceinline__ void store_pair(T *__restrict__ a, size_t k, T v0, T 
 // after the caches have turned over, so every population store carries the
 // non-temporal hint: it does not displace the lines that the sweep still
 // reads (the x-shifted pulls and the Psi neighbours).  load_stream is the
-// same hint on a load whose lines no other wavefront of the sweep reads.
+// same hint on a load whose lines no other wavefront of the sweep reads;
+// store_keep is a store with the default policy, for the scattered 8-byte
+// bounce-back writes of the sphere links, whose partly written lines are
+// better left in the caches until the next sweep reads them (wall links
+// fill whole planes and keep the hint).
 typedef float NtF2 __attribute__((ext_vector_type(2)));
 typedef double NtD2 __attribute__((ext_vector_type(2)));
 template <typename V, typename P>
@@ -135,6 +139,9 @@ struct Storage<double> {
         return make_double2(v.x, v.y);
     }
     __device__ static void store(double *a, size_t k, double x, double y) { nt_store(a + k, NtD2{x, y}); }
+    __device__ static void store_keep(double *a, size_t k, double x, double y) {
+        *reinterpret_cast<double2 *>(a + k) = make_double2(x, y);
+    }
 };
 template <>
 struct Storage<float> {
@@ -145,6 +152,9 @@ struct Storage<float> {
         return make_float2(v.x, v.y);
     }
     __device__ static void store(float *a, size_t k, float x, float y) { nt_store(a + k, NtF2{x, y}); }
+    __device__ static void store_keep(float *a, size_t k, float x, float y) {
+        *reinterpret_cast<float2 *>(a + k) = make_float2(x, y);
+    }
 };
 template <>
 struct Storage<__half> {
@@ -159,6 +169,9 @@ struct Storage<__half> {
     }
     __device__ static void store(__half *a, size_t k, float x, float y) {
         nt_store(a + k, pack16(__half_as_ushort(__float2half_rn(x)), __half_as_ushort(__float2half_rn(y))));
+    }
+    __device__ static void store_keep(__half *a, size_t k, float x, float y) {
+        *reinterpret_cast<__half2 *>(a + k) = __floats2half2_rn(x, y);
     }
 };
 template <>
@@ -175,6 +188,9 @@ struct Storage<__hip_bfloat16> {
     __device__ static void store(__hip_bfloat16 *a, size_t k, float x, float y) {
         nt_store(a + k, pack16(__bfloat16_as_ushort(__float2bfloat16(x)), __bfloat16_as_ushort(__float2bfloat16(y))));
     }
+    __device__ static void store_keep(__hip_bfloat16 *a, size_t k, float x, float y) {
+        *reinterpret_cast<__hip_bfloat162 *>(a + k) = __float22bfloat162_rn(make_float2(x, y));
+    }
 };
 template <typename S>
 using Cmp = typename Storage<S>::T;
@@ -185,6 +201,10 @@ __device__ __forceinline__ Pair<Cmp<S>> load_pop(const S *__restrict__ a, size_t
 template <typename S>
 __device__ __forceinline__ void store_pop(S *__restrict__ a, size_t k, Cmp<S> v0, Cmp<S> v1) {
     Storage<S>::store(a, k, v0, v1);
+}
+template <typename S>
+__device__ __forceinline__ void store_pop_keep(S *__restrict__ a, size_t k, Cmp<S> v0, Cmp<S> v1) {
+    Storage<S>::store_keep(a, k, v0, v1);
 }
 __host__ __device__ __forceinline__ size_t padded_sites(long long N) { return (size_t)((N + VB - 1) / VB) * VB; }
 

@@ -327,7 +327,7 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
                 const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
                 const T wz = (T)(6.0 * zeta(i) * cub);
                 const T w0 = wz * (r0[u] + ref0), w1 = wz * (r1[u] + ref1);
-                store_pop(fout, pidx(0, j, ss), raw0[u] - w0, raw1[u] - w1);
+                store_pop_keep(fout, pidx(0, j, ss), raw0[u] - w0, raw1[u] - w1);
                 const double sum = (2.0 * ((double)raw0[u] + zeta(i) * P.rho_ref[0]) - (double)w0) +
                                    (2.0 * ((double)raw1[u] + zeta(i) * P.rho_ref[1]) - (double)w1);
                 const double dp[3] = {cx(i) * sum, cy(i) * sum, cz(i) * sum};
