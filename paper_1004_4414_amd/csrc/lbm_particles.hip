@@ -200,7 +200,8 @@ __device__ __forceinline__ void new_box(const DevParams &P, const DevParticles &
 // s), and the sphere gains the momentum c_i sum_c (2 f*_i - w^c).
 // ---------------------------------------------------------------------------
 // The virtual-fluid sites are taken in chunks of BLOCK, one per thread; the
-// links of a chunk are numbered by a block scan of their counts and then
+// links of a chunk are numbered by a block scan of their counts, each site
+// writes its links into an LDS table at its offset, and they are then
 // handled LINKS_PER_PASS per thread with all their loads issued together.
 constexpr int LINKS_PER_PASS = 4;
 
@@ -209,9 +210,10 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
                                                                 const T *__restrict__ rho, const T *__restrict__ fsc,
                                                                 const uint32_t *__restrict__ info, const Grid &g) {
     __shared__ double lds[6 * (BLOCK / 64)];
-    __shared__ int pre[BLOCK + 1];     // exclusive prefix of the link counts of the chunk's sites
-    __shared__ uint32_t fmask[BLOCK];  // fluid-neighbour masks of the chunk's sites
+    // the chunk's links in their numbering: (chunk index of the site) << 5 | j
+    __shared__ uint16_t lk[BLOCK * (Q - 1)];
     __shared__ unsigned sites[BLOCK];
+    __shared__ int sx[BLOCK], sy[BLOCK], sz[BLOCK];
     __shared__ int wtot[BLOCK / 64];
     const int p = g.bid, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double v[6] = {0, 0, 0, 0, 0, 0};
@@ -227,6 +229,7 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
         const int k = c0 + t;
         uint32_t fl = 0;
         unsigned s = 0;
+        int x = 0, y = 0, z = 0;
         if (k < ns) {
             s = (unsigned)D.shell[soff + k];
             const uint32_t inf = info[s];
@@ -240,7 +243,6 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
             } else {
                 for (int a = 0; a < 3; ++a) F[a] = (double)fsc[vidx(a, s)];
             }
-            int x, y, z;
             site_xyz(s, P, x, y, z);
             const double r[3] = {minimg(x - R[0], L[0]), minimg(y - R[1], L[1]), minimg(z - R[2], L[2])};
             v[0] += F[0];
@@ -265,14 +267,18 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
             if (w < wave) before += wtot[w];
             total += wtot[w];
         }
-        pre[t] = before + inc - cnt;
-        fmask[t] = fl;
+        // link numbers before + inc - cnt ... are this site's links, its fluid
+        // neighbours j in increasing order
+        for (int pos = before + inc - cnt; fl; fl &= fl - 1) lk[pos++] = (uint16_t)((t << 5) | (__ffs(fl) - 1));
         sites[t] = s;
+        sx[t] = x;
+        sy[t] = y;
+        sz[t] = z;
         __syncthreads();
         // ---- the chunk's links, LINKS_PER_PASS per thread per pass
         for (int l0 = t; l0 < total; l0 += LINKS_PER_PASS * BLOCK) {
             unsigned sl[LINKS_PER_PASS], ml[LINKS_PER_PASS];
-            int jl[LINKS_PER_PASS];
+            int jl[LINKS_PER_PASS], cl[LINKS_PER_PASS];
             bool ok[LINKS_PER_PASS];
             T r0[LINKS_PER_PASS], r1[LINKS_PER_PASS], raw0[LINKS_PER_PASS], raw1[LINKS_PER_PASS];
 #pragma unroll
@@ -282,23 +288,15 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
                 sl[u] = 0;
                 ml[u] = 0;
                 jl[u] = 1;
+                cl[u] = 0;
                 if (ok[u]) {
-                    // the site: the largest chunk index whose prefix is <= l
-                    int lo = 0, hi = BLOCK - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (pre[mid] <= l) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    uint32_t m = fmask[lo];
-                    for (int q = l - pre[lo]; q > 0; --q) m &= m - 1;
-                    const int j = __ffs(m) - 1;
-                    const unsigned ss = sites[lo];
-                    int x, y, z;
-                    site_xyz(ss, P, x, y, z);
-                    sl[u] = ss;
+                    const unsigned e = lk[l];
+                    const int c = (int)(e >> 5), j = (int)(e & 31u);
+                    const int xs = sx[c], ys = sy[c], zs = sz[c];
+                    sl[u] = sites[c];
                     jl[u] = j;
-                    ml[u] = (unsigned)site_of(wrapc(x + cx(j), P.nx), wrapc(y + cy(j), P.ny), wrapc(z + cz(j), P.nz), P);
+                    cl[u] = c;
+                    ml[u] = (unsigned)site_of(wrapc(xs + cx(j), P.nx), wrapc(ys + cy(j), P.ny), wrapc(zs + cz(j), P.nz), P);
                 }
             }
 #pragma unroll
@@ -317,8 +315,7 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
                 // into slot (j, s), where x reads direction j at the next step
                 const int j = jl[u], i = opp(j);
                 const unsigned ss = sl[u];
-                int x, y, z;
-                site_xyz(ss, P, x, y, z);
+                const int x = sx[cl[u]], y = sy[cl[u]], z = sz[cl[u]];
                 // lever arm at the link midpoint s - c_i/2 = s + c_j/2
                 const double rb[3] = {minimg(x + 0.5 * cx(j) - R[0], L[0]), minimg(y + 0.5 * cy(j) - R[1], L[1]),
                                       minimg(z + 0.5 * cz(j) - R[2], L[2])};
