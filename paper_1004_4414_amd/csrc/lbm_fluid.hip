@@ -107,7 +107,8 @@ __device__ __forceinline__ void density_body(const DevParams &P, const S *__rest
             const NbrOffsets o(P, x, y, z);
             pull_sum(f, n, o, s0, s1);
         }
-        const bool fluid = site_class(info[n]) == CLS_FLUID;
+        // the class word is read once per sweep: streamed like the pulls
+        const bool fluid = site_class(__builtin_nontemporal_load(info + n)) == CLS_FLUID;
         const T irho0 = (T)P.inv_rho0;
         T dr[2] = {-(T)P.rho_ref[0], -(T)P.rho_ref[1]};
         if (fluid) {
@@ -335,7 +336,7 @@ __device__ __forceinline__ void collide_body(const DevParams &P, const S *__rest
         pull_load(fin, n, o, f);
         load_psi_neighbours(psi, n, o, pn, own_psi);
     }
-    const uint32_t inf = info[n];
+    const uint32_t inf = __builtin_nontemporal_load(info + n);  // read once per sweep
     hold_loads(f[0]);
     hold_loads(f[1]);
     hold_loads(pn[0]);
