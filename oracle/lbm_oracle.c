@@ -116,6 +116,7 @@ typedef struct {
     long covered_last, uncovered_last;
     double covered_mass[NCOMP], refill_mass[NCOMP]; /* running totals */
     double wall_mass[NCOMP]; /* running total of the mass the moving-wall term adds */
+    int runaway; /* a sphere moved a lattice unit or more in one step (or left the reals) */
 } orc_state;
 
 /* ------------------------------------------------------------------------- */
@@ -699,6 +700,9 @@ static void move_particles(orc_state *s) {
                 s->U[3 * p + a] = vs[3 * p + a];
                 s->W[3 * p + a] += s->Ttot[3 * p + a] / s->inertia[p];
             }
+            /* the map update takes sub-lattice moves per step: a faster or
+               non-finite sphere is outside the scheme and stops the run */
+            if (!(fabs(s->U[3 * p + a]) < 1.0)) s->runaway = 1;
             double r = s->R[3 * p + a] + s->U[3 * p + a];
             if (r >= L[a]) r -= L[a];
             if (r < 0.0) r += L[a];
@@ -832,8 +836,10 @@ static void step_once(orc_state *s) {
     ++s->step;
 }
 
-void orc_step(orc_state *s, int nsteps) {
-    for (int k = 0; k < nsteps; ++k) step_once(s);
+/* 0, or -1 once a sphere has run away (the state is then left as it is) */
+int orc_step(orc_state *s, int nsteps) {
+    for (int k = 0; k < nsteps && !s->runaway; ++k) step_once(s);
+    return s->runaway ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -70,6 +70,7 @@ def lib():
         L.orc_destroy.argtypes = [vp]
         L.orc_add_particles.restype = ctypes.c_int
         L.orc_add_particles.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp, dp, dp, ip]
+        L.orc_step.restype = ctypes.c_int
         L.orc_step.argtypes = [vp, ctypes.c_int]
         L.orc_get_populations.argtypes = [vp, dp]
         L.orc_set_populations.argtypes = [vp, dp]
@@ -181,7 +182,8 @@ class Oracle:
 
     # -- stepping ------------------------------------------------------------
     def step(self, n=1):
-        lib().orc_step(self._h, int(n))
+        if lib().orc_step(self._h, int(n)) != 0:
+            raise RuntimeError("a sphere moved a lattice unit or more in one step: outside the scheme")
 
     # -- state ---------------------------------------------------------------
     def populations(self):

@@ -318,6 +318,38 @@ def test_moving_spheres_fp64_end_to_end_and_conservation():
     assert o1["covered_total"] == ref.counts()["covered_total"] > 0
 
 
+def test_tiny_spheres_fp64_end_to_end():
+    """Degenerate spheres: radius 0.6 centred in a lattice cube covers no site
+    at all (no virtual fluid, no links); radius 0.6 or 0.9 centred on a site
+    covers that site alone, a virtual-fluid site with 18 fluid neighbours and
+    so 18 links; radius 1.2 covers 7 sites.  They move across sites, so sites
+    are covered and uncovered.  FP64 end to end, bookkeeping exact."""
+    p = W.params(nx=20, ny=18, nz=16, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=12)
+    pos = [[4.5, 4.5, 4.5], [10.0, 4.0, 4.0], [15.0, 9.0, 8.0], [5.0, 12.0, 11.0], [12.3, 13.6, 5.2]]
+    vel = [[0.03, 0.02, 0.0], [0.0, 0.03, -0.02], [-0.03, 0.0, 0.02], [0.02, -0.03, 0.01], [-0.02, 0.02, 0.03]]
+    # dense enough that 18 links on one site do not push a sphere a lattice unit per step
+    parts = W.make_particles(pos, [0.6, 0.6, 0.9, 1.2, 1.5], vel=vel, density=[30.0, 30.0, 10.0, 4.0, 2.0],
+                             color=[0.0, 0.05, -0.05, 0.0, 0.02])
+    gpu = lbm().Lattice(p, precision="fp64")
+    gpu.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    compare_bookkeeping(gpu, ref)
+    links, shell = ref.particle_counts()
+    assert links[0] == 0 and shell[0] == 0  # the empty sphere
+    assert links[1] == 18 and shell[1] == 1 and links[2] == 18 and shell[2] == 1
+    gpu.step(60)
+    ref.step(60)
+    compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
+    compare_bookkeeping(gpu, ref)
+    Pg, Pr = gpu.particles(), ref.particles()
+    for k in ("R", "U", "W", "Ffluid", "Tfluid", "P", "PT"):
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+    c, o = ref.counts(), gpu.observables()
+    assert o["covered_total"] == c["covered_total"] > 0
+    assert o["uncovered_total"] == c["uncovered_total"] > 0
+
+
 @pytest.mark.parametrize("mode,order", [(0, 3), (1, 2), (0, 2)])
 def test_velocity_and_equilibrium_variants_fp64(mode, order):
     p = W.params(nx=16, ny=12, nz=10, rho_init=(0.5, 0.4), noise_amp=0.02, g_br=0.06, seed=8,

@@ -286,3 +286,15 @@ def test_stiff_lubrication_network_dissipates_and_conserves_momentum():
         ke = ke_new
         assert np.allclose((m * P["U"]).sum(axis=0), mom0, rtol=0, atol=1e-16)
     assert np.abs(orc.particles()["U"][:, 0]).max() < 0.002
+
+
+def test_runaway_sphere_stops_the_oracle():
+    """A sphere that moves a lattice unit or more in one step is outside the
+    scheme (the map update takes sub-lattice moves): the oracle stops with an
+    error instead of stepping on."""
+    p = W.params(nx=16, ny=16, nz=16, noise_amp=0.0, g_br=0.0, seed=3)
+    ref = O.Oracle(p)
+    assert ref.add_particles(W.make_particles([[8.0, 8.0, 8.0]], 2.0, vel=[[1.5, 0.0, 0.0]], prescribed=1)) == 0
+    with pytest.raises(RuntimeError):
+        ref.step(3)
+    assert ref.counts()["step"] == 1
