@@ -350,6 +350,33 @@ def test_tiny_spheres_fp64_end_to_end():
     assert o["uncovered_total"] == c["uncovered_total"] > 0
 
 
+def test_largest_allowed_spheres_fp64_end_to_end():
+    """Spheres at the largest radius the interface accepts (a quarter of the
+    shortest axis) in a ragged box, one of them across the periodic boundary,
+    moving and rotating: FP64 end to end, bookkeeping exact."""
+    p = W.params(nx=34, ny=30, nz=28, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=21)
+    r = 28 / 4.0
+    pos = [[8.3, 7.6, 7.2], [25.4, 22.1, 26.5]]
+    parts = W.make_particles(pos, r, vel=[[0.02, -0.01, 0.015], [-0.015, 0.02, -0.01]],
+                             omega=[[0.0, 0.004, -0.003], [0.003, 0.0, 0.002]], density=1.2, color=[0.04, -0.04])
+    gpu = lbm().Lattice(p, precision="fp64")
+    gpu.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    with pytest.raises(lbm().LBError):  # just above the limit is refused
+        g2 = lbm().Lattice(p, precision="fp64")
+        g2.add_particles(W.make_particles([[16.0, 15.0, 14.0]], r + 0.01))
+    gpu.step(40)
+    ref.step(40)
+    compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
+    compare_bookkeeping(gpu, ref)
+    Pg, Pr = gpu.particles(), ref.particles()
+    for k in ("R", "U", "W", "Ffluid", "Tfluid", "P", "PT"):
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+    c, o = ref.counts(), gpu.observables()
+    assert o["covered_total"] == c["covered_total"] > 0
+
+
 @pytest.mark.parametrize("mode,order", [(0, 3), (1, 2), (0, 2)])
 def test_velocity_and_equilibrium_variants_fp64(mode, order):
     p = W.params(nx=16, ny=12, nz=10, rho_init=(0.5, 0.4), noise_amp=0.02, g_br=0.06, seed=8,
