@@ -113,6 +113,11 @@ void build_shared(lb_batch *b, lbm::BatchLaunch &L) {
     for (int par = 0; par < 2; ++par) L.plan[par] = BatchPlan{dt + (size_t)par * nm, ds, nm};
     for (int k = 0; k < BM_COUNT; ++k) L.total[k] = start[(size_t)k * (nm + 1) + nm];
     L.nm = nm;
+    L.any_rows = L.any_flat = 0;
+    for (int i = 0; i < nm; ++i) {
+        if (b->m[i]->prm.nx % (int)VB == 0) L.any_rows = 1;
+        else L.any_flat = 1;
+    }
     L.prm = b->m[0]->prm;
 }
 

@@ -651,15 +651,16 @@ void launch_sums(lb_handle *h, const void *f) {
 // ---------------------------------------------------------------------------
 // Batched launches of the fluid stages (see lbm_particles.hip)
 // ---------------------------------------------------------------------------
-template <typename S>
+// The sweeps come in a row-aligned and a general instance, launched for the
+// members of their kind only (the blocks of the others return at once), so
+// neither carries the other's registers.
+template <typename S, bool ROWS>
 __global__ __launch_bounds__(BLOCK) void kb_density(BatchPlan B) {
     using T = Cmp<S>;
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_DENSE, g)];
-    if (M.rows)
-        density_body<S, true>(M.P, (const S *)M.fin, M.info, (T *)M.rho, (T *)M.psi, M.partial, g);
-    else
-        density_body<S, false>(M.P, (const S *)M.fin, M.info, (T *)M.rho, (T *)M.psi, M.partial, g);
+    if ((M.rows != 0) != ROWS) return;
+    density_body<S, ROWS>(M.P, (const S *)M.fin, M.info, (T *)M.rho, (T *)M.psi, M.partial, g);
 }
 __global__ __launch_bounds__(FIN_THREADS) void kb_finalize_mass(BatchPlan B) {
     const int m = (int)(blockIdx.x / FIN_BLOCKS);
@@ -673,15 +674,13 @@ __global__ __launch_bounds__(SHELL_THREADS) void kb_shell_fill(BatchPlan B) {
     const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
     shell_fill_body(M.P, M.D, M.info, (T *)M.rho, (T *)M.psi, g);
 }
-template <typename S, typename Mo>
+template <typename S, typename Mo, bool ROWS>
 __global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void kb_collide_stream(BatchPlan B) {
     using T = Cmp<S>;
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_DENSE, g)];
-    if (M.rows)
-        collide_body<S, Mo, true>(M.P, (const S *)M.fin, (S *)M.fout, (const T *)M.psi, M.info, (T *)M.fsc, g);
-    else
-        collide_body<S, Mo, false>(M.P, (const S *)M.fin, (S *)M.fout, (const T *)M.psi, M.info, (T *)M.fsc, g);
+    if ((M.rows != 0) != ROWS) return;
+    collide_body<S, Mo, ROWS>(M.P, (const S *)M.fin, (S *)M.fout, (const T *)M.psi, M.info, (T *)M.fsc, g);
 }
 
 // density, mass total, virtual fluid and collide sweep of every member
@@ -691,10 +690,14 @@ void launch_batch_fluid(const BatchLaunch &L, int parity, hipStream_t s) {
     with_storage(L.prm, [&](auto tag) {
         using S = typename decltype(tag)::type;
         using T = Cmp<S>;
-        kb_density<S><<<nd, BLOCK, 0, s>>>(B);
+        if (L.any_rows) kb_density<S, true><<<nd, BLOCK, 0, s>>>(B);
+        if (L.any_flat) kb_density<S, false><<<nd, BLOCK, 0, s>>>(B);
         kb_finalize_mass<<<(unsigned)(L.nm * FIN_BLOCKS), FIN_THREADS, 0, s>>>(B);
         if (L.total[BM_SPHERE] > 0) kb_shell_fill<T><<<(unsigned)L.total[BM_SPHERE], SHELL_THREADS, 0, s>>>(B);
-        with_model(L.prm, [&](auto m) { kb_collide_stream<S, decltype(m)><<<nd, BLOCK, 0, s>>>(B); });
+        with_model(L.prm, [&](auto m) {
+            if (L.any_rows) kb_collide_stream<S, decltype(m), true><<<nd, BLOCK, 0, s>>>(B);
+            if (L.any_flat) kb_collide_stream<S, decltype(m), false><<<nd, BLOCK, 0, s>>>(B);
+        });
     });
     LB_HIP_CHECK(hipGetLastError());
 }

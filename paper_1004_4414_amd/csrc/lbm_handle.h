@@ -127,6 +127,7 @@ struct BatchLaunch {
     BatchPlan plan[2];       // device tables for the two step parities (fin / fout swapped)
     int total[BM_COUNT];     // blocks of each map over all members
     int nm;
+    int any_rows, any_flat;  // members with row-aligned addressing (nx % 64 == 0), and without
     lb_params prm;           // precision and collision model shared by the members
 };
 void launch_batch_fluid(const BatchLaunch &L, int parity, hipStream_t s);
