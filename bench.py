@@ -323,6 +323,12 @@ def main():
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "mflups_fluid": round(mlups * fluid_sites / N, 1),
+        # the whole step as one sweep of the algorithmic bytes per site
+        "step_effective": {
+            "gbs": round(mlups * bps / 1e3, 1),
+            "frac_of_peak": round(mlups * bps / 1e3 / HBM_PEAK_GBS, 4),
+            "frac_of_copy": round(mlups * bps / 1e3 / copy_gbs, 4),
+        },
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
