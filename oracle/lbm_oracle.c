@@ -88,6 +88,7 @@ typedef struct {
     double c0_mass_corr;   /* C_0 of Eq. (31) */
     double k_hertz, lub_hc, lub_hmin;
     int32_t virtual_fluid; /* 1: paper's virtual fluid (Sec. IV); 0: empty particles */
+    int32_t lub_mode;      /* 0: Eq. (22) as an explicit force; 1: pair impulses (see move_particles) */
 } orc_params;
 
 typedef struct {
@@ -302,10 +303,16 @@ int orc_add_particles(orc_state *s, int n, const double *pos, const double *vel,
     int minL = s->nx < s->ny ? s->nx : s->ny;
     if (s->nz < minL) minL = s->nz;
     const double L[3] = {s->nx, s->ny, s->nz};
+    /* spheres need periodic boxes: walls and spheres are not combined */
+    if (n > 0 && s->p.wall_axis >= 0) return -1;
     for (int k = 0; k < n; ++k) {
         if (!(radius[k] > 0.0) || radius[k] > 0.25 * minL || !(density[k] > 0.0)) return -1;
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
             if (!(pos[3 * k + a] >= 0.0 && pos[3 * k + a] < L[a])) return -1;
+            /* the sphere's bounding box with its neighbour ring, 2 ceil(r) + 7
+               sites, must fit in one period of every axis */
+            if (2 * (int)ceil(radius[k]) + 7 > (int)L[a]) return -1;
+        }
     }
     /* pairwise overlap among new and existing spheres (minimum image) */
     int tot = s->np + n;
@@ -598,17 +605,22 @@ static void shan_chen_on_particles(orc_state *s) {
 /* is -c rhat [rhat.(u_1-u_2)] with c = 6 pi nu rho_0 (r_a r_b/(r_a+r_b))^2    */
 /* (1/h - 1/h_c) for gaps h = |r| - r_a - r_b below h_c, with h clamped at     */
 /* h_min; nu is the mean of c_s^2 (tau^c - 1/2).                               */
-/* Reading (integration): the paper gives no scheme for this velocity-       */
-/* dependent force, and applied explicitly at the h_min clamp it is stiffer   */
-/* than one step can carry once a sphere has close neighbours at particle    */
-/* densities near the fluid's.  It is applied as pair impulses: with v* the  */
-/* velocities after every other force, w = n.(v*_p - v*_q) the approach      */
-/* speed and k_p the number of lubrication contacts of sphere p, the pair    */
-/* exchanges J = c w / (1 + c (k_p/m_p + k_q/m_q)) along n, equal and        */
-/* opposite.  For an isolated pair (k = 1) this is the backward-Euler        */
-/* solution of the pair's lubrication; sharing each sphere's mass among its  */
-/* contacts keeps the simultaneous impulses from overshooting.  A sphere     */
-/* with prescribed motion counts as infinitely heavy.                        */
+/* Reading (integration; the paper names a leap-frog and no scheme for this   */
+/* velocity-dependent force), two modes:                                     */
+/*  lub_mode 0: Eq. (22) as printed, an explicit force: u_1 - u_2 are the     */
+/*    latest velocities U(t-1/2), and the force joins every other force in    */
+/*    U(t+1/2) = U(t-1/2) + F/m.  For an isolated pair the approach speed     */
+/*    becomes w (1 - c (1/m_1 + 1/m_2)): with c (1/m_1 + 1/m_2) > 2, which    */
+/*    happens at the h_min clamp for particle densities near the fluid's,     */
+/*    it reverses and grows every step.                                      */
+/*  lub_mode 1 (default): pair impulses.  With v* the velocities after every  */
+/*    other force, w = n.(v*_p - v*_q) the approach speed and k_p the number  */
+/*    of lubrication contacts of sphere p, the pair exchanges                */
+/*    J = c w / (1 + c (k_p/m_p + k_q/m_q)) along n, equal and opposite.  For */
+/*    an isolated pair (k = 1) this is the backward-Euler solution of the     */
+/*    pair's lubrication; sharing each sphere's mass among its contacts keeps */
+/*    the simultaneous impulses from overshooting.                           */
+/* A sphere with prescribed motion counts as infinitely heavy.                */
 /* ------------------------------------------------------------------------- */
 static void move_particles(orc_state *s) {
     const double L[3] = {s->nx, s->ny, s->nz};
@@ -661,12 +673,23 @@ static void move_particles(orc_state *s) {
                 ++ncon;
             }
         }
+    if (s->p.lub_mode == 0)
+        for (int k = 0; k < ncon; ++k) {
+            const int p = cp[k], q = cq[k];
+            const double *n = cn + 3 * k;
+            double w = 0.0;
+            for (int a = 0; a < 3; ++a) w += n[a] * (s->U[3 * p + a] - s->U[3 * q + a]);
+            for (int a = 0; a < 3; ++a) {
+                s->Ftot[3 * p + a] -= cc[k] * w * n[a];
+                s->Ftot[3 * q + a] += cc[k] * w * n[a];
+            }
+        }
     /* velocities after every other force */
     double *vs = malloc(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
     for (int p = 0; p < np; ++p)
         for (int a = 0; a < 3; ++a)
             vs[3 * p + a] = s->U[3 * p + a] + (s->prescribed[p] ? 0.0 : s->Ftot[3 * p + a] / s->mass[p]);
-    if (ncon > 0) {
+    if (ncon > 0 && s->p.lub_mode != 0) {
         int *kc = calloc((size_t)np, sizeof(int));
         for (int k = 0; k < ncon; ++k) {
             ++kc[cp[k]];

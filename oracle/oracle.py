@@ -26,7 +26,7 @@ DEFAULTS = dict(
     velocity_mode=1, eq_order=3,
     rho_init=(0.35, 0.35), noise_amp=0.01, seed=1,
     body_accel=(0.0, 0.0, 0.0), wall_axis=-1, wall_vel=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
-    c0_mass_corr=0.0, k_hertz=100.0, lub_hc=2.0 / 3.0, lub_hmin=0.1,
+    c0_mass_corr=0.0, k_hertz=100.0, lub_hc=2.0 / 3.0, lub_hmin=0.1, lub_mode=1,
     virtual_fluid=1,
 )
 
@@ -42,7 +42,7 @@ class _Params(ctypes.Structure):
         ("wall_vel", (ctypes.c_double * 3) * 2),
         ("c0_mass_corr", ctypes.c_double), ("k_hertz", ctypes.c_double),
         ("lub_hc", ctypes.c_double), ("lub_hmin", ctypes.c_double),
-        ("virtual_fluid", ctypes.c_int32),
+        ("virtual_fluid", ctypes.c_int32), ("lub_mode", ctypes.c_int32),
     ]
 
 
@@ -136,6 +136,7 @@ class Oracle:
         s.c0_mass_corr, s.k_hertz = p["c0_mass_corr"], p["k_hertz"]
         s.lub_hc, s.lub_hmin = p["lub_hc"], p["lub_hmin"]
         s.virtual_fluid = int(p["virtual_fluid"])
+        s.lub_mode = int(p["lub_mode"])
         self.shape = (s.nz, s.ny, s.nx)
         self.N = s.nx * s.ny * s.nz
         self._h = lib().orc_create(ctypes.byref(s))

@@ -62,14 +62,16 @@ def test_periodic_box_conserves_mass_and_momentum():
     assert np.abs(orc.populations() - O.Oracle(p).populations()).max() > 1e-3
 
 
-def test_uniform_flow_is_preserved():
-    """A uniform state moving at u0 is a fixed point (Galilean check of the
-    common-velocity collision)."""
+@pytest.mark.parametrize("velocity_mode", [0, 1])
+def test_uniform_flow_is_preserved(velocity_mode):
+    """A uniform state whose two components move together at u0 is a fixed
+    point of the step (Galilean check) under either equilibrium velocity of
+    Eq. (6): the common velocity (mode 0) and the per-component one (mode 1)."""
     rho = np.zeros((2, 4, 4, 4))
     rho[0], rho[1] = 0.5, 0.25
     u = np.zeros((4, 4, 4, 3))
     u[...] = (0.02, -0.01, 0.005)
-    orc = _uniform(4, 4, 4, g_br=0.05)
+    orc = _uniform(4, 4, 4, g_br=0.05, tau=(0.8, 1.3), velocity_mode=velocity_mode)
     orc.set_populations(equilibrium_field(rho, u))
     orc.step(10)
     fl = orc.fields()
@@ -77,10 +79,70 @@ def test_uniform_flow_is_preserved():
     assert np.allclose(fl["rho"], rho, atol=1e-15)
 
 
+def _interpenetrating(velocity_mode, rho, u, tau):
+    """uniform red and blue fluids at equilibrium with different velocities u[c]"""
+    orc = _uniform(4, 4, 4, rho=rho, g_br=0.0, tau=tau, velocity_mode=velocity_mode)
+    f = np.zeros((2, 19, 4, 4, 4))
+    for c in range(2):
+        f[c] = O.equilibrium(rho[c], u[c], 3)[:, None, None, None]
+    orc.set_populations(f)
+    return orc
+
+
+@pytest.mark.parametrize("velocity_mode", [0, 1])
+def test_interpenetrating_components_relax_as_eq6_states(velocity_mode):
+    """Closed form of one BGK step, Eqs. (2), (6), without forces: two uniform
+    components with different velocities.  Streaming leaves a uniform state
+    unchanged and the equilibrium of Eq. (3) carries momentum rho u exactly, so
+    after one step j^c = j^c (1 - 1/tau^c) + rho^c u_eq^c / tau^c with
+    u_eq^c = u' = sum_c (j^c/tau^c) / sum_c (rho^c/tau^c) in mode 0 (the
+    common Shan-Chen velocity) and u_eq^c = j^c/rho^c in mode 1.  A common
+    velocity weighted by rho alone, or by tau instead of 1/tau, fails here."""
+    rho = (0.5, 0.2)
+    tau = (0.8, 1.3)
+    u = [np.array([0.03, -0.01, 0.02]), np.array([-0.02, 0.015, 0.0])]
+    orc = _interpenetrating(velocity_mode, rho, u, tau)
+    orc.step(1)
+    j = orc.fields()["j"]  # (2, nz, ny, nx, 3)
+    jc = [rho[c] * u[c] for c in range(2)]
+    if velocity_mode == 0:
+        ubar = (jc[0] / tau[0] + jc[1] / tau[1]) / (rho[0] / tau[0] + rho[1] / tau[1])
+        expect = [jc[c] * (1.0 - 1.0 / tau[c]) + rho[c] * ubar / tau[c] for c in range(2)]
+    else:
+        expect = jc
+    for c in range(2):
+        assert np.abs(j[c] - expect[c]).max() < 1e-16
+    # the mixture momentum is the same in both modes; the split between the
+    # components is what mode 0 changes
+    if velocity_mode == 0:
+        assert np.abs(j[0][0, 0, 0] - jc[0]).max() > 1e-3
+    assert np.abs(j[0] + j[1] - (jc[0] + jc[1])).max() < 1e-16
+
+
+@pytest.mark.parametrize("velocity_mode", [0, 1])
+def test_demixing_box_conserves_total_momentum_with_unequal_tau(velocity_mode):
+    """Periodic box, unequal relaxation times and densities, demixing: the
+    post-collision mixture momentum is the pre-collision one plus sum_c F^c
+    in either mode of Eq. (6) (in mode 0 because u' sum_c rho^c/tau^c =
+    sum_c j^c/tau^c), and the Shan-Chen forces of Eq. (4) cancel over a
+    periodic box, so the total momentum is conserved to rounding."""
+    p = W.params(nx=10, ny=10, nz=8, rho_init=(0.5, 0.3), noise_amp=0.05, g_br=0.1, tau=(0.8, 1.3),
+                 velocity_mode=velocity_mode, seed=21)
+    orc = O.Oracle(p)
+    s0 = orc.sums()
+    orc.step(40)
+    s1 = orc.sums()
+    assert np.allclose(s1["mass"], s0["mass"], rtol=1e-13, atol=0)
+    assert np.all(np.abs(s1["fluid_momentum"] - s0["fluid_momentum"]) < 1e-12 * s0["mass"].sum())
+    # the components did move relative to each other (the test has teeth)
+    j = orc.fields()["j"]
+    assert np.abs(j[0]).max() > 1e-4
+
+
 def test_rotation_by_quarter_turn_commutes_with_the_step():
     """Rotating the initial state (fluid and a moving sphere) by 90 degrees
     about z gives the rotated result: catches swapped or mis-signed axes."""
-    L = 12
+    L = 13
     c, _, _ = O.lattice()
     rot = lambda v: np.array([-v[1], v[0], v[2]])
     perm = np.array([next(k for k in range(19) if np.array_equal(c[k], rot(c[i]))) for i in range(19)])

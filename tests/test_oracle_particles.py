@@ -141,6 +141,62 @@ def test_mass_correction_counteracts_the_mass_error():
     assert np.all(np.abs(mb - m0) < np.abs(ma - m0))
 
 
+def _c0_pair(c0, rho_init, delta):
+    """two lattices with the same history, C_0 = 0 and C_0 = c0: one step, then
+    the fluid rescaled per component so that the mass error of Eq. (31),
+    Delta rho^c = M^c(now) - M^c(first step), is delta N for both components
+    (N = all sites); returns the two lattices, the owner maps before and after
+    a second step, and the mass errors"""
+    out = []
+    for c in (0.0, c0):
+        p = W.params(nx=16, ny=16, nz=16, rho_init=rho_init, noise_amp=0.01, g_br=0.05, seed=5, c0_mass_corr=c)
+        orc = O.Oracle(p)
+        assert orc.add_particles(W.make_particles([[8.1, 8.3, 7.7]], 3.0, vel=[[0.23, 0.11, -0.07]],
+                                                  prescribed=1)) == 0
+        m0 = orc.sums()["mass"]  # the baseline M(0), taken at the start of the first step
+        orc.step(1)
+        f = orc.populations()
+        m1 = orc.sums()["mass"]
+        N = 16 ** 3
+        for comp in range(2):
+            f[comp] *= (m0[comp] + delta * N) / m1[comp]
+        orc.set_populations(f)
+        dM = orc.sums()["mass"] - m0
+        own_before = orc.owner()
+        orc.step(1)
+        out.append((orc, own_before, orc.owner(), dM))
+    return out
+
+
+def test_mass_correction_factor_of_eq31():
+    """Eq. (31) in closed form on refilled sites.  Everything before the refill
+    is the same with and without the correction, so the refilled density
+    (the only density of a new fluid site, since sum_i f_i^eq = rho_new) with
+    C_0 divided by the one without is 1 - C_0 (sum_c rho_init^c / rho_init^c)
+    Delta rho^c / N, with N all lattice sites.  With rho_init = (0.6, 0.2) and
+    equal Delta rho^c / N the blue correction is exactly three times the red
+    one; dropping the density ratio, or taking N as the fluid sites only,
+    fails this."""
+    c0, delta = 10.0, 2.5e-3
+    rho_init = (0.6, 0.2)
+    (a, own_b, own_a, dMa), (b, own_b2, own_a2, dMb) = _c0_pair(c0, rho_init, delta)
+    assert np.array_equal(own_b, own_b2) and np.array_equal(own_a, own_a2)
+    assert np.allclose(dMa, delta * 16 ** 3, rtol=1e-12) and np.allclose(dMb, dMa, rtol=0, atol=1e-12)
+    unc = (own_b >= 0) & (own_a == -1)
+    assert unc.sum() == a.counts()["uncovered_last"] == 8
+    ra, rb = a.fields()["rho"], b.fields()["rho"]
+    ratio = rb[:, unc] / ra[:, unc]  # (2, sites)
+    N = 16 ** 3
+    for comp in range(2):
+        expect = 1.0 - c0 * (sum(rho_init) / rho_init[comp]) * dMb[comp] / N
+        assert np.abs(ratio[comp] - expect).max() < 1e-12
+    # equal mass errors per site: the blue correction is three times the red one
+    assert np.allclose((1.0 - ratio[1]) / (1.0 - ratio[0]), 3.0, rtol=1e-9)
+    # sites that were fluid before and after are untouched by the correction
+    keep = (own_b == -1) & (own_a == -1)
+    assert np.abs(rb[:, keep] - ra[:, keep]).max() == 0.0
+
+
 def test_colour_sign_sets_the_preferred_fluid():
     """Sec. IV: a positive colour adds red virtual fluid and makes the particle
     prefer red (blue is repelled from its surface); a negative colour the reverse."""
@@ -180,7 +236,7 @@ def test_fixed_sphere_balances_the_driving_force():
     """A fixed sphere in a body-forced periodic flow: at steady state the fluid
     force on the sphere equals the total force that drives the fluid."""
     a = 2e-5
-    orc = O.Oracle(W.params(nx=12, ny=12, nz=12, rho_init=(0.35, 0.35), noise_amp=0.0, g_br=0.0,
+    orc = O.Oracle(W.params(nx=13, ny=13, nz=13, rho_init=(0.35, 0.35), noise_amp=0.0, g_br=0.0,
                             body_accel=(a, 0.0, 0.0)))
     assert orc.add_particles(W.make_particles([[6.0, 6.0, 6.0]], 2.5, prescribed=1)) == 0
     orc.step(3000)
@@ -268,6 +324,58 @@ def test_lubrication_of_an_isolated_pair_is_backward_euler():
     assert U[0, 0] == -U[1, 0] and U[0, 0] > 0.0
 
 
+def _explicit_pair(gap, v, rho_p, r=3.0):
+    orc = O.Oracle(W.params(nx=int(2 * (2 * r + gap)) + 8, ny=16, nz=16, rho_init=(0.0, 0.0), noise_amp=0.0,
+                            g_br=0.0, lub_mode=0))
+    xs = [4.0 + r, 4.0 + 3 * r + gap]
+    assert orc.add_particles(W.make_particles([[x, 8.0, 8.0] for x in xs], r, vel=[[v, 0, 0], [-v, 0, 0]],
+                                              density=rho_p)) == 0
+    return orc
+
+
+def test_explicit_lubrication_is_eq22_under_the_leapfrog():
+    """lub_mode 0: Eq. (22) as printed, evaluated with the latest velocities
+    U(t - 1/2) and integrated by the leap-frog of Eqs. (9), (10).  For an
+    isolated pair the approach speed after one step is w (1 - c (1/m_1 +
+    1/m_2)) and the force on each sphere is -c w along the centre line
+    (closed form); in a stiff case (c (1/m_1 + 1/m_2) > 2, at the h_min clamp
+    with light spheres) the speed reverses and grows, which is why the
+    default mode applies the term implicitly."""
+    r, v = 3.0, 0.002
+    nu = (1.0 - 0.5) / 3.0
+    for gap, rho_p in ((0.3, 1.0), (0.1, 0.05)):
+        orc = _explicit_pair(gap, v, rho_p, r)
+        m = rho_p * 4.0 / 3.0 * math.pi * r ** 3
+        h = max(gap, 0.1)
+        c = 6.0 * math.pi * nu * 1.0 * (r * r / (2 * r)) ** 2 * (1.0 / h - 1.0 / (2.0 / 3.0))
+        orc.step(1)
+        P = orc.particles()
+        w = 2 * v
+        assert abs(P["Ftotal"][0, 0] + c * w) < 1e-15 and P["Ftotal"][1, 0] == -P["Ftotal"][0, 0]
+        w_after = P["U"][0, 0] - P["U"][1, 0]
+        assert abs(w_after - w * (1.0 - 2.0 * c / m)) < 1e-15
+        if 2.0 * c / m > 2.0:
+            assert w_after < -w  # reversed and amplified
+        else:
+            assert 0.0 < w_after < w
+
+
+def test_explicit_and_implicit_lubrication_agree_when_soft():
+    """Far from the clamp and with heavy spheres the two readings of Eq. (22)
+    differ only at second order in c/m over one step."""
+    r, v, gap = 3.0, 0.002, 0.5
+    a = _explicit_pair(gap, v, 5.0, r)
+    b = _row_of_spheres(2, gap, [[v, 0, 0], [-v, 0, 0]], 5.0, r)
+    a.step(1)
+    b.step(1)
+    Ua, Ub = a.particles()["U"], b.particles()["U"]
+    m = 5.0 * 4.0 / 3.0 * math.pi * r ** 3
+    nu = 0.5 / 3.0
+    c = 6.0 * math.pi * nu * (r * r / (2 * r)) ** 2 * (1.0 / gap - 1.5)
+    assert 0.0 < c * 2.0 / m < 0.02
+    assert abs((Ua[0, 0] - Ua[1, 0]) - (Ub[0, 0] - Ub[1, 0])) < 2 * v * (2 * c / m) ** 2 * 1.01
+
+
 def test_stiff_lubrication_network_dissipates_and_conserves_momentum():
     """A packed row of light spheres with alternating velocities (stiff: the
     explicit update would grow them geometrically): the shared-mass pair
@@ -298,3 +406,33 @@ def test_runaway_sphere_stops_the_oracle():
     with pytest.raises(RuntimeError):
         ref.step(3)
     assert ref.counts()["step"] == 1
+
+
+def test_runaway_criterion_is_per_axis():
+    """The limit is one lattice unit per step along each axis (the map update
+    walks sub-lattice moves per axis): a sphere moving (0.8, 0.8, 0) per step
+    (speed 1.13) continues, one moving exactly 1 along an axis stops."""
+    p = W.params(nx=16, ny=16, nz=16, noise_amp=0.0, g_br=0.0, seed=3)
+    a = O.Oracle(p)
+    assert a.add_particles(W.make_particles([[8.0, 8.0, 8.0]], 2.0, vel=[[0.8, 0.8, 0.0]], prescribed=1)) == 0
+    a.step(3)
+    assert a.counts()["step"] == 3
+    b = O.Oracle(p)
+    assert b.add_particles(W.make_particles([[8.0, 8.0, 8.0]], 2.0, vel=[[0.0, -1.0, 0.0]], prescribed=1)) == 0
+    with pytest.raises(RuntimeError):
+        b.step(3)
+    assert b.counts()["step"] == 1
+
+
+def test_add_particles_refuses_what_the_library_refuses():
+    """Spheres need a periodic box (no walls) and a bounding box of
+    2 ceil(r) + 7 sites that fits in one period of every axis."""
+    orc = O.Oracle(W.params(nx=16, ny=16, nz=16, wall_axis=2))
+    assert orc.add_particles(W.make_particles([[8, 8, 8]], 2.0)) == -1
+    # r = 4 needs 15 sites; r = 4.01 needs 17
+    orc = O.Oracle(W.params(nx=16, ny=16, nz=17))
+    assert orc.add_particles(W.make_particles([[8, 8, 8]], 4.01)) == -1
+    orc = O.Oracle(W.params(nx=17, ny=17, nz=17))
+    assert orc.add_particles(W.make_particles([[8, 8, 8]], 4.01)) == 0
+    orc = O.Oracle(W.params(nx=16, ny=16, nz=16))
+    assert orc.add_particles(W.make_particles([[8, 8, 8]], 4.0)) == 0
