@@ -48,7 +48,7 @@ enum {
     LB_EDEVICE = -3,   /* HIP runtime error */
     LB_EOVERLAP = -4,  /* spheres overlap */
     LB_ESTATE = -5,    /* call not allowed in the current state */
-    LB_EUNSTABLE = -6, /* the fluid mass became non-finite */
+    LB_EUNSTABLE = -6, /* the fluid mass became non-finite, or a sphere moved >= 1 site along an axis */
     LB_ECAPACITY = -7  /* a per-particle list overflowed (a sphere moved too far in one step) */
 };
 
@@ -97,13 +97,22 @@ typedef struct {
     double lub_hc, lub_hmin; /* lubrication cut-off and clamp gaps of Eq. (22); hc <= 0: off */
     int32_t kernel;          /* LB_KERNEL_* */
     int32_t tile[3];         /* tile edge lengths of the fused kernel; 0 = automatic */
+    int32_t lub_mode;        /* how Eq. (22) enters the leap-frog of Eqs. (9), (10), which the
+                                paper does not fix for a velocity-dependent force:
+                                0: explicit force from the velocities U(t - 1/2), as printed;
+                                   an isolated pair's approach speed w becomes
+                                   w (1 - c (1/m_1 + 1/m_2)), unstable once that factor < -1
+                                   (light spheres at the h_min clamp);
+                                1 (default): pair impulses J = c w / (1 + c (k_p/m_p + k_q/m_q))
+                                   from the velocities after every other force (k: lubrication
+                                   contacts of a sphere), backward Euler for an isolated pair */
 } lb_params;
 
 typedef struct {
     double pos[3];    /* centre, in [0, n) per axis */
     double vel[3];    /* velocity U(t - 1/2) */
     double omega[3];  /* angular velocity Omega(t - 1/2) */
-    double radius;    /* > 0 and <= min(nx, ny, nz)/4 */
+    double radius;    /* > 0, <= min(nx, ny, nz)/4 and 2 ceil(radius) + 7 <= each edge */
     double density;   /* mass density, > 0; m = density 4/3 pi r^3 */
     double color;     /* wettability Delta rho of Sec. IV (> 0 prefers red) */
     int32_t prescribed; /* 1: velocities fixed, the sphere moves but is not integrated */
@@ -131,12 +140,20 @@ typedef struct {
 /* Fill p with the defaults: FP32, tau = 1, g_br = 0.08, rho0 = 1, weights
  * (4, 2), velocity_mode 1, eq_order 3, rho_init 0.35 each, noise 0.01,
  * seed 1, no walls, no body force, C_0 = 0, K_Hertz = 100, h_c = 2/3,
- * h_min = 0.1, automatic kernel and tiles; the box is 16^3. */
+ * h_min = 0.1 (the cut-off and clamp stated with Eq. (22)), lub_mode 1,
+ * automatic kernel and tiles; the box is 16^3.  Start every lb_params from
+ * here: a zeroed struct selects lub_mode 0. */
 void lb_default_params(lb_params *p);
 
-/* Create a lattice with the initial random densities at rest (f = zeta_i rho).
- * stream: a hipStream_t (NULL = the null stream). alloc may be NULL.
- * Errors: LB_EINVAL (bad parameter), LB_ENOMEM, LB_EDEVICE. */
+/* Create a lattice: two fluid components "distributed randomly" (Sec. VI),
+ * rho^c(x) = rho_init^c + noise_amp (2U - 1) with U the SplitMix64 draw of
+ * index 2n + c, at rest in the equilibrium of Eq. (3) (f_i = zeta_i rho^c),
+ * plus the two wall planes if wall_axis >= 0.
+ * stream: a hipStream_t (NULL = the null stream); every later call of the
+ * handle enqueues its device work there.  alloc may be NULL (hipMalloc).
+ * Errors: LB_EINVAL (a parameter out of range: box edge < 1 or more than
+ * 2^30 sites, tau <= 1/2, rho0 <= 0, an unknown mode, precision or kernel,
+ * walls on an axis shorter than 3), LB_ENOMEM, LB_EDEVICE. */
 int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_handle **out);
 
 /* Release the handle and all its device memory (after the stream drains). */
@@ -146,20 +163,44 @@ void lb_destroy(lb_handle *h);
  * with h == NULL, of the last failed lb_create on the calling thread. */
 const char *lb_last_error(const lb_handle *h);
 
-/* Add n spheres (Sec. III); allowed only before the first lb_step. The sites
- * inside a sphere (strict |x - R| < r on positions rounded to multiples of
- * 2^-20) become solid and their fluid is removed. Errors: LB_EOVERLAP (two
- * spheres closer than r_a + r_b, minimum image), LB_EINVAL (radius, density
- * or position out of range, or walls present), LB_ESTATE (after stepping). */
+/* Add n spheres (Sec. III: homogeneous spheres, lattice sites inside them
+ * are solid); allowed only before the first lb_step.  parts is a host array
+ * of n entries, copied.  The sites inside a sphere (strict |x - R| < r on
+ * positions rounded to multiples of 2^-20) become solid and their fluid is
+ * removed.  Input domain: 0 < radius <= min(nx, ny, nz)/4 and
+ * 2 ceil(radius) + 7 <= each box edge (a sphere's bounding box and its
+ * neighbour ring fit in one period), density > 0, centre in [0, n) per
+ * axis, spheres only in periodic boxes (no walls).
+ * Errors: LB_EOVERLAP (two spheres closer than r_a + r_b, minimum image,
+ * new against new and old), LB_EINVAL (outside the input domain, or walls
+ * present), LB_ESTATE (after stepping, or in a batch). */
 int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts);
 
-/* Enqueue nsteps time steps (nsteps >= 0). */
+/* Enqueue nsteps time steps (nsteps >= 0) on the handle's stream and return.
+ * One step follows Secs. II-IV in this order: moments and densities (Sec.
+ * II), virtual fluid on the outermost solid layer (Sec. IV, Eqs. (27),
+ * (29), (30)), effective mass Psi (Eq. (5)), Shan-Chen force (Eq. (4)), BGK
+ * collision with the velocity shift (Eqs. (2), (3), (6)), streaming with
+ * bounce-back and the moving-wall term (Eqs. (11), (12), (16)), momentum
+ * exchange and the Shan-Chen force on the spheres (Eqs. (13)-(17), (28)),
+ * Hertz and lubrication forces (Eqs. (21), (22)), the leap-frog (Eqs. (9),
+ * (10)), then covering and uncovering with refill (Eqs. (18)-(20), (23)-(26),
+ * (31)); impulses of covering and refilling act in the next step.  Device
+ * failures (a non-finite mass, a sphere moving one site or more along an
+ * axis in one step, a list overflow) are reported by the next synchronising
+ * call: LB_EUNSTABLE or LB_ECAPACITY. */
 int lb_step(lb_handle *h, int32_t nsteps);
 
 /* Wait for the stream; report deferred device failures. */
 int lb_synchronize(lb_handle *h);
 
-/* Conserved sums and bookkeeping counters of the current state (synchronises). */
+/* Conserved sums and bookkeeping counters of the current state
+ * (synchronises; out is caller-owned host memory).  mass[c] is the fluid
+ * mass M^c whose drift from its first-step value is the Delta rho^c of the
+ * mass correction, Eq. (31); the momenta are the fluid's sum_i f_i c_i
+ * (Sec. II), the spheres' m U (Eq. (9)) and the pending impulses of covering
+ * and refilling (Eqs. (18), (20)), whose sum is conserved in a periodic box
+ * without walls or body force.  Errors: those of lb_step, deferred. */
 int lb_observables(lb_handle *h, lb_observables_t *out);
 
 /* Fields of the current state, each pointer may be NULL:
@@ -195,12 +236,24 @@ int lb_set_particle_state(lb_handle *h, const double *state);
  * of every sphere on the current map. */
 int lb_particle_counts(lb_handle *h, int32_t *links, int32_t *shell);
 
-/* Checkpoint: *bytes in = capacity of buf, out = bytes written (or needed when
- * buf is NULL). Holds the parameters, step counter, populations, particles
- * and the mass baseline of Eq. (31). */
+/* Checkpoint (no passage of the paper: storage of the state the method
+ * advances).  *bytes in = capacity of buf (caller-owned host memory), out =
+ * bytes written (or needed when buf is NULL).  Holds the lb_params the
+ * lattice was created with, the step counter, the populations in their
+ * storage type, every sphere's state, radius, density, colour and motion
+ * flag, and the mass baseline of Eq. (31).  Errors: LB_EINVAL (buffer too
+ * small), LB_EDEVICE. */
 int lb_get_state(lb_handle *h, void *buf, size_t *bytes);
 
-/* Restore a checkpoint written by lb_get_state for the same box and precision. */
+/* Restore a checkpoint written by lb_get_state.  The lattice must have the
+ * same box, precision and model parameters (tau, g_br, rho0, weights,
+ * velocity_mode, eq_order, rho_init, walls, body force, C_0, K_Hertz,
+ * lubrication; the noise draw and kernel choice may differ) and, if it has
+ * spheres, the same number with the same radius, density, colour and motion
+ * flag; a lattice without spheres that has not stepped takes the
+ * checkpoint's spheres.  Errors: LB_EINVAL (not a checkpoint, another format
+ * version, other parameters or spheres), LB_ESTATE (other number of spheres,
+ * or the lattice is in a batch). */
 int lb_set_state(lb_handle *h, const void *buf, size_t bytes);
 
 /* Sec. V: the paper's linear fit theta = 442 Delta rho + 90 (degrees) of the

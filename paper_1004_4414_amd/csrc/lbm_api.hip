@@ -57,7 +57,7 @@ int fail(lb_handle *h, int code, const std::string &msg) {
     }
 
 const char *kStateMagic = "LBMSTATE";
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 
 // upper bound of the lattice sites of a sphere's outermost solid layer: those
 // sites lie within sqrt(2) inside the surface, so their unit cells lie in the
@@ -102,6 +102,7 @@ void set_dev_params(lb_handle *h) {
     d.velocity_mode = p.velocity_mode;
     d.eq_order = p.eq_order;
     d.wall_axis = p.wall_axis;
+    d.lub_mode = p.lub_mode;
     for (int a = 0; a < 3; ++a) {
         d.body[a] = p.body_accel[a];
         d.wall_vel[0][a] = p.wall_vel[0][a];
@@ -126,6 +127,7 @@ int validate_params(const lb_params *p, std::string &msg) {
     if (!(p->rho0 > 0.0)) return msg = "rho0 must be positive", LB_EINVAL;
     if (p->velocity_mode != 0 && p->velocity_mode != 1) return msg = "velocity_mode must be 0 or 1", LB_EINVAL;
     if (p->eq_order != 2 && p->eq_order != 3) return msg = "eq_order must be 2 or 3", LB_EINVAL;
+    if (p->lub_mode != 0 && p->lub_mode != 1) return msg = "lub_mode must be 0 or 1", LB_EINVAL;
     if (p->wall_axis < -1 || p->wall_axis > 2) return msg = "wall_axis must be -1, 0, 1 or 2", LB_EINVAL;
     if (p->wall_axis >= 0 && (p->wall_axis == 0 ? p->nx : (p->wall_axis == 1 ? p->ny : p->nz)) < 3)
         return msg = "a box with walls needs at least 3 sites along the wall axis", LB_EINVAL;
@@ -380,6 +382,7 @@ void lb_default_params(lb_params *p) {
     p->lub_hc = 2.0 / 3.0;
     p->lub_hmin = 0.1;
     p->kernel = LB_KERNEL_AUTO;
+    p->lub_mode = 1;
 }
 
 // message of the last failed lb_create on this thread (lb_last_error(NULL))
@@ -840,13 +843,14 @@ int lb_particle_counts(lb_handle *h, int32_t *links, int32_t *shell) {
     LB_API_END
 }
 
-// checkpoint layout: magic[8], version, precision, nx, ny, nz, np (u32 each),
-// step (i64), DevState, populations (raw storage type), then per sphere
-// R U W P PT (15 doubles) radius density colour (3 doubles) prescribed (i32)
+// checkpoint layout: magic[8], version, np (u32 each), the lb_params the
+// lattice was created with, step (i64), DevState, populations (raw storage
+// type), then per sphere R U W P PT (15 doubles) radius density colour (3
+// doubles) prescribed (i32)
 int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
     if (!h || !bytes) return LB_EINVAL;
     const size_t fsz = (size_t)2 * Q * padded_sites(h->N) * h->tsize;
-    const size_t need = 8 + 6 * 4 + 8 + sizeof(DevState) + fsz + (size_t)h->np * (18 * 8 + 4);
+    const size_t need = 8 + 2 * 4 + sizeof(lb_params) + 8 + sizeof(DevState) + fsz + (size_t)h->np * (18 * 8 + 4);
     if (!buf) {
         *bytes = need;
         return LB_OK;
@@ -856,10 +860,11 @@ int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
     char *o = (char *)buf;
     std::memcpy(o, kStateMagic, 8);
     o += 8;
-    const uint32_t hdr[6] = {kStateVersion, (uint32_t)h->prm.precision, (uint32_t)h->prm.nx, (uint32_t)h->prm.ny,
-                             (uint32_t)h->prm.nz, (uint32_t)h->np};
+    const uint32_t hdr[2] = {kStateVersion, (uint32_t)h->np};
     std::memcpy(o, hdr, sizeof(hdr));
     o += sizeof(hdr);
+    std::memcpy(o, &h->prm, sizeof(lb_params));
+    o += sizeof(lb_params);
     const int64_t st = h->step;
     std::memcpy(o, &st, 8);
     o += 8;
@@ -893,23 +898,38 @@ int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
     LB_API_END
 }
 
+// the parameters that fix the stored state and the model it follows (the
+// initial-noise draw and the kernel choice do not)
+static bool same_model(const lb_params &a, const lb_params &b) {
+    bool eq = a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.precision == b.precision && a.g_br == b.g_br &&
+              a.rho0 == b.rho0 && a.w_face == b.w_face && a.w_edge == b.w_edge &&
+              a.velocity_mode == b.velocity_mode && a.eq_order == b.eq_order && a.wall_axis == b.wall_axis &&
+              a.c0_mass_corr == b.c0_mass_corr && a.k_hertz == b.k_hertz && a.lub_hc == b.lub_hc &&
+              a.lub_hmin == b.lub_hmin && a.lub_mode == b.lub_mode;
+    for (int c = 0; c < 2; ++c) eq = eq && a.tau[c] == b.tau[c] && a.rho_init[c] == b.rho_init[c];
+    for (int k = 0; k < 3; ++k)
+        eq = eq && a.body_accel[k] == b.body_accel[k] && a.wall_vel[0][k] == b.wall_vel[0][k] &&
+             a.wall_vel[1][k] == b.wall_vel[1][k];
+    return eq;
+}
+
 int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
     if (!h || !buf) return LB_EINVAL;
     if (h->in_batch) return fail(h, LB_ESTATE, "the lattice belongs to a batch");
     const char *in = (const char *)buf;
-    if (bytes < 8 + 24 + 8 + sizeof(DevState) || std::memcmp(in, kStateMagic, 8) != 0)
-        return fail(h, LB_EINVAL, "not a checkpoint");
-    uint32_t hdr[6];
+    const size_t head = 8 + 2 * 4 + sizeof(lb_params) + 8 + sizeof(DevState);
+    if (bytes < head || std::memcmp(in, kStateMagic, 8) != 0) return fail(h, LB_EINVAL, "not a checkpoint");
+    uint32_t hdr[2];
     std::memcpy(hdr, in + 8, sizeof(hdr));
-    if (hdr[0] != kStateVersion || (int)hdr[1] != h->prm.precision || (int)hdr[2] != h->prm.nx ||
-        (int)hdr[3] != h->prm.ny || (int)hdr[4] != h->prm.nz)
-        return fail(h, LB_EINVAL, "checkpoint of a different lattice");
-    const int np = (int)hdr[5];
+    if (hdr[0] != kStateVersion) return fail(h, LB_EINVAL, "checkpoint of another format version");
+    lb_params saved;
+    std::memcpy(&saved, in + 16, sizeof(lb_params));
+    if (!same_model(saved, h->prm))
+        return fail(h, LB_EINVAL, "checkpoint of a lattice with other parameters (box, precision or model)");
+    const int np = (int)hdr[1];
     const size_t fsz = (size_t)2 * Q * padded_sites(h->N) * h->tsize;
-    if (bytes < 8 + 24 + 8 + sizeof(DevState) + fsz + (size_t)np * (18 * 8 + 4))
-        return fail(h, LB_EINVAL, "truncated checkpoint");
-    LB_API_BEGIN
-    const char *p = in + 32;
+    if (bytes < head + fsz + (size_t)np * (18 * 8 + 4)) return fail(h, LB_EINVAL, "truncated checkpoint");
+    const char *p = in + 16 + sizeof(lb_params);
     int64_t st;
     std::memcpy(&st, p, 8);
     p += 8;
@@ -917,33 +937,41 @@ int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
     p += sizeof(DevState);
     const char *pops = p;
     p += fsz;
-    // spheres: rebuild the particle arrays as a fresh addition
-    if (np != h->np) {
-        if (h->step == 0 && h->np == 0 && np > 0) {
-            std::vector<lb_particle> parts(np);
-            const char *q = p;
-            for (int k = 0; k < np; ++k) {
-                double v[18];
-                std::memcpy(v, q, sizeof(v));
-                q += sizeof(v);
-                int32_t pr;
-                std::memcpy(&pr, q, 4);
-                q += 4;
-                for (int a = 0; a < 3; ++a) {
-                    parts[k].pos[a] = v[a];
-                    parts[k].vel[a] = v[3 + a];
-                    parts[k].omega[a] = v[6 + a];
-                }
-                parts[k].radius = v[15];
-                parts[k].density = v[16];
-                parts[k].color = v[17];
-                parts[k].prescribed = pr;
+    // the spheres' fixed properties as stored
+    std::vector<lb_particle> parts(np);
+    {
+        const char *q = p;
+        for (int k = 0; k < np; ++k) {
+            double v[18];
+            std::memcpy(v, q, sizeof(v));
+            q += sizeof(v);
+            int32_t pr;
+            std::memcpy(&pr, q, 4);
+            q += 4;
+            for (int a = 0; a < 3; ++a) {
+                parts[k].pos[a] = v[a];
+                parts[k].vel[a] = v[3 + a];
+                parts[k].omega[a] = v[6 + a];
             }
-            const int rc = lb_add_particles(h, np, parts.data());
-            if (rc != LB_OK) return rc;
-        } else {
-            return fail(h, LB_ESTATE, "checkpoint has a different number of spheres");
+            parts[k].radius = v[15];
+            parts[k].density = v[16];
+            parts[k].color = v[17];
+            parts[k].prescribed = pr;
         }
+    }
+    if (np == h->np) {
+        for (int k = 0; k < np; ++k)
+            if (parts[k].radius != h->h_rad[k] || parts[k].density != h->h_dens[k] ||
+                parts[k].color != h->h_color[k] || (parts[k].prescribed != 0) != (h->h_prescribed[k] != 0))
+                return fail(h, LB_EINVAL, "checkpoint spheres differ in radius, density, colour or motion");
+    } else if (!(h->step == 0 && h->np == 0 && np > 0)) {
+        return fail(h, LB_ESTATE, "checkpoint has a different number of spheres");
+    }
+    LB_API_BEGIN
+    // spheres: a lattice without any is given the checkpoint's as a fresh addition
+    if (np != h->np) {
+        const int rc = lb_add_particles(h, np, parts.data());
+        if (rc != LB_OK) return rc;
     }
     if (np) {
         std::vector<double> s((size_t)15 * np);

@@ -246,7 +246,7 @@ struct DevParams {
     long long N;
     double tau[2];
     double g, rho0, w_face, w_edge;
-    int velocity_mode, eq_order, wall_axis, pad;
+    int velocity_mode, eq_order, wall_axis, lub_mode;
     double rho_init[2];
     double rho_ref[2];  // populations are stored as f_i - zeta_i rho_ref^c
     double psi_e[2];    // rho0 exp(-rho_ref^c / rho0): Psi(rho_ref + d) - Psi(rho_ref) = -psi_e expm1(-d/rho0)

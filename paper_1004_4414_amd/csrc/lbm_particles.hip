@@ -357,13 +357,19 @@ __global__ __launch_bounds__(BLOCK) void k_particle_fluid_force(DevParams P, Dev
 // pair forces, Eqs. (21) and (22), then the total force and torque: Hertz
 // repulsion (5/2) K (r_a + r_b - d)^(3/2) along the centre line, and the
 // lubrication contacts (gaps h < h_c) of each sphere, listed in index order.
-// The lubrication, c = 6 pi nu rho0 (r_a r_b/(r_a+r_b))^2 (1/h - 1/h_c) with h
-// clamped at h_min, acting on the approach speed, is stiff at the clamp; it is
-// applied as pair impulses in k_integrate: with v* the velocities after every
-// other force, w = n.(v*_p - v*_q) and k_p the number of contacts of sphere p,
-// the pair exchanges J = c w / (1 + c (k_p/m_p + k_q/m_q)) along n (the
-// backward-Euler solution for an isolated pair; sharing a sphere's mass among
-// its contacts keeps simultaneous impulses from overshooting).
+// The lubrication of Eq. (22), c = 6 pi nu rho0 (r_a r_b/(r_a+r_b))^2 (1/h -
+// 1/h_c) with h clamped at h_min, acting on the approach speed, comes in two
+// modes (lub_mode):
+//  0: the explicit force of Eq. (22) with the latest velocities U(t-1/2),
+//     summed here with the Hertz force (the leap-frog then takes it like any
+//     other force); unstable where c (1/m_p + 1/m_q) > 2;
+//  1: pair impulses in k_integrate: with v* the velocities after every other
+//     force, w = n.(v*_p - v*_q) and k_p the number of contacts of sphere p,
+//     the pair exchanges J = c w / (1 + c (k_p/m_p + k_q/m_q)) along n (the
+//     backward-Euler solution for an isolated pair; sharing a sphere's mass
+//     among its contacts keeps simultaneous impulses from overshooting).
+// Either way the pair's geometry and c are computed from the lower index to
+// the higher, so both ends use identical values.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, DevState *st, const Grid &g) {
     __shared__ double lds[3 * (BLOCK / 64)];
@@ -401,7 +407,7 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
             }
         }
         const int slot = block_compact(lub, ncont, clds);
-        if (lub && slot < MAX_LUB_CONTACTS) {
+        if (lub && (P.lub_mode == 0 || slot < MAX_LUB_CONTACTS)) {
             // the pair's geometry as both ends compute it: from the lower index to the higher
             const int lo = min(p, q), hi = max(p, q);
             double d[3], dist2 = 0.0;
@@ -414,16 +420,25 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
             const double h = dist - rsum;
             const double hh = h < P.lub_hmin ? P.lub_hmin : h;
             const double ared = D.rad[lo] * D.rad[hi] / rsum;
-            const size_t e = (size_t)p * MAX_LUB_CONTACTS + slot;
-            D.cont[e] = q;
-            D.cont_c[e] = 6.0 * M_PI * nu * P.rho0 * ared * ared * (1.0 / hh - 1.0 / P.lub_hc);
-            for (int a = 0; a < 3; ++a) D.cont_n[3 * e + a] = d[a] / dist;
+            const double c = 6.0 * M_PI * nu * P.rho0 * ared * ared * (1.0 / hh - 1.0 / P.lub_hc);
+            if (P.lub_mode == 0) {
+                // explicit force, Eq. (22): -c n [n.(U_lo - U_hi)] on lo, the opposite on hi
+                double w = 0.0;
+                for (int a = 0; a < 3; ++a) w += d[a] / dist * (D.U[3 * lo + a] - D.U[3 * hi + a]);
+                const double sgn = p == lo ? -1.0 : 1.0;
+                for (int a = 0; a < 3; ++a) F[a] += sgn * (c * w) * (d[a] / dist);
+            } else {
+                const size_t e = (size_t)p * MAX_LUB_CONTACTS + slot;
+                D.cont[e] = q;
+                D.cont_c[e] = c;
+                for (int a = 0; a < 3; ++a) D.cont_n[3 * e + a] = d[a] / dist;
+            }
         }
     }
     block_sum<3>(F, lds);
     if (threadIdx.x == 0) {
-        D.ncont[p] = min(ncont, MAX_LUB_CONTACTS);
-        if (ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
+        D.ncont[p] = P.lub_mode == 0 ? 0 : min(ncont, MAX_LUB_CONTACTS);
+        if (P.lub_mode != 0 && ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
             D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + F[a];
             D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
@@ -599,7 +614,7 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
         const unsigned long long ball = __ballot(lub);
         const int slot = ncont + __popcll(ball & ((t == 0) ? 0ull : (~0ull >> (64 - t))));
         ncont += __popcll(ball);
-        if (lub && slot < MAX_LUB_CONTACTS) {
+        if (lub && (P.lub_mode == 0 || slot < MAX_LUB_CONTACTS)) {
             // the pair's geometry as both ends compute it: from the lower index to the higher
             const int lo = min(p, q), hi = max(p, q);
             double d[3], dist2 = 0.0;
@@ -612,18 +627,27 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
             const double h = dist - rsum;
             const double hh = h < P.lub_hmin ? P.lub_hmin : h;
             const double ared = D.rad[lo] * D.rad[hi] / rsum;
-            const size_t e = (size_t)p * MAX_LUB_CONTACTS + slot;
-            D.cont[e] = q;
-            D.cont_c[e] = 6.0 * M_PI * nu * P.rho0 * ared * ared * (1.0 / hh - 1.0 / P.lub_hc);
-            for (int a = 0; a < 3; ++a) D.cont_n[3 * e + a] = d[a] / dist;
+            const double c = 6.0 * M_PI * nu * P.rho0 * ared * ared * (1.0 / hh - 1.0 / P.lub_hc);
+            if (P.lub_mode == 0) {
+                // explicit force, Eq. (22): -c n [n.(U_lo - U_hi)] on lo, the opposite on hi
+                double w = 0.0;
+                for (int a = 0; a < 3; ++a) w += d[a] / dist * (D.U[3 * lo + a] - D.U[3 * hi + a]);
+                const double sgn = p == lo ? -1.0 : 1.0;
+                for (int a = 0; a < 3; ++a) F[a] += sgn * (c * w) * (d[a] / dist);
+            } else {
+                const size_t e = (size_t)p * MAX_LUB_CONTACTS + slot;
+                D.cont[e] = q;
+                D.cont_c[e] = c;
+                for (int a = 0; a < 3; ++a) D.cont_n[3 * e + a] = d[a] / dist;
+            }
         }
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         for (int off = 32; off > 0; off >>= 1) F[a] += __shfl_down(F[a], off, 64);
     if (t == 0) {
-        D.ncont[p] = min(ncont, MAX_LUB_CONTACTS);
-        if (ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
+        D.ncont[p] = P.lub_mode == 0 ? 0 : min(ncont, MAX_LUB_CONTACTS);
+        if (P.lub_mode != 0 && ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
             D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + F[a];
             D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
@@ -659,7 +683,7 @@ __device__ __forceinline__ void integrate_body(DevParams P, DevParticles D, DevS
         const double sgn = p == lo ? -1.0 : 1.0;
         for (int a = 0; a < 3; ++a) imp[a] += sgn * J * n[a];
     }
-    double step2 = 0.0;
+    bool fast = false;
     for (int a = 0; a < 3; ++a) {
         D.Rprev[3 * p + a] = D.R[3 * p + a];
         D.Ftot[3 * p + a] += imp[a];
@@ -673,9 +697,10 @@ __device__ __forceinline__ void integrate_body(DevParams P, DevParticles D, DevS
         D.R[3 * p + a] = r;
         D.P[3 * p + a] = 0.0;
         D.PT[3 * p + a] = 0.0;
-        step2 += D.U[3 * p + a] * D.U[3 * p + a];
+        // the map update takes moves below one site per step along each axis
+        fast = fast || !(fabs(D.U[3 * p + a]) < 1.0);
     }
-    if (!(step2 < 1.0)) atomicOr(&st->overflow, 8);
+    if (fast) atomicOr(&st->overflow, 8);
 }
 
 __global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {

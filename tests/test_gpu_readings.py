@@ -1,0 +1,257 @@
+"""GPU-vs-oracle parity of the parts of the method whose reading the oracle
+pins in closed form: the mass correction of Eq. (31), both integrations of
+the lubrication of Eq. (22), the per-axis speed limit of the map update, the
+checkpoint's parameter check, and developed (event-rich) states of the 64^3
+sphere workload in FP32 against the 1e-5 gate."""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_1004_4414_amd import workloads as W
+from test_gpu_parity import compare_bookkeeping, compare_fields, compare_particle_forces, lbm, load_into_oracle
+
+pytestmark = pytest.mark.gpu
+
+PKEYS = ("R", "U", "W", "Ffluid", "Tfluid", "Ftotal", "P", "PT")
+
+
+def _moving_spheres(c0, seed=4):
+    p = W.params(nx=20, ny=20, nz=20, rho_init=(0.6, 0.2), noise_amp=0.02, g_br=0.06, seed=seed, c0_mass_corr=c0)
+    pos = [[5.2, 5.5, 6.1], [14.3, 6.2, 13.7], [9.6, 14.4, 4.8]]
+    vel = [[0.04, 0.03, -0.02], [-0.03, 0.05, 0.01], [0.02, -0.04, 0.05]]
+    om = [[0.01, -0.02, 0.015], [0.0, 0.02, -0.01], [-0.02, 0.0, 0.01]]
+    parts = W.make_particles(pos, [3.0, 2.6, 3.3], vel=vel, omega=om, color=[0.05, -0.05, 0.0],
+                             density=[0.6, 1.0, 1.4])
+    return p, parts
+
+
+def test_mass_correction_fp64_end_to_end():
+    """C_0 = 200 with moving spheres (covering and refilling every few steps),
+    FP64 end to end: fields, masses, sphere states and forces, and the
+    covered / uncovered / fallback counts against the oracle; the correction
+    visibly changed the masses."""
+    p, parts = _moving_spheres(200.0)
+    gpu = lbm().Lattice(p, precision="fp64")
+    gpu.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    gpu.step(60)
+    ref.step(60)
+    compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
+    compare_bookkeeping(gpu, ref)
+    Pg, Pr = gpu.particles(), ref.particles()
+    for k in PKEYS:
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+    og, sr, cr = gpu.observables(), ref.sums(), ref.counts()
+    assert np.allclose(og["mass"], sr["mass"], rtol=1e-12, atol=0)
+    assert og["covered_total"] == cr["covered_total"] > 0
+    assert og["uncovered_total"] == cr["uncovered_total"] > 0
+    assert og["refill_fallback"] == cr["refill_fallback"]
+    p0, parts0 = _moving_spheres(0.0)
+    ref0 = Oracle(p0)
+    assert ref0.add_particles(parts0) == 0
+    ref0.step(60)
+    assert np.abs(ref0.sums()["mass"] - sr["mass"]).max() > 1e-6
+
+
+def test_mass_correction_factor_on_refilled_sites_fp64():
+    """The closed form of Eq. (31) on the GPU: after one step the fluid is
+    rescaled so that Delta rho^c / N is the same for both components; in the
+    next step the refilled densities with C_0 = 10 are those of the oracle to
+    1e-12, and their ratio to the C_0 = 0 run is
+    1 - C_0 (sum_c rho_init^c / rho_init^c) Delta rho^c / N."""
+    rho_init, c0, delta, L = (0.6, 0.2), 10.0, 2.5e-3, 16
+    N = L ** 3
+    runs = {}
+    for c in (0.0, c0):
+        p = W.params(nx=L, ny=L, nz=L, rho_init=rho_init, noise_amp=0.01, g_br=0.05, seed=5, c0_mass_corr=c)
+        parts = W.make_particles([[8.1, 8.3, 7.7]], 3.0, vel=[[0.23, 0.11, -0.07]], prescribed=1)
+        gpu = lbm().Lattice(p, precision="fp64")
+        gpu.add_particles(parts)
+        ref = Oracle(p)
+        assert ref.add_particles(parts) == 0
+        m0 = ref.sums()["mass"]
+        gpu.step(1)
+        ref.step(1)
+        f = ref.populations()
+        m1 = ref.sums()["mass"]
+        for comp in range(2):
+            f[comp] *= (m0[comp] + delta * N) / m1[comp]
+        gpu.set_populations(f)
+        ref.set_populations(f)
+        own_b = gpu.owner()
+        gpu.step(1)
+        ref.step(1)
+        compare_bookkeeping(gpu, ref)
+        own_a = gpu.owner()
+        unc = (own_b >= 0) & (own_a == -1)
+        assert unc.sum() == ref.counts()["uncovered_last"] > 0
+        assert gpu.observables()["uncovered_total"] == ref.counts()["uncovered_total"]
+        rg, rr = gpu.fields()["rho"], ref.fields()["rho"]
+        assert np.abs(rg[:, unc] - rr[:, unc]).max() < 1e-12
+        compare_fields(gpu, ref, p, tol_rho=1e-12, tol_u=1e-10)
+        runs[c] = rg[:, unc]
+    ratio = runs[c0] / runs[0.0]
+    for comp in range(2):
+        expect = 1.0 - c0 * (sum(rho_init) / rho_init[comp]) * delta
+        assert np.abs(ratio[comp] - expect).max() < 1e-9
+    assert np.allclose((1.0 - ratio[1]) / (1.0 - ratio[0]), 3.0, rtol=1e-6)
+
+
+@pytest.mark.parametrize("lub_mode", [0, 1])
+def test_lubrication_modes_cluster_fp64(lub_mode):
+    """Four spheres closing in with gaps below h_c (all-pairs search), each
+    integration of Eq. (22), FP64 end to end."""
+    edge = 40
+    p = W.params(nx=edge, ny=edge, nz=edge, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=21,
+                 lub_mode=lub_mode)
+    c, s = edge / 2.0, 6.3 / 2.0
+    pos = [[c - s, c - s * 0.6, c], [c + s, c - s * 0.6, c], [c, c + s * 1.1, c], [c, c, c + 6.3]]
+    vel = [[0.01, 0.0, 0.0], [-0.01, 0.0, 0.0], [0.0, -0.01, 0.0], [0.0, 0.0, -0.01]]
+    parts = W.make_particles(pos, 3.0, vel=vel, density=1.0)
+    gpu = lbm().Lattice(p, precision="fp64")
+    gpu.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    gpu.step(40)
+    ref.step(40)
+    compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
+    compare_bookkeeping(gpu, ref)
+    Pg, Pr = gpu.particles(), ref.particles()
+    for k in PKEYS:
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+
+
+def test_explicit_lubrication_cell_list_fp64():
+    """lub_mode 0 with the cell-list pair search: 1200 spheres of r = 1.5 with
+    gaps from 0.15 in 64^3 (density 2, so c (1/m_p + 1/m_q) < 2 at the clamp),
+    FP64 end to end against the oracle's all-pairs search."""
+    p = W.params(nx=64, ny=64, nz=64, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=77, lub_mode=0)
+    pos = W.random_sphere_positions((64, 64, 64), 1200, 1.5, seed=77, min_gap=0.15)
+    rng = np.random.default_rng(77)
+    parts = W.make_particles(pos, 1.5, vel=rng.uniform(-0.02, 0.02, (1200, 3)), density=2.0)
+    gpu = lbm().Lattice(p, precision="fp64")
+    gpu.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    gpu.step(8)
+    ref.step(8)
+    compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
+    compare_bookkeeping(gpu, ref)
+    Pg, Pr = gpu.particles(), ref.particles()
+    for k in PKEYS:
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+
+
+def test_runaway_is_reported_where_the_oracle_stops():
+    """The speed limit is per axis on both sides: (0.8, 0.8, 0) per step runs
+    on; exactly one site per step along an axis is reported as LB_EUNSTABLE
+    after the first step, where the oracle stops."""
+    L = lbm()
+    p = W.params(nx=16, ny=16, nz=16, noise_amp=0.0, g_br=0.0, seed=3)
+    ok = W.make_particles([[8.0, 8.0, 8.0]], 2.0, vel=[[0.8, 0.8, 0.0]], prescribed=1)
+    g = L.Lattice(p, precision="fp64")
+    g.add_particles(ok)
+    ref = Oracle(p)
+    assert ref.add_particles(ok) == 0
+    for _ in range(3):
+        g.step(1)
+        g.synchronize()
+    ref.step(3)
+    compare_bookkeeping(g, ref)
+    bad = W.make_particles([[8.0, 8.0, 8.0]], 2.0, vel=[[0.0, -1.0, 0.0]], prescribed=1)
+    g = L.Lattice(p, precision="fp64")
+    g.add_particles(bad)
+    ref = Oracle(p)
+    assert ref.add_particles(bad) == 0
+    g.step(1)
+    with pytest.raises(L.LBError) as e:
+        g.synchronize()
+    assert e.value.code == L.LB_EUNSTABLE
+    with pytest.raises(RuntimeError):
+        ref.step(3)
+    assert ref.counts()["step"] == 1
+
+
+def test_checkpoint_refuses_other_parameters():
+    """A checkpoint restores only into a lattice of the same box, precision and
+    model (here: another rho_init, which the FP32 storage is relative to, or
+    another tau), and only with the same spheres."""
+    L = lbm()
+    p = W.params(nx=24, ny=24, nz=24, noise_amp=0.01, seed=4)
+    parts = W.make_particles([[8.0, 9.0, 10.0]], 3.0, vel=[[0.01, 0.0, 0.0]])
+    a = L.Lattice(p, precision="fp32")
+    a.add_particles(parts)
+    a.step(4)
+    blob = a.get_state()
+    for other in (dict(rho_init=(0.36, 0.35)), dict(tau=(1.0, 0.9)), dict(lub_mode=0)):
+        b = L.Lattice(dict(p, **other), precision="fp32")
+        b.add_particles(parts)
+        with pytest.raises(L.LBError) as e:
+            b.set_state(blob)
+        assert e.value.code == L.LB_EINVAL
+    b = L.Lattice(p, precision="fp32")
+    b.add_particles(W.make_particles([[8.0, 9.0, 10.0]], 3.0, density=2.0))
+    with pytest.raises(L.LBError):
+        b.set_state(blob)
+    # a different noise seed is the same model: accepted, and then identical
+    b = L.Lattice(dict(p, seed=99), precision="fp32")
+    b.add_particles(parts)
+    b.set_state(blob)
+    a.step(3)
+    b.step(3)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("kernel", ["twopass", "fused"])
+def test_spheres64_fp32_shadowing_developed_states(kernel):
+    """64^3 with 100 free spheres, FP32, shadowed from the states at t = 200,
+    500 and 1000 (spheres moving, interfaces formed) for 1 and 4 steps at the
+    1e-5 gate; every window holds covering and uncovering events, and the
+    bookkeeping matches exactly."""
+    p, parts, _, _ = W.config("spheres64")
+    gpu = lbm().Lattice(p, precision="fp32", kernel=kernel)
+    gpu.add_particles(parts)
+    for t_check in (200, 500, 1000):
+        gpu.step(t_check - gpu.observables()["step"])
+        ref = load_into_oracle(gpu, p, parts)
+        compare_bookkeeping(gpu, ref)
+        g0 = gpu.observables()
+        gpu.step(1)
+        ref.step(1)
+        compare_fields(gpu, ref, p)
+        compare_particle_forces(gpu, ref, p)
+        compare_bookkeeping(gpu, ref)
+        gpu.step(4)
+        ref.step(4)
+        compare_fields(gpu, ref, p)
+        compare_particle_forces(gpu, ref, p)
+        compare_bookkeeping(gpu, ref)
+        g1, c = gpu.observables(), ref.counts()
+        assert g1["covered_total"] - g0["covered_total"] == c["covered_total"] > 0
+        assert g1["uncovered_total"] - g0["uncovered_total"] == c["uncovered_total"] > 0
+
+
+def test_prescribed_motion_fp32_end_to_end_1000_steps():
+    """The sphere geometry of the 64^3 workload (volume fraction 0.1, r = 4)
+    on a 24^3 box at g = 0.05 < g_c with prescribed motion, FP32 end to end
+    for 1000 steps against the FP64 oracle at the 1e-5 gate (a stable regime,
+    so rounding does not grow); bookkeeping exact."""
+    n = 24
+    p = W.params(nx=n, ny=n, nz=n, rho_init=(0.35, 0.35), noise_amp=0.01, g_br=0.05, seed=1002)
+    count = W.sphere_count((n, n, n), 0.1, 4.0)
+    pos = W.random_sphere_positions((n, n, n), count, 4.0, seed=1002, min_gap=3.0)
+    rng = np.random.default_rng(1002)
+    parts = W.make_particles(pos, 4.0, vel=rng.uniform(-0.02, 0.02, (count, 3)),
+                             omega=rng.uniform(-0.005, 0.005, (count, 3)), prescribed=1)
+    gpu = lbm().Lattice(p, precision="fp32")
+    gpu.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    gpu.step(1000)
+    ref.step(1000)
+    compare_bookkeeping(gpu, ref)
+    compare_fields(gpu, ref, p, tol_rho=1e-5, tol_u=1e-5)
+    og, cr = gpu.observables(), ref.counts()
+    assert og["covered_total"] == cr["covered_total"] > 100
+    assert og["uncovered_total"] == cr["uncovered_total"] > 100
