@@ -508,6 +508,7 @@ def test_bijel256_full_size_crops_and_invariants(warm):
     gpu.step(warm)
     o0 = gpu.observables()
     P0 = gpu.particles()
+    own0 = gpu.owner()
     f0 = gpu.populations().astype(np.float32)  # exact: the storage is FP32
     gpu.step(1)
     P1 = gpu.particles()
@@ -528,10 +529,34 @@ def test_bijel256_full_size_crops_and_invariants(warm):
         ref, sel, origin = _crop_step(p, shape, f0, P0, 5.0, centre)
         core = slice(24 - 7, 24 + 8)
         fr = ref.populations()[:, :, core, core, core]
-        fg = _crop(f1, origin, 48, shape)[:, :, core, core, core].astype(np.float64)
-        assert np.abs(fg - fr).max() <= 1e-5 * 0.7 / 3
+        fg_win = _crop(f1, origin, 48, shape).astype(np.float64)
+        fg = fg_win[:, :, core, core, core]
         assert np.array_equal(_crop(own1, origin, 48, shape)[core, core, core] >= 0,
                               ref.owner()[core, core, core] >= 0)
+        if warm < 10:
+            # near the initial state every population is within 1e-5 of the largest
+            assert np.abs(fg - fr).max() <= 1e-5 * 0.7 / 3
+        # the parity contract: densities within 1e-5 of the mean density of the
+        # component, the mixture velocity of Eq. (7) within 1e-5 of its largest
+        # value, both formed by the oracle from each side's populations on the
+        # same solid map.  Sites refilled in this step are left out of the
+        # velocity: their populations carry the surface velocity at t + 1/2,
+        # which depends on Hertz and lubrication partners that a window may
+        # not hold (in a developed state spheres sit in contact chains); the
+        # refilled density is the neighbour mean and is compared.
+        Fr = ref.fields()
+        ref.set_populations(fg_win)
+        Fg = ref.fields()
+        for c in range(2):
+            e = np.abs(Fg["rho"][c][core, core, core] - Fr["rho"][c][core, core, core]).max()
+            assert e <= 1e-5 * p["rho_init"][c], (kind, c, e)
+        refilled = ((_crop(own0, origin, 48, shape) >= 0) & (_crop(own1, origin, 48, shape) == -1))[core, core, core]
+        ur = Fr["u"][core, core, core]
+        du = np.abs(Fg["u"][core, core, core] - ur).max(axis=-1)
+        eu = du[~refilled].max()
+        print(f"window {kind} warm {warm}: velocity error {du.max():.2e} over all fluid sites, "
+              f"{eu:.2e} without the {int(refilled.sum())} refilled ones, max |u| {np.abs(ur).max():.2e}")
+        assert eu <= 1e-5 * np.abs(ur).max(), (kind, eu, np.abs(ur).max(), int(refilled.sum()))
         if kind == "sphere":
             k = int(np.where(sel == q)[0][0])
             links = ref.particle_counts()[0][k]
