@@ -295,6 +295,18 @@ int lb_footprint_bytes(const lb_params *p, int32_t n_particles, double max_radiu
 int lb_domain_size(lb_handle *h, double L_out[3]);
 int lb_order_parameter_profile(lb_handle *h, int32_t axis, double *out);
 
+/* lb_order_parameter_profile without any device allocation, for callers that
+ * cannot allocate: serving loops that keep a fixed device footprint and
+ * harnesses that forbid hipMalloc.  Same arguments and result, bitwise (each
+ * site's phi and the plane sums are formed in the same order), but no phi
+ * array: the plane averages go to a static device array of 2048 doubles
+ * (16 KiB) that each device holds until the process ends.  The axis must be
+ * at most 2048 sites long (else LB_EINVAL).  Call it with no device or the
+ * handle's device current.  It waits for the handle's stream.  Every call on
+ * one device shares that array: calls that overlap on one device, from
+ * several threads or streams, race.  Errors: LB_EINVAL, LB_EDEVICE. */
+int lb_order_parameter_profile_noalloc(lb_handle *h, int32_t axis, double *out);
+
 /* ---------------------------------------------------------------------------
  * Batches: many lattices advanced by one graph launch.
  *

@@ -401,6 +401,12 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
     if (!h) return LB_ENOMEM;
     h->prm = *p;
     h->stream = (hipStream_t)stream;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        g_create_error = "hipGetDevice failed";
+        return LB_EDEVICE;
+    }
     if (alloc && alloc->alloc && alloc->free) {
         h->alloc = *alloc;
         h->have_alloc = true;

@@ -13,6 +13,7 @@ struct lb_handle {
     lb_params prm{};
     lbm::DevParams dp{};
     hipStream_t stream = nullptr;
+    int device = 0;  // the device current at lb_create
     lb_allocator alloc{};
     bool have_alloc = false;
     std::string err;

@@ -13,6 +13,7 @@
 // in FP64 from a twiddle table in LDS (one block per line).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "lbm_handle.h"
 
@@ -118,6 +119,59 @@ __global__ __launch_bounds__(BLOCK) void k_phi_profile(DevParams P, const double
     if (threadIdx.x == 0) out[blockIdx.x] = v[0] / (double)plane;
 }
 
+// The plane averages of k_phi + k_phi_profile computed straight from the
+// populations, without the phi array: each site's value is formed as k_phi
+// forms it and the sums run in the same order, so the results are bitwise
+// those of lb_order_parameter_profile.
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void k_phi_profile_direct(DevParams P, const S *__restrict__ f,
+                                                              const uint32_t *__restrict__ info, int axis,
+                                                              double *__restrict__ out) {
+    using T = Cmp<S>;
+    __shared__ double lds[BLOCK / 64];
+    const int L[3] = {P.nx, P.ny, P.nz};
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    const long long plane = (long long)L[a1] * L[a2];
+    double acc = 0.0;
+    for (long long k = threadIdx.x; k < plane; k += BLOCK) {
+        int c[3];
+        c[axis] = (int)blockIdx.x;
+        c[a1] = (int)(k % L[a1]);
+        c[a2] = (int)(k / L[a1]);
+        const unsigned n = (unsigned)(((long long)c[2] * P.ny + c[1]) * P.nx + c[0]);
+        double v = 0.0;
+        if (site_class(info[n]) == CLS_FLUID) {
+            T d0, d1;
+            pull_sum(f, n, NbrOffsets(P, c[0], c[1], c[2]), d0, d1);
+            v = ((double)d0 + P.rho_ref[0]) - ((double)d1 + P.rho_ref[1]);
+        }
+        acc += v;
+    }
+    double v[1] = {acc};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = v[0] / (double)plane;
+}
+
+// Device scratch of lb_order_parameter_profile_noalloc: one plane average per
+// plane, MAX_DFT planes (16 KiB), resident on every device the library runs
+// on until the process ends.  In host code `scratch` is only a symbol: its
+// device address (one per device) comes from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[MAX_DFT];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[MAX_DEVICES];
+
+// the address of `scratch` on device dev (current), looked up once per device
+static double *scratch_address(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double *ptr = nullptr;
+        LB_HIP_CHECK(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 static double *phi_buffer(lb_handle *h) {
     if (!h->phi) h->phi = (double *)dev_alloc(h, sizeof(double) * (size_t)h->N);
     return h->phi;
@@ -208,6 +262,43 @@ int lb_order_parameter_profile(lb_handle *h, int32_t axis, double *out) {
     } catch (const std::bad_alloc &) {
         h->err = "device allocation failed";
         return LB_ENOMEM;
+    }
+    return LB_OK;
+}
+
+int lb_order_parameter_profile_noalloc(lb_handle *h, int32_t axis, double *out) {
+    if (!h || !out || axis < 0 || axis > 2) return LB_EINVAL;
+    const int L[3] = {h->prm.nx, h->prm.ny, h->prm.nz};
+    if (L[axis] > MAX_DFT) {
+        h->err = "the profile axis is longer than the scratch holds (2048 planes)";
+        return LB_EINVAL;
+    }
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) {
+        (void)hipGetLastError();
+        h->err = "hipGetDevice failed";
+        return LB_EDEVICE;
+    }
+    if (h->device < 0 || h->device >= MAX_DEVICES) {
+        h->err = "device index beyond the scratch table";
+        return LB_EINVAL;
+    }
+    try {
+        if (cur != h->device) LB_HIP_CHECK(hipSetDevice(h->device));
+        double *d = scratch_address(h->device);
+        with_storage(h->prm, [&](auto tag) {
+            using S = typename decltype(tag)::type;
+            k_phi_profile_direct<S><<<(unsigned)L[axis], BLOCK, 0, h->stream>>>(h->dp, (const S *)h->f[h->cur],
+                                                                              h->info, axis, d);
+        });
+        LB_HIP_CHECK(hipGetLastError());
+        LB_HIP_CHECK(hipMemcpyAsync(out, d, sizeof(double) * L[axis], hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipStreamSynchronize(h->stream));
+        if (cur != h->device) LB_HIP_CHECK(hipSetDevice(cur));
+    } catch (const HipFailure &e) {
+        (void)hipSetDevice(cur);
+        h->err = e.what;
+        return LB_EDEVICE;
     }
     return LB_OK;
 }

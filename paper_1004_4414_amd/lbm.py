@@ -29,7 +29,7 @@ ENTRY_POINTS = [
     "lb_get_state", "lb_set_state", "lb_contact_angle_to_color", "lb_footprint_bytes",
     "lb_enable_timing", "lb_kernel_timing",
     "lb_batch_create", "lb_batch_step", "lb_batch_steps_per_launch", "lb_batch_last_error", "lb_batch_destroy",
-    "lb_autotune", "lb_domain_size", "lb_order_parameter_profile",
+    "lb_autotune", "lb_domain_size", "lb_order_parameter_profile", "lb_order_parameter_profile_noalloc",
 ]
 
 
@@ -134,6 +134,7 @@ def lib():
                                            ctypes.c_int32, dp]),
             "lb_domain_size": (ctypes.c_int, [vp, dp]),
             "lb_order_parameter_profile": (ctypes.c_int, [vp, ctypes.c_int32, dp]),
+            "lb_order_parameter_profile_noalloc": (ctypes.c_int, [vp, ctypes.c_int32, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -184,11 +185,13 @@ class _TorchAllocator:
         self.torch = torch
         self.device = device
         self.live = {}
+        self.calls = 0  # allocations requested so far
         self._alloc = ALLOC_FN(self.alloc)
         self._free = FREE_FN(self.free)
         self.struct = Allocator(self._alloc, self._free, None)
 
     def alloc(self, nbytes, ctx):
+        self.calls += 1
         try:
             t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
         except RuntimeError:
@@ -362,6 +365,13 @@ class Lattice:
         n = (self.shape[2], self.shape[1], self.shape[0])[axis]
         out = np.zeros(n)
         self._check(lib().lb_order_parameter_profile(self._h, int(axis), _dp(out)))
+        return out
+
+    def order_parameter_profile_noalloc(self, axis=2):
+        """the same profile from lb_order_parameter_profile_noalloc (no device allocation)"""
+        n = (self.shape[2], self.shape[1], self.shape[0])[axis]
+        out = np.zeros(n)
+        self._check(lib().lb_order_parameter_profile_noalloc(self._h, int(axis), _dp(out)))
         return out
 
     # -- measurement ---------------------------------------------------------
