@@ -103,6 +103,8 @@ void set_dev_params(lb_handle *h) {
     d.eq_order = p.eq_order;
     d.wall_axis = p.wall_axis;
     d.lub_mode = p.lub_mode;
+    d.any_color = 0;
+    for (double c : h->h_color) d.any_color |= c != 0.0;
     for (int a = 0; a < 3; ++a) {
         d.body[a] = p.body_accel[a];
         d.wall_vel[0][a] = p.wall_vel[0][a];
@@ -120,8 +122,6 @@ int validate_params(const lb_params *p, std::string &msg) {
     const long long N = (long long)p->nx * p->ny * p->nz;
     if (N > 0x7fffffffLL / 2) return msg = "box too large (sites must fit 30 bits)", LB_EINVAL;
     if (p->precision < LB_FP64 || p->precision > LB_BF16) return msg = "unknown precision", LB_EINVAL;
-    if ((p->precision == LB_FP16 || p->precision == LB_BF16) && p->kernel == LB_KERNEL_FUSED)
-        return msg = "the fused kernel stores FP32 or FP64 populations only", LB_EINVAL;
     for (int c = 0; c < 2; ++c)
         if (!(p->tau[c] > 0.5)) return msg = "tau must exceed 1/2", LB_EINVAL;
     if (!(p->rho0 > 0.0)) return msg = "rho0 must be positive", LB_EINVAL;
@@ -171,7 +171,7 @@ size_t fluid_bytes(const lb_params *p) {
 size_t particle_bytes(const lb_params *p, int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
     const size_t cells = (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
-    size_t b = (size_t)np * (37 * 8 + (19 + MAX_LUB_CONTACTS) * 4 + MAX_LUB_CONTACTS * 32) + 4 * cells;
+    size_t b = (size_t)np * (41 * 8 + (22 + MAX_LUB_CONTACTS + CAND_CAP) * 4 + MAX_LUB_CONTACTS * 32) + 4 * cells;
     const double reach = 2.0 * max_r + std::max(p->lub_hc, 0.0);  // cell list of the pair search
     if (reach > 0.0) b += 8 * (size_t)(p->nx / reach + 1) * (size_t)(p->ny / reach + 1) * (size_t)(p->nz / reach + 1);
     b += (size_t)np * sc * (4 + 2 * 4);  // virtual-fluid sites, covered and uncovered sites
@@ -185,7 +185,9 @@ void rebuild_map(lb_handle *h) {
     launch_fill_int(h, h->stage, h->N, STAGE_NONE);
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.Rprev, h->dpart.R, sizeof(double) * 3 * h->np, hipMemcpyDeviceToDevice,
                                 h->stream));
-    launch_map_mark(h, false);
+    LB_HIP_CHECK(hipMemcpyAsync(h->dpart.Rscan, h->dpart.R, sizeof(double) * 3 * h->np, hipMemcpyDeviceToDevice,
+                                h->stream));
+    launch_map_mark(h, true);  // every sphere is classified afresh
     launch_map_commit(h, true);
     launch_info_dense(h);
     launch_fill_int(h, h->stage, h->N, STAGE_NONE);
@@ -261,27 +263,17 @@ int check_device_state(lb_handle *h) {
     return LB_OK;
 }
 
-// fused-kernel tile: explicit request, else the widest of the compiled shapes
-// that fits the box in x
+// fused-kernel tile: 64 sites wide (a wavefront per row), ty rows (4 or 8;
+// FP64 4) and a z segment of tz planes (default 64)
 void choose_fused_tile(lb_handle *h) {
     const lb_params &p = h->prm;
-    int tx = p.tile[0], ty = p.tile[1], tz = p.tile[2];
-    // compiled shapes; a tile must satisfy tx <= nx - 2, ty <= ny - 2
-    auto fits = [&](int a, int b) { return a <= p.nx - 2 && b <= p.ny - 2; };
-    bool known;
-    if (p.precision == LB_FP64)
-        known = (tx == 32 && ty == 4) || (tx == 16 && ty == 8);
-    else
-        known = (tx == 64 && ty == 4) || (tx == 32 && ty == 8) || (tx == 32 && ty == 4) || (tx == 16 && ty == 8);
-    if (!known || !fits(tx, ty)) {
-        if (p.precision != LB_FP64 && fits(64, 4)) tx = 64, ty = 4;
-        else if (fits(32, 4)) tx = 32, ty = 4;
-        else tx = 16, ty = 8;
-    }
-    if (tz <= 0) tz = 32;
-    h->fused_tx = tx;
+    int ty = p.tile[1], tz = p.tile[2];
+    if (ty != 4 && ty != 8) ty = 4;
+    if (p.precision == LB_FP64) ty = 4;
+    if (tz <= 0) tz = 64;
+    h->fused_tx = 64;
     h->fused_ty = ty;
-    h->fused_tz = std::max(1, std::min(tz, p.nz - 1));
+    h->fused_tz = std::max(1, std::min(tz, p.nz));
 }
 
 void enqueue_step(lb_handle *h) {
@@ -307,7 +299,7 @@ void enqueue_step(lb_handle *h) {
         launch_particle_fluid_force(h, fout);
         launch_pair_forces(h);
         launch_integrate(h);
-        launch_map_mark(h, true);  // also clears the dirty cells
+        launch_map_mark(h, false);  // also clears the dirty cells
         launch_map_events(h);
         launch_cover_refill(h, fout);
         launch_map_commit(h, false);
@@ -600,6 +592,18 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.ncont = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
     D.cont = (int32_t *)dev_alloc(h, sizeof(int32_t) * MAX_LUB_CONTACTS * (size_t)tot);
     D.vs = (double *)dev_alloc(h, sizeof(double) * 3 * (size_t)tot);
+    D.Rscan = (double *)dev_alloc(h, sizeof(double) * 3 * (size_t)tot);
+    D.margin = (double *)dev_alloc(h, sizeof(double) * (size_t)tot);
+    D.frozen = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+    D.touch = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+    D.ncand = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+    D.cand = (int32_t *)dev_alloc(h, sizeof(int32_t) * CAND_CAP * (size_t)tot);
+    h->part_allocs.push_back(D.ncand);
+    h->part_allocs.push_back(D.cand);
+    h->part_allocs.push_back(D.Rscan);
+    h->part_allocs.push_back(D.margin);
+    h->part_allocs.push_back(D.frozen);
+    h->part_allocs.push_back(D.touch);
     D.cont_c = (double *)dev_alloc(h, sizeof(double) * MAX_LUB_CONTACTS * (size_t)tot);
     D.cont_n = (double *)dev_alloc(h, sizeof(double) * 3 * MAX_LUB_CONTACTS * (size_t)tot);
     h->part_allocs.push_back(D.cont_c);
@@ -611,7 +615,8 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     h->part_allocs.push_back(D.vs);
     {  // cell list of the pair search: cells at least 2 r_max + h_c wide
         const double rmax = *std::max_element(rad.begin(), rad.end());
-        const double reach = 2.0 * rmax + std::max(h->prm.lub_hc, 0.0);
+        // (TOUCH_SLACK: pairs that may share sites are found as well)
+        const double reach = 2.0 * rmax + std::max(h->prm.lub_hc, 0.0) + 1e-5;
         int pg[3];
         for (int a = 0; a < 3; ++a) pg[a] = reach > 0.0 ? (int)(L[a] / reach) : 1;
         if (pg[0] >= 3 && pg[1] >= 3 && pg[2] >= 3 && (long long)pg[0] * pg[1] * pg[2] <= (1 << 22)) {

@@ -247,6 +247,7 @@ struct DevParams {
     double tau[2];
     double g, rho0, w_face, w_edge;
     int velocity_mode, eq_order, wall_axis, lub_mode;
+    int any_color, pad2;  // any sphere with a non-zero colour (Sec. IV)
     double rho_init[2];
     double rho_ref[2];  // populations are stored as f_i - zeta_i rho_ref^c
     double psi_e[2];    // rho0 exp(-rho_ref^c / rho0): Psi(rho_ref + d) - Psi(rho_ref) = -psi_e expm1(-d/rho0)
@@ -277,6 +278,15 @@ struct DevState {
 // per-particle arrays (FP64), each np*3 unless noted
 struct DevParticles {
     double *R, *U, *W, *Rprev;
+    // discretisation skip: Rscan is the centre of the last classification of
+    // the sphere's sites; cand lists the sites closer than margin (tau) to
+    // that sphere's surface, with bit 31 set on those inside; ncand their
+    // number.  While the fixed-point centre stays closer than tau to Rscan
+    // only those sites can change side, and when none of them does and the
+    // sphere touches no other (touch, from the pair search) it is frozen:
+    // its map update is skipped
+    double *Rscan, *margin;
+    int32_t *frozen, *touch, *cand, *ncand;
     double *Ffl, *Tfl, *Ftot, *Ttot, *P, *PT;
     double *rad, *mass, *inertia, *color;  // np each
     int32_t *prescribed;
@@ -307,6 +317,7 @@ struct DevParticles {
 };
 constexpr int CELL_SHIFT = 3;  // coarse cells of 8^3 sites
 constexpr int MAX_LUB_CONTACTS = 32;
+constexpr int CAND_CAP = 256;  // near-surface sites kept per sphere
 
 
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
@@ -470,6 +481,33 @@ __device__ __forceinline__ bool inside_sphere(int x, int y, int z, const long lo
         d2 += d * d;
     }
     return d2 < r2q;
+}
+
+// squared fixed-point distance of site (x, y, z) from the centre cq (minimum
+// image), the quantity the inside test compares with r^2
+// (x in [0, L) and a centre rounded from [0, L): one wrap suffices)
+__device__ __forceinline__ long long dist2_sphere(int x, int y, int z, const long long cq[3], int nx, int ny, int nz) {
+    const int pos[3] = {x, y, z};
+    const int L[3] = {nx, ny, nz};
+    long long d2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long Lq = (long long)L[a] << 20;
+        long long d = ((long long)pos[a] << 20) - cq[a];
+        if (d > Lq / 2) d -= Lq;
+        else if (d <= -(Lq / 2)) d += Lq;
+        d2 += d * d;
+    }
+    return d2;
+}
+__device__ __forceinline__ long long dist2_unwrapped(const int u[3], const long long cq[3]) {
+    long long d2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long d = ((long long)u[a] << 20) - cq[a];
+        d2 += d * d;
+    }
+    return d2;
 }
 
 // The same test on unwrapped box coordinates u (u = x mod L): equal to
@@ -786,29 +824,30 @@ struct RowView {
 // whole lines that no other wavefront reads in this sweep (every slot has
 // exactly one puller), so it streams past the caches; with c_ix != 0 the
 // run straddles a line that the neighbouring wavefront reads too.
-template <int I, typename S>
+template <int I, typename S, bool STREAM = true>
 __device__ __forceinline__ Pair<Cmp<S>> load_pull(const S *__restrict__ at) {
-    if constexpr (cx(I) == 0)
+    if constexpr (STREAM && cx(I) == 0)
         return Storage<S>::load_stream(at, 0);
     else
         return Storage<S>::load(at, 0);
 }
 
-// f_i(x) = slot (i, x - c_i), row-aligned addressing
-template <typename S, typename T = Cmp<S>>
+// f_i(x) = slot (i, x - c_i), row-aligned addressing; STREAM: the pulls
+// that no other wavefront reads carry the streaming hint
+template <typename S, bool STREAM = true, typename T = Cmp<S>>
 __device__ __forceinline__ void pull_load_rows(const S *__restrict__ fin, const RowView<S> &rv, T (&f)[2][Q]) {
     const char *base = reinterpret_cast<const char *>(fin);
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const char *row = base + rv.row(-cy(i), -cz(i)) * rv.prow + (size_t)i * RowView<S>::DB;
-        const Pair<T> v = load_pull<i>(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]));
+        const Pair<T> v = load_pull<i, S, STREAM>(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]));
         f[0][i] = v.x;
         f[1][i] = v.y;
     });
 }
 
 // sum_i f_i(x) of both components, row-aligned addressing
-template <typename S, typename T = Cmp<S>>
+template <typename S, bool STREAM = true, typename T = Cmp<S>>
 __device__ __forceinline__ void pull_sum_rows(const S *__restrict__ fin, const RowView<S> &rv, T &s0, T &s1) {
     const char *base = reinterpret_cast<const char *>(fin);
     s0 = 0;
@@ -816,7 +855,7 @@ __device__ __forceinline__ void pull_sum_rows(const S *__restrict__ fin, const R
     Unroll<Q>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const char *row = base + rv.row(-cy(i), -cz(i)) * rv.prow + (size_t)i * RowView<S>::DB;
-        const Pair<T> v = load_pull<i>(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]));
+        const Pair<T> v = load_pull<i, S, STREAM>(reinterpret_cast<const S *>(row + rv.po[1 - cx(i)]));
         s0 += v.x;
         s1 += v.y;
     });
@@ -912,6 +951,17 @@ __device__ __forceinline__ void put_shell_force(T (&f)[2][Q], const T (&F)[3], u
         f[0][i] = i == j0 ? F[2] : f[0][i];
         f[1][i] = i == j0 ? (T)0 : f[1][i];
     }
+}
+
+// Shan-Chen force of Eq. (4) on a virtual-fluid site, kept for the particle
+// sums: Psi of the site is its stored deviation plus Psi(rho_ref) = rho0 - psi_e
+template <typename T>
+__device__ __forceinline__ void shell_force(const DevParams &P, const T (&own)[2], const T (&acc)[2][3], T (&F)[3]) {
+    const T g = (T)P.g;
+    const T ps0 = own[0] + (T)(P.rho0 - P.psi_e[0]);
+    const T ps1 = own[1] + (T)(P.rho0 - P.psi_e[1]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
 }
 
 // ---------------------------------------------------------------------------

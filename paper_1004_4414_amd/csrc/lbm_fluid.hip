@@ -298,17 +298,6 @@ __device__ __forceinline__ void load_psi_neighbours_rows(const T *__restrict__ p
     });
 }
 
-// Shan-Chen force of Eq. (4) on a virtual-fluid site, kept for the particle
-// sums: Psi of the site is its stored deviation plus Psi(rho_ref) = rho0 - psi_e
-template <typename T>
-__device__ __forceinline__ void shell_force(const DevParams &P, const T (&own)[2], const T (&acc)[2][3], T (&F)[3]) {
-    const T g = (T)P.g;
-    const T ps0 = own[0] + (T)(P.rho0 - P.psi_e[0]);
-    const T ps1 = own[1] + (T)(P.rho0 - P.psi_e[1]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) F[a] = -ps0 * g * acc[1][a] - ps1 * g * acc[0][a];
-}
-
 // ---------------------------------------------------------------------------
 // collide and stream (two-pass variant, second sweep): populations of the
 // site, Psi of the neighbours from the Psi array.  On shell sites it stores

@@ -14,6 +14,11 @@
 
 namespace lbm {
 
+// spheres closer than r_a + r_b + TOUCH_SLACK may share lattice sites (the
+// fixed-point radius exceeds r by at most 2^-21)
+constexpr double TOUCH_SLACK = 1e-5;
+constexpr int INFO_TILE = 8192;  // owners of a class-word box and its rim held in LDS
+
 __device__ __forceinline__ void load3(const double *a, int p, double v[3]) {
     v[0] = a[3 * p];
     v[1] = a[3 * p + 1];
@@ -134,8 +139,9 @@ __device__ __forceinline__ void axis_cells(const DevParams &P, const int lo[3], 
         ac.lo[a] = lo[a] - 1;
         ac.ext[a] = ext[a] > 0 ? ext[a] + 2 : 0;
         int k = 0, last = -1;
-        for (int u = lo[a] - 1; ext[a] > 0 && u <= lo[a] + ext[a]; ++u) {
-            const int cell = wrapany(u, L[a]) >> CELL_SHIFT;
+        int w = ext[a] > 0 ? wrapany(lo[a] - 1, L[a]) : 0;  // the wrapped coordinate, stepped along
+        for (int u = lo[a] - 1; ext[a] > 0 && u <= lo[a] + ext[a]; ++u, w = w + 1 == L[a] ? 0 : w + 1) {
+            const int cell = w >> CELL_SHIFT;
             if (cell != last) {
                 if (k == MAX_AXIS_CELLS) {
                     ac.wide = 1;
@@ -381,6 +387,7 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
     double F[3] = {0, 0, 0};
     int ncont = 0;
+    int touch = 0;  // another sphere closer than the two radii (they may share sites)
     double nu = 0.0;  // mean kinematic viscosity of the two components
     for (int c = 0; c < 2; ++c) nu += (1.0 / 3.0) * (P.tau[c] - 0.5);
     nu /= 2.0;
@@ -394,6 +401,7 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
                 dist2 += d[a] * d[a];
             }
             const double rsum = rp + D.rad[q];
+            touch |= dist2 < (rsum + TOUCH_SLACK) * (rsum + TOUCH_SLACK);
             const double reach = rsum + (P.lub_hc > 0.0 ? P.lub_hc : 0.0);
             if (dist2 < reach * reach) {
                 const double dist = sqrt(dist2);
@@ -436,7 +444,9 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
         }
     }
     block_sum<3>(F, lds);
+    touch = __syncthreads_or(touch);
     if (threadIdx.x == 0) {
+        D.touch[p] = touch != 0;
         D.ncont[p] = P.lub_mode == 0 ? 0 : min(ncont, MAX_LUB_CONTACTS);
         if (P.lub_mode != 0 && ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
@@ -560,6 +570,7 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
     if (K > PAIR_MAX_CAND) {
         if (t == 0) {
             D.ncont[p] = 0;
+            D.touch[p] = 1;
             atomicOr(&st->overflow, 16);
         }
         return;
@@ -588,6 +599,7 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
         }
     double F[3] = {0, 0, 0};
     int ncont = 0;
+    bool touch = false;  // another sphere closer than the two radii (they may share sites)
     for (int j0 = 0; j0 < K; j0 += 64) {
         const int j = j0 + t;
         const int q = j < K ? cand[j] : -1;
@@ -599,6 +611,7 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
                 dist2 += d[a] * d[a];
             }
             const double rsum = rp + D.rad[q];
+            touch = touch || dist2 < (rsum + TOUCH_SLACK) * (rsum + TOUCH_SLACK);
             const double reach = rsum + (P.lub_hc > 0.0 ? P.lub_hc : 0.0);
             if (dist2 < reach * reach) {
                 const double dist = sqrt(dist2);
@@ -645,7 +658,9 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         for (int off = 32; off > 0; off >>= 1) F[a] += __shfl_down(F[a], off, 64);
+    const bool any_touch = __ballot(touch) != 0ull;
     if (t == 0) {
+        D.touch[p] = any_touch;
         D.ncont[p] = P.lub_mode == 0 ? 0 : min(ncont, MAX_LUB_CONTACTS);
         if (P.lub_mode != 0 && ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
@@ -685,7 +700,6 @@ __device__ __forceinline__ void integrate_body(DevParams P, DevParticles D, DevS
     }
     bool fast = false;
     for (int a = 0; a < 3; ++a) {
-        D.Rprev[3 * p + a] = D.R[3 * p + a];
         D.Ftot[3 * p + a] += imp[a];
         if (!D.prescribed[p]) {
             D.U[3 * p + a] = D.vs[3 * p + a] + imp[a] / D.mass[p];
@@ -711,32 +725,95 @@ __global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
 // solid map: every site inside sphere p (at its current position) proposes p;
 // the lowest index wins.  stage[] holds STAGE_NONE everywhere else.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void map_mark_body(DevParams P, DevParticles D, int32_t *__restrict__ stage, const Grid &g) {
+__device__ __forceinline__ void map_mark_body(DevParams P, DevParticles D, int32_t *__restrict__ stage, int full,
+                                              const Grid &g) {
     const int p = g.bid;
     {  // the blocks also clear the coarse dirty cells of the previous step, a slice each
         const int ncell = D.cgx * D.cgy * D.cgz;
         const int per = (ncell + (int)g.nb - 1) / (int)g.nb;
         for (int c = p * per + threadIdx.x; c < min(ncell, (p + 1) * per); c += BLOCK) D.dirty[c] = 0;
     }
-    int lo[3], ext[3];
-    new_box(P, D, p, lo, ext);
     long long cq[3];
     for (int a = 0; a < 3; ++a) cq[a] = fixed20(D.R[3 * p + a]);
     const long long rq = fixed20(D.rad[p]);
     const long long r2q = rq * rq;
+    // Frozen: no other sphere can share its sites, the fixed-point centre C'
+    // is closer than tau to the centre C of the last classification, and none
+    // of the sites within tau of that sphere's surface changes side (the
+    // others cannot: |x - C'| and |x - C| differ by at most |C' - C|).  Every
+    // thread takes the same decision.
+    bool frz = !full && !D.touch[p];
+    if (frz) {
+        long long d2 = 0;
+        for (int a = 0; a < 3; ++a) {
+            const long long Lq = (long long)(a == 0 ? P.nx : (a == 1 ? P.ny : P.nz)) << 20;
+            long long d = cq[a] - fixed20(D.Rscan[3 * p + a]);
+            if (d > Lq / 2) d -= Lq;
+            else if (d <= -(Lq / 2)) d += Lq;
+            d2 += d * d;
+            frz = frz && fabs(D.U[3 * p + a]) < 1.0;
+        }
+        frz = frz && sqrt((double)d2) * (1.0 / 1048576.0) < D.margin[p] - 1e-9;
+    }
+    if (frz) {
+        const int nc = D.ncand[p];
+        const int32_t *cd = D.cand + (size_t)p * CAND_CAP;
+        bool flip = false;
+        for (int k = threadIdx.x; k < nc; k += BLOCK) {
+            const uint32_t e = (uint32_t)cd[k];
+            int x, y, z;
+            site_xyz(e & 0x7fffffffu, P, x, y, z);
+            flip = flip || (dist2_sphere(x, y, z, cq, P.nx, P.ny, P.nz) < r2q) != ((e >> 31) != 0u);
+        }
+        frz = !__syncthreads_or(flip);
+    }
+    if (threadIdx.x == 0) {
+        D.frozen[p] = frz;
+        if (!frz)  // the previous classification's centre (for the union boxes) and the new one
+            for (int a = 0; a < 3; ++a) {
+                D.Rprev[3 * p + a] = D.Rscan[3 * p + a];
+                D.Rscan[3 * p + a] = D.R[3 * p + a];
+            }
+    }
+    if (frz) return;  // uniform over the block
+    int lo[3], ext[3];
+    new_box(P, D, p, lo, ext);
     const BoxWalk bw(P, lo, ext);
     const bool near = near_box(lo, ext, cq, P);
     const int V = bw.size();
-    for (int k = threadIdx.x; k < V; k += BLOCK) {
-        int u[3], x, y, z;
-        bw.site(k, P, u, x, y, z);
-        const bool in = near ? inside_unwrapped(u, cq, r2q) : inside_sphere(x, y, z, cq, r2q, P.nx, P.ny, P.nz);
-        if (in) atomicMin(&stage[site_of(x, y, z, P)], p);
+    // the sites within tau of the sphere's surface (every site within one
+    // site of it lies in the box); tau is chosen so that about 64 qualify
+    __shared__ int lds[BLOCK / 64 + 1];
+    const double r = D.rad[p];
+    const double tau = fmin(0.5, 64.0 / (8.0 * M_PI * r * r));
+    int32_t *cd = D.cand + (size_t)p * CAND_CAP;
+    int nc = 0;
+    for (int k0 = 0; k0 < V; k0 += BLOCK) {
+        const int k = k0 + threadIdx.x;
+        bool near_surface = false;
+        bool in = false;
+        long long n = 0;
+        if (k < V) {
+            int u[3], x, y, z;
+            bw.site(k, P, u, x, y, z);
+            const long long d2 = near ? dist2_unwrapped(u, cq) : dist2_sphere(x, y, z, cq, P.nx, P.ny, P.nz);
+            n = site_of(x, y, z, P);
+            in = d2 < r2q;
+            if (in) atomicMin(&stage[n], p);
+            near_surface = fabs(sqrt((double)d2) - (double)rq) * (1.0 / 1048576.0) < tau;
+        }
+        const int slot = block_compact(near_surface, nc, lds);
+        if (near_surface && slot < CAND_CAP) cd[slot] = (int32_t)((uint32_t)n | (in ? 0x80000000u : 0u));
+    }
+    if (threadIdx.x == 0) {
+        D.ncand[p] = min(nc, CAND_CAP);
+        D.margin[p] = nc <= CAND_CAP ? tau : 0.0;  // a full list only: else never frozen
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage) {
-    map_mark_body(P, D, stage, own_grid());
+__global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage,
+                                                    int full) {
+    map_mark_body(P, D, stage, full, own_grid());
 }
 
 // covered (fluid -> inside p) and uncovered (inside p -> fluid) sites of
@@ -745,6 +822,14 @@ __device__ __forceinline__ void map_events_body(DevParams P, DevParticles D, con
                                                       const int32_t *__restrict__ stage, DevState *st, const Grid &g) {
     __shared__ int lds[8];
     const int p = g.bid;
+    if (D.frozen[p]) {  // uniform over the block: its sites keep their owner
+        if (threadIdx.x == 0) {
+            D.cov_cnt[p] = 0;
+            D.unc_cnt[p] = 0;
+            D.changed[p] = 0;
+        }
+        return;
+    }
     int lo[3], ext[3];
     union_box(P, D, p, 0, lo, ext);
     const BoxWalk bw(P, lo, ext);
@@ -936,8 +1021,11 @@ __device__ __forceinline__ void map_commit_body(DevParams P, DevParticles D, int
         int u[3], x, y, z;
         bw.site(k, P, u, x, y, z);
         const long long n = site_of(x, y, z, P);
-        const int32_t s = stage[n];
-        owner[n] = s == STAGE_NONE ? OWN_FLUID : s;
+        const int32_t s = stage[n], o = owner[n];
+        // a frozen sphere did not mark, and still holds the sites it owns
+        // (no sphere shares them); the lowest index wins as ever.  Every block
+        // writes the same value, whichever it reads first.
+        owner[n] = (o >= 0 && D.frozen[o]) ? min(o, s) : (s == STAGE_NONE ? OWN_FLUID : s);
     }
 }
 
@@ -950,17 +1038,58 @@ __global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles 
 __device__ __forceinline__ void map_info_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
                                                     uint32_t *__restrict__ info, int32_t *__restrict__ stage, const Grid &g) {
     const int p = g.bid;
+    if (D.frozen[p]) return;  // no change and no marks (uniform over the block)
     int lo[3], ext[3];
     int V;
     if (D.changed[p]) {
         union_box(P, D, p, 1, lo, ext);
         const BoxWalk bw(P, lo, ext);
         V = bw.size();
-        for (int k = threadIdx.x; k < V; k += BLOCK) {
-            int u[3], x, y, z;
-            bw.site(k, P, u, x, y, z);
-            const long long n = site_of(x, y, z, P);
-            info[n] = compute_info_at(n, x, y, z, P, owner);
+        // the owners of the box and its one-site rim, read once into LDS; each
+        // class word is then formed from its 18 neighbours there (boxes too
+        // large for the tile take them from global memory)
+        __shared__ int32_t tile[INFO_TILE];
+        const int gext[3] = {ext[0] + 2, ext[1] + 2, ext[2] + 2};
+        const int glo[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};
+        const int TV = gext[0] * gext[1] * gext[2];
+        if (TV <= INFO_TILE) {
+            const BoxWalk tw(P, glo, gext);
+            for (int k = threadIdx.x; k < TV; k += BLOCK) {
+                int u[3], x, y, z;
+                tw.site(k, P, u, x, y, z);
+                tile[k] = owner[site_of(x, y, z, P)];
+            }
+            __syncthreads();
+            for (int k = threadIdx.x; k < V; k += BLOCK) {
+                int u[3], x, y, z;
+                bw.site(k, P, u, x, y, z);
+                const int c = ((u[2] - glo[2]) * gext[1] + (u[1] - glo[1])) * gext[0] + (u[0] - glo[0]);
+                const int32_t own = tile[c];
+                uint32_t word;
+                if (own == OWN_WALL_LO || own == OWN_WALL_HI) {
+                    word = (uint32_t)CLS_WALL << CLS_SHIFT;
+                } else {
+                    uint32_t mask = 0;
+                    bool any_fluid = false;
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) {
+                        const int32_t o = tile[c + (cz(i) * gext[1] + cy(i)) * gext[0] + cx(i)];
+                        if (o != OWN_FLUID) mask |= 1u << i;
+                        else any_fluid = true;
+                    }
+                    word = own == OWN_FLUID ? mask
+                                            : (any_fluid ? ((uint32_t)CLS_SHELL << CLS_SHIFT) | mask
+                                                         : (uint32_t)CLS_SOLID << CLS_SHIFT);
+                }
+                info[site_of(x, y, z, P)] = word;
+            }
+        } else {
+            for (int k = threadIdx.x; k < V; k += BLOCK) {
+                int u[3], x, y, z;
+                bw.site(k, P, u, x, y, z);
+                const long long n = site_of(x, y, z, P);
+                info[n] = compute_info_at(n, x, y, z, P, owner);
+            }
         }
     }
     new_box(P, D, p, lo, ext);
@@ -1073,9 +1202,9 @@ void launch_integrate(lb_handle *h) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
-void launch_map_mark(lb_handle *h, bool) {
+void launch_map_mark(lb_handle *h, bool full) {
     if (!h->np) return;
-    k_map_mark<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->stage);
+    k_map_mark<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->stage, full ? 1 : 0);
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -1157,7 +1286,7 @@ __global__ void kb_integrate(BatchPlan B) {
 __global__ __launch_bounds__(BLOCK) void kb_map_mark(BatchPlan B) {
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
-    map_mark_body(M.P, M.D, M.stage, g);
+    map_mark_body(M.P, M.D, M.stage, 0, g);
 }
 __global__ __launch_bounds__(BLOCK) void kb_map_events(BatchPlan B) {
     Grid g;
