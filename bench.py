@@ -35,22 +35,30 @@ def algorithmic_bytes_per_site(precision):
     return 2 * 19 * ts * 2
 
 
-def measured_traffic():
-    """HBM bytes per launch of the collide sweep from the committed counter
-    summary, or None when the sweep's sources changed since it was taken"""
+def measured_traffic(kernel, precision, tile):
+    """HBM bytes per launch of the dominant sweep from the committed counter
+    summary of that sweep, or None when its sources changed since the
+    counters were taken"""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "bijel256_collide_traffic.md")
+    name = {("twopass", "fp32"): "bijel256_collide_traffic.md",
+            ("fused", "fp32"): "bijel256_fused_traffic.md"}.get((kernel, precision))
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    h = hashlib.sha256()
-    for f in ("lbm_device.h", "lbm_fluid.hip"):
-        with open(os.path.join(ROOT, "paper_1004_4414_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    m_hash = re.search(r"source-sha256 \(lbm_device.h \+ lbm_fluid.hip\): ([0-9a-f]{64})", text)
+    m_files = re.search(r"source-sha256 \(([^)]*)\): ([0-9a-f]{64})", text)
     m_bytes = re.search(r"traffic-bytes-per-launch: (\d+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != h.hexdigest():
+    m_tile = re.search(r"tile: (\S+)", text)
+    if not m_files or not m_bytes or (m_tile and m_tile.group(1) != tile):
+        return None
+    h = hashlib.sha256()
+    for f in m_files.group(1).split(" + "):
+        with open(os.path.join(ROOT, "paper_1004_4414_amd", "csrc", f.strip()), "rb") as fh:
+            h.update(fh.read())
+    if m_files.group(2) != h.hexdigest():
         return None
     return int(m_bytes.group(1))
 
@@ -72,10 +80,9 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(seconds_budget=20.0):
-    """The FP64 oracle, single-threaded, on a bounded sample of the workload:
-    a 64^3 box with the same volume fraction (75 spheres of radius 5) and the
-    same fluid parameters, stepped until about `seconds_budget` have passed."""
+def _oracle_sample(seconds_budget):
+    """(sites, steps, seconds) of the FP64 oracle stepping the bounded sample
+    (a 64^3 box at the workload's volume fraction and fluid parameters)"""
     from oracle.oracle import Oracle
     from paper_1004_4414_amd import workloads as W
     n = 64
@@ -92,9 +99,73 @@ def cpu_baseline(seconds_budget=20.0):
         dt = time.perf_counter() - t0
         if dt > seconds_budget or steps >= 200:
             break
-    return dict(value=n ** 3 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"64^3 box, {count} spheres of radius 5 (volume fraction 0.15), g=0.08, "
-                       f"{steps} steps, single thread")
+    return n ** 3, steps, dt
+
+
+def _oracle_worker(args):
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    return _oracle_sample(args)
+
+
+def cpu_baseline(seconds_budget=12.0):
+    """The FP64 oracle on the host on a bounded sample of the workload: a 64^3
+    box with the same volume fraction (75 spheres of radius 5) and fluid
+    parameters, stepped for about `seconds_budget` on one core, then as
+    independent copies on every core this process may use (the oracle itself
+    is single-threaded)."""
+    import multiprocessing as mp
+    sites, steps, dt = _oracle_sample(seconds_budget)
+    one = sites * steps / dt / 1e6
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(ncores, 16))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_worker, [seconds_budget] * workers)
+    wall = time.perf_counter() - t0
+    total = sum(s * k for s, k, _ in res)
+    allc = total / max(wall, max(d for _, _, d in res)) / 1e6
+    return dict(value=round(allc, 3), unit="MLUPS", cores=workers, kind="oracle",
+                single_core_mlups=round(one, 3), host_cpus=os.cpu_count(), affinity_cpus=ncores,
+                sample=f"64^3 box, {W_count()} spheres of radius 5 (volume fraction 0.15), g=0.08; "
+                       f"one copy per core for about {seconds_budget:.0f} s each ({workers} copies), "
+                       f"and one copy alone ({steps} steps); the 256^3 workload itself takes about "
+                       f"{sites * 64 / (one * 1e6):.0f} s per oracle step on one core")
+
+
+def W_count():
+    from paper_1004_4414_amd import workloads as W
+    return W.sphere_count((64, 64, 64), 0.15, 5.0)
+
+
+def serving_leg(seconds_hint=None):
+    """A short served trace on the default line: 8 jobs (edges 32-64, radii
+    4-6, fractions 0.05-0.15, 200-400 steps, BF16 storage) arriving over half
+    a second, through the continuous-batching server; jobs/hour and p50/p99
+    time-to-result."""
+    import torch
+    from paper_1004_4414_amd import serving as S, workloads as W
+    rng = __import__("numpy").random.Generator(__import__("numpy").random.PCG64(1006))
+    jobs = []
+    t = 0.0
+    for k in range(8):
+        t += float(rng.exponential(0.06))
+        edge = int(rng.choice([32, 48, 64]))
+        job = W._job(rng, edge, float(rng.uniform(0.5, 0.7)), float(rng.uniform(0.05, 0.15)),
+                     float(rng.uniform(4.0, 6.0)), float(rng.uniform(60.0, 120.0)),
+                     int(rng.integers(20, 41)) * 10, 1006 * 1000 + k)
+        jobs.append(S.Job(job["params"], job["particles"], job["steps"], arrival=t,
+                          contact_angle=job["contact_angle"], name=f"job{k}"))
+    free, _ = torch.cuda.mem_get_info()
+    small = min(jobs, key=lambda j: (j.params["nx"], j.steps))
+    srv = S.Server(int(0.5 * free), precision="bf16", steps_per_launch=10, keep_density=(small.name,))
+    out = srv.run(jobs)
+    res = S.summary(out)
+    err = next((S.density_error(r, small) for r in out if r.name == small.name and r.observables is not None), None)
+    return dict(jobs_per_hour=round(res["jobs_per_hour"], 1), p50_s=round(res["p50_s"], 4),
+                p99_s=round(res["p99_s"], 4), jobs=res["jobs"], failed=res["failed"], launches=srv.launches,
+                batch_rebuilds=srv.batch_rebuilds, dtype="bf16", error_vs_fp64=err,
+                workload="8 jobs, edges 32-64, radii 4-6, fractions 0.05-0.15, 200-400 steps, BF16 storage "
+                         "(FP32 arithmetic), arrivals over about half a second")
 
 
 def bench_ensemble(args):
@@ -190,8 +261,11 @@ def bench_serving(args):
                   name=f"job{i}") for i, t in enumerate(trace)]
     free, total = torch.cuda.mem_get_info()
     budget = int(0.6 * free)
-    srv = S.Server(budget, precision="bf16", steps_per_launch=k)
-    served = S.summary(srv.run(jobs))
+    small = min(jobs, key=lambda j: (j.params["nx"], j.steps))
+    srv = S.Server(budget, precision="bf16", steps_per_launch=k, keep_density=(small.name,))
+    out = srv.run(jobs)
+    served = S.summary(out)
+    err = next((S.density_error(r, small) for r in out if r.name == small.name and r.observables is not None), None)
     print(f"# served: {served}, batch rebuilds {srv.batch_rebuilds}", file=sys.stderr, flush=True)
     alone = S.summary(S.run_alone(jobs, precision="fp32"))
     print(f"# one at a time (FP32): {alone}", file=sys.stderr, flush=True)
@@ -200,11 +274,12 @@ def bench_serving(args):
         "value": round(served["jobs_per_hour"], 1), "unit": "jobs/hour", "n_gpus": 1,
         "steps": int(sum(j.steps for j in jobs)), "warmup": 0,
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "serving trace: 40 jobs, Poisson 20/min (times / 60), edges 48-192, radii 4-8, "
                                "fractions 0.05-0.3, angles 45-135 deg, 2000-20000 steps x 1/20; BF16 storage",
                    "budget_bytes": budget, "steps_per_launch": k},
         "served_bf16": served, "one_at_a_time_fp32": alone,
+        "error_vs_fp64": err, "launches": srv.launches, "batch_rebuilds": srv.batch_rebuilds,
     }
 
 
@@ -219,7 +294,11 @@ def main():
     ap.add_argument("--tile", default="0,0,0", help="fused-kernel tile TX,TY,TZ (0 = automatic)")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp16", "bf16"],
                     help="population storage (default: the workload's); fp16/bf16 store deviations and compute in FP32")
+    ap.add_argument("--develop", type=int, default=2000,
+                    help="untimed steps before the warmup, so that the timed window is a developed state "
+                         "(interfaces formed, spheres moving and in contact)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the short served trace of the default line")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the run, negate a buffer of this many MiB into another three times "
                          "(a kernel of known traffic that calibrates rocprofv3's FETCH_SIZE/WRITE_SIZE)")
@@ -261,6 +340,10 @@ def main():
     lat.add_particles(parts)
     print(f"# workload {args.workload}: {p['nx']}x{p['ny']}x{p['nz']}, {len(parts['radius'])} spheres, "
           f"{precision}, kernel {args.kernel}", file=sys.stderr, flush=True)
+    if args.develop > 0:
+        lat.step(args.develop)
+        lat.synchronize()
+        print(f"# developed for {args.develop} untimed steps", file=sys.stderr, flush=True)
     lat.step(args.warmup)
     lat.synchronize()
     lat.enable_timing(True)
@@ -281,11 +364,11 @@ def main():
     fluid_sites = int((lat.owner() == -1).sum())
     copy_gbs = copy_bandwidth(torch)
     bps = algorithmic_bytes_per_site(precision)
-    kern_name = "twopass" if args.kernel in ("auto", "twopass") else args.kernel
-    traffic = measured_traffic() if (args.workload == "bijel256" and precision == "fp32" and kern_name == "twopass"
-                                     and args.tile == "0,0,0") else None
+    kern_name = {"auto": "twopass"}.get(args.kernel, args.kernel)
+    traffic = measured_traffic(kern_name, precision, args.tile) if args.workload == "bijel256" else None
     sweep_s = k_ms / 1e3 / max(k_n, 1)
     achieved = bps * N / sweep_s / 1e9
+    step_gbs = mlups * bps / 1e3
     line = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -297,7 +380,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16", "bf16": "bf16"}[precision],
         "data": "synthetic",
         "config": {
             "workload": "bijel256: 256^3 periodic, 50:50 at 0.35+-0.01, g=0.08, tau=1, "
@@ -305,10 +388,13 @@ def main():
             if args.workload == "bijel256" else args.workload,
             "sites": N,
             "spheres": len(parts["radius"]),
-            "kernel": args.kernel,
+            "kernel": kern_name,
             "tile": args.tile,
             "storage": precision,
+            "developed_steps_before_timing": args.develop,
         },
+        # the dominant kernel: the sweep that collides and streams every
+        # population (algorithmic bytes per site x sites / its mean launch time)
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
@@ -316,20 +402,32 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "collide-and-stream sweep",
+            "kernel": {"twopass": "k_collide_stream (second sweep of the two-pass step)",
+                       "fused": "k_fused_step (the whole fluid step in one sweep)"}.get(kern_name, kern_name),
             "bytes_per_site": bps,
             "ms_per_launch": round(sweep_s * 1e3, 4),
             "copy_reference_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
-        "mflups_fluid": round(mlups * fluid_sites / N, 1),
-        # the whole step as one sweep of the algorithmic bytes per site
-        "step_effective": {
-            "gbs": round(mlups * bps / 1e3, 1),
-            "frac_of_peak": round(mlups * bps / 1e3 / HBM_PEAK_GBS, 4),
-            "frac_of_copy": round(mlups * bps / 1e3 / copy_gbs, 4),
+        # the whole step against the roofline: MLUPS x algorithmic bytes per
+        # site over the peak, i.e. MLUPS as a fraction of the roofline MLUPS
+        "step_roofline": {
+            "achieved_gbs": round(step_gbs, 1),
+            "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4),
+            "roofline_mlups": round(HBM_PEAK_GBS * 1e3 / bps, 1),
+            "frac_of_copy": round(step_gbs / copy_gbs, 4),
         },
+        "mflups_fluid": round(mlups * fluid_sites / N, 1),
     }
+    if not args.no_serving and args.workload == "bijel256":
+        try:
+            sv = serving_leg()
+            line["jobs_per_hour"] = sv["jobs_per_hour"]
+            line["p50_s"] = sv["p50_s"]
+            line["p99_s"] = sv["p99_s"]
+            line["serving"] = sv
+        except Exception as e:  # reported, not hidden
+            line["serving"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

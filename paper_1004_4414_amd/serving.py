@@ -4,10 +4,13 @@ Jobs (a box, its spheres, a step count) arrive over time.  The server admits a
 waiting job as soon as its device footprint (lb_footprint_bytes) fits in the
 memory budget left by the resident jobs, keeps every admitted lattice resident
 on the GPU, and advances all resident jobs together: one graph launch of a
-batch (lb_batch_*) moves every member by ``steps_per_launch`` steps.  When a
-job has done its steps its result is read back, its lattice is freed and the
-batch is rebuilt with whatever is resident and admitted by then; jobs that
-arrive while others run join at the next launch.
+batch (lb_batch_*) moves every member by ``steps_per_launch`` steps.  The host
+keeps at most ``ahead`` launches queued on the device (it waits on the event
+of the oldest one before queueing another), and before every launch it admits
+the jobs that have arrived and fit: a job that arrives while others are on the
+GPU joins at the next launch, not at the next completion.  When a job has done
+its steps its result is read back, its lattice is freed and its memory goes
+back to the budget.
 
 Each job's kernels are the ones it would run alone, so its result is bitwise
 the same alone and in the mix.
@@ -59,9 +62,10 @@ def digest(lat):
     return hashlib.sha256(np.ascontiguousarray(lat.populations()).tobytes()).hexdigest()
 
 
-def _finish(lat, job, admitted, t0, clock, keep_digest):
+def _finish(lat, job, admitted, t0, clock, keep_digest, keep_density=False):
     """the job's result; a job whose lattice reports an error (e.g. it went
-    unstable) finishes with that error instead of observables"""
+    unstable) finishes with that error instead of observables.  With
+    ``keep_density`` the two components' density fields go into ``extra``."""
     sites = job.params["nx"] * job.params["ny"] * job.params["nz"]
     try:
         lat.synchronize()
@@ -70,7 +74,8 @@ def _finish(lat, job, admitted, t0, clock, keep_digest):
                       extra={"error": str(e)})
     obs = lat.observables()
     dg = digest(lat) if keep_digest else ""
-    return Result(job.name, job.arrival, admitted, clock() - t0, job.steps, sites, obs, dg)
+    extra = {"rho": lat.fields()["rho"]} if keep_density else {}
+    return Result(job.name, job.arrival, admitted, clock() - t0, job.steps, sites, obs, dg, extra=extra)
 
 
 class Server:
@@ -78,29 +83,37 @@ class Server:
 
     ``budget_bytes``: device memory the resident jobs may use (lb_footprint_bytes
     per job); ``precision``: population storage of every job; ``steps_per_launch``:
-    steps per graph launch (every job's step count must be a multiple)."""
+    steps per graph launch (every job's step count must be a multiple);
+    ``ahead``: launches the host may keep queued on the device;
+    ``keep_density``: names of jobs whose density fields the results carry."""
 
-    def __init__(self, budget_bytes, precision="bf16", steps_per_launch=10, keep_digest=False):
+    def __init__(self, budget_bytes, precision="bf16", steps_per_launch=10, keep_digest=False, ahead=2,
+                 keep_density=()):
         self.budget = int(budget_bytes)
         self.precision = precision
         self.k = int(steps_per_launch)
         self.keep_digest = keep_digest
+        self.ahead = max(1, int(ahead))
+        self.keep_density = set(keep_density)
         self.batch_rebuilds = 0
+        self.launches = 0
 
     def footprint(self, job):
         r = float(job.particles["radius"].max()) if len(job.particles["radius"]) else 0.0
         return lbm.footprint_bytes(job.params, len(job.particles["radius"]), r, self.precision)
 
     def run(self, jobs, clock=time.perf_counter):
+        import torch
         for j in jobs:
-            if j.steps % self.k:
-                raise ValueError(f"job {j.name}: {j.steps} steps is not a multiple of {self.k}")
+            if j.steps <= 0 or j.steps % self.k:
+                raise ValueError(f"job {j.name}: {j.steps} steps is not a positive multiple of {self.k}")
             if self.footprint(j) > self.budget:
                 raise ValueError(f"job {j.name} does not fit the memory budget")
         pending = sorted(jobs, key=lambda j: j.arrival)
         active = []  # [job, lattice, remaining, admitted, bytes]
         used = 0
         batch = None
+        inflight = []  # events of the launches queued on the device, oldest first
         results = []
         t0 = clock()
         while pending or active:
@@ -121,27 +134,39 @@ class Server:
                 continue
             if changed or batch is None:
                 if batch is not None:
-                    batch.close()
+                    batch.close()  # waits for its queued launches
+                    inflight.clear()
                 batch = lbm.Batch([a[1] for a in active], steps_per_launch=self.k)
                 self.batch_rebuilds += 1
+            # device progress: at most `ahead` launches queued before this one
+            while len(inflight) >= self.ahead:
+                inflight.pop(0).synchronize()
             batch.step(1)
+            ev = torch.cuda.Event()
+            ev.record(batch.stream)
+            inflight.append(ev)
+            self.launches += 1
             done = []
             for a in active:
                 a[2] -= self.k
-                if a[2] == 0:
+                if a[2] <= 0:
                     done.append(a)
             if done:
                 batch.close()
                 batch = None
+                inflight.clear()
                 for a in done:
-                    results.append(_finish(a[1], a[0], a[3], t0, clock, self.keep_digest))
+                    results.append(_finish(a[1], a[0], a[3], t0, clock, self.keep_digest,
+                                           a[0].name in self.keep_density))
                     a[1].close()
                     used -= a[4]
                     active.remove(a)
+        if batch is not None:
+            batch.close()
         return results
 
 
-def run_alone(jobs, precision="fp32", keep_digest=False, clock=time.perf_counter):
+def run_alone(jobs, precision="fp32", keep_digest=False, clock=time.perf_counter, keep_density=()):
     """One job at a time in arrival order, each stepped by lb_step alone (the
     comparison point of the server)."""
     results = []
@@ -155,7 +180,7 @@ def run_alone(jobs, precision="fp32", keep_digest=False, clock=time.perf_counter
         if len(j.particles["radius"]):
             lat.add_particles(coloured(j))
         lat.step(j.steps)
-        results.append(_finish(lat, j, admitted, t0, clock, keep_digest))
+        results.append(_finish(lat, j, admitted, t0, clock, keep_digest, j.name in set(keep_density)))
         lat.close()
     return results
 
@@ -171,3 +196,16 @@ def summary(results):
                 p50_s=float(np.percentile(ttr, 50)), p99_s=float(np.percentile(ttr, 99)),
                 makespan_s=float(makespan), jobs_per_hour=float(len(ok) / makespan * 3600.0),
                 mlups=float(updates / makespan / 1e6))
+
+
+def density_error(result, job):
+    """The served result's density fields against the same job stepped alone
+    with FP64 storage (the path that matches the oracle to rounding): the
+    largest |rho - rho_fp64| over both components and sites, and the largest
+    relative error of a component's total mass."""
+    ref = run_alone([Job(job.params, job.particles, job.steps, 0.0, job.contact_angle, job.name)],
+                    precision="fp64", keep_density=(job.name,))[0]
+    a, b = result.extra["rho"], ref.extra["rho"]
+    mass = np.abs(a.sum(axis=(1, 2, 3)) / b.sum(axis=(1, 2, 3)) - 1.0)
+    return dict(job=job.name, steps=job.steps, max_abs_rho=float(np.abs(a - b).max()),
+                max_rel_mass=float(mass.max()))

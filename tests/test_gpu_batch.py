@@ -179,3 +179,44 @@ def test_served_results_equal_results_alone():
     for name, r in alone.items():
         assert served[name].populations_digest == r.populations_digest, name
         assert served[name].observables["step"] == r.observables["step"] == r.steps
+
+
+class _FakeClock:
+    """a clock that advances a fixed amount at every reading"""
+
+    def __init__(self, dt):
+        self.t = 0.0
+        self.dt = dt
+
+    def __call__(self):
+        self.t += self.dt
+        return self.t
+
+
+def test_late_arrival_is_admitted_at_the_next_launch():
+    """Continuous batching: a job arriving while another is on the GPU, with
+    room in the memory budget, is admitted before the running job completes
+    (at a launch boundary), and both results equal the jobs run alone."""
+    from paper_1004_4414_amd import serving as S
+    p1 = W.params(nx=32, ny=32, nz=32, seed=71)
+    p2 = W.params(nx=24, ny=24, nz=24, seed=72)
+    a = S.Job(p1, W.make_particles(W.random_sphere_positions((32, 32, 32), 2, 4.0, seed=71), 4.0), 200,
+              arrival=0.0, name="early")
+    b = S.Job(p2, W.make_particles(W.random_sphere_positions((24, 24, 24), 1, 4.0, seed=72), 4.0), 40,
+              arrival=0.3, name="late")
+    srv = S.Server(budget_bytes=10 * max(S.Server(1, "fp32").footprint(j) for j in (a, b)), precision="fp32",
+                   steps_per_launch=10, keep_digest=True)
+    res = {r.name: r for r in srv.run([a, b], clock=_FakeClock(0.05))}
+    assert res["late"].admitted >= 0.3
+    assert res["late"].admitted < res["early"].finished
+    assert res["late"].finished < res["early"].finished  # 4 launches against the early job's 20
+    alone = {r.name: r for r in S.run_alone([a, b], precision="fp32", keep_digest=True)}
+    for n in ("early", "late"):
+        assert res[n].populations_digest == alone[n].populations_digest
+
+
+def test_jobs_without_steps_are_refused():
+    from paper_1004_4414_amd import serving as S
+    j = S.Job(W.params(nx=16, ny=16, nz=16), W.empty_particles(), 0, name="empty")
+    with pytest.raises(ValueError):
+        S.Server(1 << 40, precision="fp32", steps_per_launch=10).run([j])
