@@ -171,10 +171,11 @@ size_t fluid_bytes(const lb_params *p) {
 size_t particle_bytes(const lb_params *p, int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
     const size_t cells = (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
-    size_t b = (size_t)np * (41 * 8 + (22 + MAX_LUB_CONTACTS + CAND_CAP) * 4 + MAX_LUB_CONTACTS * 32) + 4 * cells;
-    const double reach = 2.0 * max_r + std::max(p->lub_hc, 0.0);  // cell list of the pair search
-    if (reach > 0.0) b += 8 * (size_t)(p->nx / reach + 1) * (size_t)(p->ny / reach + 1) * (size_t)(p->nz / reach + 1);
-    b += (size_t)np * sc * (4 + 2 * 4);  // virtual-fluid sites, covered and uncovered sites
+    size_t b = (size_t)np * (41 * 8 + (21 + MAX_LUB_CONTACTS + CAND_CAP + NB_CAP) * 4 + MAX_LUB_CONTACTS * 32) +
+               4 * cells;
+    const double reach = 2.0 * max_r + std::max(p->lub_hc, NB_REACH);  // cell list of the pair search
+    b += 8 * (size_t)(p->nx / reach + 1) * (size_t)(p->ny / reach + 1) * (size_t)(p->nz / reach + 1);
+    b += (size_t)np * sc * (4 + 4 * 4);  // virtual-fluid sites; covered, uncovered and changed sites
     return b + 4096;
 }
 
@@ -187,7 +188,7 @@ void rebuild_map(lb_handle *h) {
                                 h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.Rscan, h->dpart.R, sizeof(double) * 3 * h->np, hipMemcpyDeviceToDevice,
                                 h->stream));
-    launch_map_mark(h, true);  // every sphere is classified afresh
+    launch_map_mark(h);  // every sphere is classified afresh
     launch_map_commit(h, true);
     launch_info_dense(h);
     launch_fill_int(h, h->stage, h->N, STAGE_NONE);
@@ -299,8 +300,7 @@ void enqueue_step(lb_handle *h) {
         launch_particle_fluid_force(h, fout);
         launch_pair_forces(h);
         launch_integrate(h);
-        launch_map_mark(h, false);  // also clears the dirty cells
-        launch_map_events(h);
+        launch_map_flip(h);  // also clears the dirty cells
         launch_cover_refill(h, fout);
         launch_map_commit(h, false);
         launch_map_info(h);
@@ -583,7 +583,7 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.ev_cap = i32 + 6 * tot;
     D.cov_cnt = i32 + 7 * tot;
     D.unc_cnt = i32 + 8 * tot;
-    D.changed = i32 + 9 * tot;
+    D.chg_cnt = i32 + 9 * tot;
     D.cgx = (h->prm.nx + (1 << CELL_SHIFT) - 1) >> CELL_SHIFT;
     D.cgy = (h->prm.ny + (1 << CELL_SHIFT) - 1) >> CELL_SHIFT;
     D.cgz = (h->prm.nz + (1 << CELL_SHIFT) - 1) >> CELL_SHIFT;
@@ -594,16 +594,16 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.vs = (double *)dev_alloc(h, sizeof(double) * 3 * (size_t)tot);
     D.Rscan = (double *)dev_alloc(h, sizeof(double) * 3 * (size_t)tot);
     D.margin = (double *)dev_alloc(h, sizeof(double) * (size_t)tot);
-    D.frozen = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
-    D.touch = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+    D.nnbr = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+    D.nbr = (int32_t *)dev_alloc(h, sizeof(int32_t) * NB_CAP * (size_t)tot);
     D.ncand = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
     D.cand = (int32_t *)dev_alloc(h, sizeof(int32_t) * CAND_CAP * (size_t)tot);
     h->part_allocs.push_back(D.ncand);
     h->part_allocs.push_back(D.cand);
     h->part_allocs.push_back(D.Rscan);
     h->part_allocs.push_back(D.margin);
-    h->part_allocs.push_back(D.frozen);
-    h->part_allocs.push_back(D.touch);
+    h->part_allocs.push_back(D.nnbr);
+    h->part_allocs.push_back(D.nbr);
     D.cont_c = (double *)dev_alloc(h, sizeof(double) * MAX_LUB_CONTACTS * (size_t)tot);
     D.cont_n = (double *)dev_alloc(h, sizeof(double) * 3 * MAX_LUB_CONTACTS * (size_t)tot);
     h->part_allocs.push_back(D.cont_c);
@@ -615,8 +615,8 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     h->part_allocs.push_back(D.vs);
     {  // cell list of the pair search: cells at least 2 r_max + h_c wide
         const double rmax = *std::max_element(rad.begin(), rad.end());
-        // (TOUCH_SLACK: pairs that may share sites are found as well)
-        const double reach = 2.0 * rmax + std::max(h->prm.lub_hc, 0.0) + 1e-5;
+        // (NB_REACH: the neighbours of the map update are found as well)
+        const double reach = 2.0 * rmax + std::max(h->prm.lub_hc, NB_REACH) + 1e-5;
         int pg[3];
         for (int a = 0; a < 3; ++a) pg[a] = reach > 0.0 ? (int)(L[a] / reach) : 1;
         if (pg[0] >= 3 && pg[1] >= 3 && pg[2] >= 3 && (long long)pg[0] * pg[1] * pg[2] <= (1 << 22)) {
@@ -641,9 +641,11 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.shell = (int32_t *)dev_alloc(h, sizeof(int32_t) * ssum);
     D.cov = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.unc = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
+    D.chg = (int32_t *)dev_alloc(h, sizeof(int32_t) * 2 * esum);
     h->part_allocs.push_back(D.shell);
     h->part_allocs.push_back(D.cov);
     h->part_allocs.push_back(D.unc);
+    h->part_allocs.push_back(D.chg);
     // host image of the double block
     std::vector<double> hd((size_t)34 * tot, 0.0);
     for (int p = 0; p < tot; ++p) {

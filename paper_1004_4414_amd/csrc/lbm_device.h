@@ -239,7 +239,10 @@ constexpr int CLS_SHIFT = 29;
 __host__ __device__ inline uint32_t site_class(uint32_t info) { return (info >> CLS_SHIFT) & 3u; }
 
 constexpr int32_t OWN_FLUID = -1, OWN_WALL_LO = -2, OWN_WALL_HI = -3;
-constexpr int32_t STAGE_NONE = 0x7fffffff;
+// stage[]: STAGE_NONE, or the new owner of a site whose owner changes in this
+// step's map update (STAGE_FLUID for the fluid); the full rebuild instead
+// takes the lowest index of the spheres that contain the site
+constexpr int32_t STAGE_NONE = 0x7fffffff, STAGE_FLUID = 0x7ffffffe;
 
 struct DevParams {
     int nx, ny, nz, np;
@@ -277,16 +280,21 @@ struct DevState {
 
 // per-particle arrays (FP64), each np*3 unless noted
 struct DevParticles {
+    // Rprev: the centre at the last map update (the positions the solid map
+    // holds)
     double *R, *U, *W, *Rprev;
-    // discretisation skip: Rscan is the centre of the last classification of
-    // the sphere's sites; cand lists the sites closer than margin (tau) to
-    // that sphere's surface, with bit 31 set on those inside; ncand their
-    // number.  While the fixed-point centre stays closer than tau to Rscan
-    // only those sites can change side, and when none of them does and the
-    // sphere touches no other (touch, from the pair search) it is frozen:
-    // its map update is skipped
+    // candidate sites: Rscan is the centre of the last scan of the sphere's
+    // box; cand lists the sites closer than margin (tau) to the surface of
+    // the sphere centred there (bit 31 set on those inside) and ncand their
+    // number.  While the fixed-point centre stays closer than tau to Rscan,
+    // only those sites can change side, so a map update tests them alone.
     double *Rscan, *margin;
-    int32_t *frozen, *touch, *cand, *ncand;
+    int32_t *cand, *ncand;
+    // the spheres whose centres were closer than r_a + r_b + NB_REACH at the
+    // start of the step (the only ones that can share a site with this
+    // sphere's old or new sites after a move of less than one site per axis);
+    // nnbr > NB_CAP: too many to list, every sphere is tested instead
+    int32_t *nbr, *nnbr;
     double *Ffl, *Tfl, *Ftot, *Ttot, *P, *PT;
     double *rad, *mass, *inertia, *color;  // np each
     int32_t *prescribed;
@@ -299,9 +307,11 @@ struct DevParticles {
     int32_t *shell;
     int32_t *ev_off, *ev_cap, *cov_cnt, *unc_cnt;
     int32_t *cov, *unc;
-    // map-update bookkeeping: changed[p] = the discrete sphere p changed this
-    // step; dirty[] = coarse cells (CELL^3 sites) whose class words changed
-    int32_t *changed;
+    // map-update bookkeeping: chg lists the sites whose owner changes this
+    // step, found by sphere p (offset 2 ev_off, capacity 2 ev_cap; a site may
+    // be listed by two spheres); dirty[] = coarse cells (CELL^3 sites) whose
+    // class words changed
+    int32_t *chg_cnt, *chg;
     int32_t *dirty;
     int32_t *lbox;  // np x 6: box (lo, ext) of the last list build
     // lubrication contacts (index order) and the velocities after every other force
@@ -318,6 +328,10 @@ struct DevParticles {
 constexpr int CELL_SHIFT = 3;  // coarse cells of 8^3 sites
 constexpr int MAX_LUB_CONTACTS = 32;
 constexpr int CAND_CAP = 256;  // near-surface sites kept per sphere
+constexpr int NB_CAP = 32;     // listed neighbours per sphere
+// neighbour reach beyond r_a + r_b: two moves of less than one site per axis
+// (2 sqrt(3)) and the 2^-21 of the fixed-point radii
+constexpr double NB_REACH = 3.5;
 
 
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }

@@ -113,8 +113,8 @@ void launch_owner_reset(lb_handle *h);
 void launch_particle_fluid_force(lb_handle *h, void *fout);
 void launch_pair_forces(lb_handle *h);
 void launch_integrate(lb_handle *h);
-void launch_map_mark(lb_handle *h, bool use_prev);
-void launch_map_events(lb_handle *h);
+void launch_map_mark(lb_handle *h);  // full classification (marks in stage[])
+void launch_map_flip(lb_handle *h);  // per-step update: changed sites and events
 void launch_cover_refill(lb_handle *h, void *fout);
 void launch_map_commit(lb_handle *h, bool full);
 void launch_map_info(lb_handle *h);

@@ -14,10 +14,6 @@
 
 namespace lbm {
 
-// spheres closer than r_a + r_b + TOUCH_SLACK may share lattice sites (the
-// fixed-point radius exceeds r by at most 2^-21)
-constexpr double TOUCH_SLACK = 1e-5;
-constexpr int INFO_TILE = 8192;  // owners of a class-word box and its rim held in LDS
 
 __device__ __forceinline__ void load3(const double *a, int p, double v[3]) {
     v[0] = a[3 * p];
@@ -387,13 +383,13 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
     double F[3] = {0, 0, 0};
     int ncont = 0;
-    int touch = 0;  // another sphere closer than the two radii (they may share sites)
+    int nnb = 0;  // neighbours for the map update (index order)
     double nu = 0.0;  // mean kinematic viscosity of the two components
     for (int c = 0; c < 2; ++c) nu += (1.0 / 3.0) * (P.tau[c] - 0.5);
     nu /= 2.0;
     for (int q0 = 0; q0 < P.np; q0 += BLOCK) {
         const int q = q0 + threadIdx.x;
-        bool lub = false;
+        bool lub = false, nb = false;
         if (q < P.np && q != p) {
             double d[3], dist2 = 0.0;
             for (int a = 0; a < 3; ++a) {
@@ -401,7 +397,7 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
                 dist2 += d[a] * d[a];
             }
             const double rsum = rp + D.rad[q];
-            touch |= dist2 < (rsum + TOUCH_SLACK) * (rsum + TOUCH_SLACK);
+            nb = dist2 < (rsum + NB_REACH) * (rsum + NB_REACH);
             const double reach = rsum + (P.lub_hc > 0.0 ? P.lub_hc : 0.0);
             if (dist2 < reach * reach) {
                 const double dist = sqrt(dist2);
@@ -414,6 +410,8 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
                 }
             }
         }
+        const int nslot = block_compact(nb, nnb, clds);
+        if (nb && nslot < NB_CAP) D.nbr[(size_t)p * NB_CAP + nslot] = q;
         const int slot = block_compact(lub, ncont, clds);
         if (lub && (P.lub_mode == 0 || slot < MAX_LUB_CONTACTS)) {
             // the pair's geometry as both ends compute it: from the lower index to the higher
@@ -444,9 +442,8 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
         }
     }
     block_sum<3>(F, lds);
-    touch = __syncthreads_or(touch);
     if (threadIdx.x == 0) {
-        D.touch[p] = touch != 0;
+        D.nnbr[p] = nnb;
         D.ncont[p] = P.lub_mode == 0 ? 0 : min(ncont, MAX_LUB_CONTACTS);
         if (P.lub_mode != 0 && ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
@@ -570,7 +567,7 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
     if (K > PAIR_MAX_CAND) {
         if (t == 0) {
             D.ncont[p] = 0;
-            D.touch[p] = 1;
+            D.nnbr[p] = NB_CAP + 1;  // unknown: the map update tests every sphere
             atomicOr(&st->overflow, 16);
         }
         return;
@@ -599,11 +596,11 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
         }
     double F[3] = {0, 0, 0};
     int ncont = 0;
-    bool touch = false;  // another sphere closer than the two radii (they may share sites)
+    int nnb = 0;  // neighbours for the map update (index order: the candidates are sorted)
     for (int j0 = 0; j0 < K; j0 += 64) {
         const int j = j0 + t;
         const int q = j < K ? cand[j] : -1;
-        bool lub = false;
+        bool lub = false, nb = false;
         if (q >= 0 && q != p) {
             double d[3], dist2 = 0.0;
             for (int a = 0; a < 3; ++a) {
@@ -611,7 +608,7 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
                 dist2 += d[a] * d[a];
             }
             const double rsum = rp + D.rad[q];
-            touch = touch || dist2 < (rsum + TOUCH_SLACK) * (rsum + TOUCH_SLACK);
+            nb = dist2 < (rsum + NB_REACH) * (rsum + NB_REACH);
             const double reach = rsum + (P.lub_hc > 0.0 ? P.lub_hc : 0.0);
             if (dist2 < reach * reach) {
                 const double dist = sqrt(dist2);
@@ -624,8 +621,13 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
                 }
             }
         }
+        const unsigned long long below = (t == 0) ? 0ull : (~0ull >> (64 - t));
+        const unsigned long long nball = __ballot(nb);
+        const int nslot = nnb + __popcll(nball & below);
+        nnb += __popcll(nball);
+        if (nb && nslot < NB_CAP) D.nbr[(size_t)p * NB_CAP + nslot] = q;
         const unsigned long long ball = __ballot(lub);
-        const int slot = ncont + __popcll(ball & ((t == 0) ? 0ull : (~0ull >> (64 - t))));
+        const int slot = ncont + __popcll(ball & below);
         ncont += __popcll(ball);
         if (lub && (P.lub_mode == 0 || slot < MAX_LUB_CONTACTS)) {
             // the pair's geometry as both ends compute it: from the lower index to the higher
@@ -658,9 +660,8 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         for (int off = 32; off > 0; off >>= 1) F[a] += __shfl_down(F[a], off, 64);
-    const bool any_touch = __ballot(touch) != 0ull;
     if (t == 0) {
-        D.touch[p] = any_touch;
+        D.nnbr[p] = nnb;
         D.ncont[p] = P.lub_mode == 0 ? 0 : min(ncont, MAX_LUB_CONTACTS);
         if (P.lub_mode != 0 && ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
@@ -722,160 +723,211 @@ __global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
 }
 
 // ---------------------------------------------------------------------------
-// solid map: every site inside sphere p (at its current position) proposes p;
-// the lowest index wins.  stage[] holds STAGE_NONE everywhere else.
+// Solid map (Sec. III): a site belongs to the lowest-index sphere whose
+// centre, rounded to 2^-20, is closer than its rounded radius.
+//
+// The full classification (new spheres, restored states) marks every site
+// inside sphere p with p in stage[] (lowest index wins) and k_map_commit_full
+// turns the marks into owners.  The per-step update is incremental: a site can
+// change owner only if it changes side of some sphere's surface.  For each
+// sphere those sites are found exactly, among its candidate sites while the
+// centre stays within the margin of the last scan, else by scanning the box
+// of its old and new positions.  Each such site's new owner is the lowest
+// index among that sphere and its listed neighbours that contain the site at
+// their new positions, so the map always equals a full classification at the
+// current positions.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void map_mark_body(DevParams P, DevParticles D, int32_t *__restrict__ stage, int full,
-                                              const Grid &g) {
+
+// the band half-width of the candidate sites: about 192 of them
+__device__ __forceinline__ double cand_tau(double r) { return fmin(0.5, 192.0 / (8.0 * M_PI * r * r)); }
+
+// sphere q (current position) contains site (x, y, z)
+__device__ __forceinline__ bool sphere_holds(const DevParams &P, const DevParticles &D, int q, int x, int y, int z) {
+    long long cq[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cq[a] = fixed20(D.R[3 * q + a]);
+    const long long rq = fixed20(D.rad[q]);
+    return dist2_sphere(x, y, z, cq, P.nx, P.ny, P.nz) < rq * rq;
+}
+
+// full classification of sphere p: marks and candidate sites
+__device__ __forceinline__ void map_mark_body(DevParams P, DevParticles D, int32_t *__restrict__ stage, const Grid &g) {
     const int p = g.bid;
-    {  // the blocks also clear the coarse dirty cells of the previous step, a slice each
-        const int ncell = D.cgx * D.cgy * D.cgz;
-        const int per = (ncell + (int)g.nb - 1) / (int)g.nb;
-        for (int c = p * per + threadIdx.x; c < min(ncell, (p + 1) * per); c += BLOCK) D.dirty[c] = 0;
-    }
     long long cq[3];
     for (int a = 0; a < 3; ++a) cq[a] = fixed20(D.R[3 * p + a]);
     const long long rq = fixed20(D.rad[p]);
     const long long r2q = rq * rq;
-    // Frozen: no other sphere can share its sites, the fixed-point centre C'
-    // is closer than tau to the centre C of the last classification, and none
-    // of the sites within tau of that sphere's surface changes side (the
-    // others cannot: |x - C'| and |x - C| differ by at most |C' - C|).  Every
-    // thread takes the same decision.
-    bool frz = !full && !D.touch[p];
-    if (frz) {
-        long long d2 = 0;
-        for (int a = 0; a < 3; ++a) {
-            const long long Lq = (long long)(a == 0 ? P.nx : (a == 1 ? P.ny : P.nz)) << 20;
-            long long d = cq[a] - fixed20(D.Rscan[3 * p + a]);
-            if (d > Lq / 2) d -= Lq;
-            else if (d <= -(Lq / 2)) d += Lq;
-            d2 += d * d;
-            frz = frz && fabs(D.U[3 * p + a]) < 1.0;
-        }
-        frz = frz && sqrt((double)d2) * (1.0 / 1048576.0) < D.margin[p] - 1e-9;
-    }
-    if (frz) {
-        const int nc = D.ncand[p];
-        const int32_t *cd = D.cand + (size_t)p * CAND_CAP;
-        bool flip = false;
-        for (int k = threadIdx.x; k < nc; k += BLOCK) {
-            const uint32_t e = (uint32_t)cd[k];
-            int x, y, z;
-            site_xyz(e & 0x7fffffffu, P, x, y, z);
-            flip = flip || (dist2_sphere(x, y, z, cq, P.nx, P.ny, P.nz) < r2q) != ((e >> 31) != 0u);
-        }
-        frz = !__syncthreads_or(flip);
-    }
-    if (threadIdx.x == 0) {
-        D.frozen[p] = frz;
-        if (!frz)  // the previous classification's centre (for the union boxes) and the new one
-            for (int a = 0; a < 3; ++a) {
-                D.Rprev[3 * p + a] = D.Rscan[3 * p + a];
-                D.Rscan[3 * p + a] = D.R[3 * p + a];
-            }
-    }
-    if (frz) return;  // uniform over the block
     int lo[3], ext[3];
     new_box(P, D, p, lo, ext);
     const BoxWalk bw(P, lo, ext);
     const bool near = near_box(lo, ext, cq, P);
     const int V = bw.size();
-    // the sites within tau of the sphere's surface (every site within one
-    // site of it lies in the box); tau is chosen so that about 64 qualify
     __shared__ int lds[BLOCK / 64 + 1];
-    const double r = D.rad[p];
-    const double tau = fmin(0.5, 64.0 / (8.0 * M_PI * r * r));
+    const double tau = cand_tau(D.rad[p]);
     int32_t *cd = D.cand + (size_t)p * CAND_CAP;
     int nc = 0;
     for (int k0 = 0; k0 < V; k0 += BLOCK) {
         const int k = k0 + threadIdx.x;
         bool near_surface = false;
-        bool in = false;
         long long n = 0;
         if (k < V) {
             int u[3], x, y, z;
             bw.site(k, P, u, x, y, z);
             const long long d2 = near ? dist2_unwrapped(u, cq) : dist2_sphere(x, y, z, cq, P.nx, P.ny, P.nz);
             n = site_of(x, y, z, P);
-            in = d2 < r2q;
-            if (in) atomicMin(&stage[n], p);
+            if (d2 < r2q) atomicMin(&stage[n], p);
             near_surface = fabs(sqrt((double)d2) - (double)rq) * (1.0 / 1048576.0) < tau;
         }
         const int slot = block_compact(near_surface, nc, lds);
-        if (near_surface && slot < CAND_CAP) cd[slot] = (int32_t)((uint32_t)n | (in ? 0x80000000u : 0u));
+        if (near_surface && slot < CAND_CAP) cd[slot] = (int32_t)n;
     }
     if (threadIdx.x == 0) {
         D.ncand[p] = min(nc, CAND_CAP);
-        D.margin[p] = nc <= CAND_CAP ? tau : 0.0;  // a full list only: else never frozen
+        D.margin[p] = nc <= CAND_CAP ? tau : 0.0;  // a full list only: else every update scans
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage,
-                                                    int full) {
-    map_mark_body(P, D, stage, full, own_grid());
+__global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D, int32_t *__restrict__ stage) {
+    map_mark_body(P, D, stage, own_grid());
 }
 
-// covered (fluid -> inside p) and uncovered (inside p -> fluid) sites of
-// sphere p, listed in scan order of its box
-__device__ __forceinline__ void map_events_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                                      const int32_t *__restrict__ stage, DevState *st, const Grid &g) {
-    __shared__ int lds[8];
+// The sites of sphere p that change side between the centre of the last map
+// update (Rprev) and the new one (R).  A site whose owner changes gets the new
+// owner in stage[] and goes into p's change list; a fluid site that p takes is
+// one of p's covered sites, a site of p that no sphere takes one of its
+// uncovered sites (Eqs. (18)-(20)).  Lists are in scan order.
+__device__ __forceinline__ void map_flip_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                              int32_t *__restrict__ stage, DevState *st, const Grid &g) {
     const int p = g.bid;
-    if (D.frozen[p]) {  // uniform over the block: its sites keep their owner
+    {  // the blocks also clear the coarse dirty cells of the previous step, a slice each
+        const int ncell = D.cgx * D.cgy * D.cgz;
+        const int per = (ncell + (int)g.nb - 1) / (int)g.nb;
+        for (int c = p * per + threadIdx.x; c < min(ncell, (p + 1) * per); c += BLOCK) D.dirty[c] = 0;
+    }
+    long long cn[3], co[3];
+    for (int a = 0; a < 3; ++a) {
+        cn[a] = fixed20(D.R[3 * p + a]);
+        co[a] = fixed20(D.Rprev[3 * p + a]);
+    }
+    const long long rq = fixed20(D.rad[p]);
+    const long long r2q = rq * rq;
+    // The candidates hold every site that can change side while both centres
+    // are closer than the margin to the centre of the last scan: a site on
+    // different sides for the two is within that distance of that sphere's
+    // surface.  The old centre is (it was the last scan, or passed this test).
+    bool cand_ok = true;
+    {
+        long long d2 = 0;
+        for (int a = 0; a < 3; ++a) {
+            const long long Lq = (long long)(a == 0 ? P.nx : (a == 1 ? P.ny : P.nz)) << 20;
+            long long d = cn[a] - fixed20(D.Rscan[3 * p + a]);
+            if (d > Lq / 2) d -= Lq;
+            else if (d <= -(Lq / 2)) d += Lq;
+            d2 += d * d;
+            cand_ok = cand_ok && fabs(D.U[3 * p + a]) < 1.0;
+        }
+        cand_ok = cand_ok && sqrt((double)d2) * (1.0 / 1048576.0) < D.margin[p] - 1e-9;
+    }
+    __shared__ int lds[BLOCK / 64 + 1];
+    const int eoff = D.ev_off[p], ecap = D.ev_cap[p];
+    const int coff = 2 * eoff, ccap = 2 * ecap;
+    const int nnb = D.nnbr[p];
+    const int32_t *nb = D.nbr + (size_t)p * NB_CAP;
+    int ncov = 0, nunc = 0, nchg = 0;
+    // one site per thread (flip: it changes side of p); every thread calls
+    auto settle = [&](bool flip, bool in_new, long long n, int x, int y, int z) {
+        if (!__syncthreads_or(flip)) return;  // most chunks have no flip
+        bool chg = false, cov = false, unc = false;
+        if (flip) {
+            int best = in_new ? p : 0x7fffffff;
+            if (nnb <= NB_CAP) {
+                for (int k = 0; k < nnb; ++k) {
+                    const int q = nb[k];
+                    if (q < best && sphere_holds(P, D, q, x, y, z)) best = q;
+                }
+            } else {
+                for (int q = 0; q < min(best, P.np); ++q)
+                    if (q != p && sphere_holds(P, D, q, x, y, z)) {
+                        best = q;
+                        break;
+                    }
+            }
+            const int32_t nw = best == 0x7fffffff ? OWN_FLUID : best;
+            const int32_t o = owner[n];
+            chg = nw != o;
+            cov = chg && o == OWN_FLUID && nw == p;
+            unc = chg && o == p && nw == OWN_FLUID;
+            if (chg) stage[n] = nw == OWN_FLUID ? STAGE_FLUID : nw;  // the same value from every block
+        }
+        int slot = block_compact(chg, nchg, lds);
+        if (chg && slot < ccap) D.chg[coff + slot] = (int32_t)n;
+        slot = block_compact(cov, ncov, lds);
+        if (cov && slot < ecap) D.cov[eoff + slot] = (int32_t)n;
+        slot = block_compact(unc, nunc, lds);
+        if (unc && slot < ecap) D.unc[eoff + slot] = (int32_t)n;
+    };
+    if (cand_ok) {  // uniform over the block
+        const int nc = D.ncand[p];
+        const int32_t *cd = D.cand + (size_t)p * CAND_CAP;
+        for (int k0 = 0; k0 < nc; k0 += BLOCK) {
+            const int k = k0 + threadIdx.x;
+            bool flip = false, in_new = false;
+            long long n = 0;
+            int x = 0, y = 0, z = 0;
+            if (k < nc) {
+                n = cd[k];
+                site_xyz(n, P, x, y, z);
+                in_new = dist2_sphere(x, y, z, cn, P.nx, P.ny, P.nz) < r2q;
+                flip = in_new != (dist2_sphere(x, y, z, co, P.nx, P.ny, P.nz) < r2q);
+            }
+            settle(flip, in_new, n, x, y, z);
+        }
+    } else {
+        // scan the box of both positions; new candidates around the new centre
+        int lo[3], ext[3];
+        union_box(P, D, p, 0, lo, ext);
+        const BoxWalk bw(P, lo, ext);
+        const int V = bw.size();
+        const double tau = cand_tau(D.rad[p]);
+        int32_t *cd = D.cand + (size_t)p * CAND_CAP;
+        int nc = 0;
+        for (int k0 = 0; k0 < V; k0 += BLOCK) {
+            const int k = k0 + threadIdx.x;
+            bool flip = false, in_new = false, near_surface = false;
+            long long n = 0;
+            int x = 0, y = 0, z = 0;
+            if (k < V) {
+                int u[3];
+                bw.site(k, P, u, x, y, z);
+                n = site_of(x, y, z, P);
+                const long long d2 = dist2_sphere(x, y, z, cn, P.nx, P.ny, P.nz);
+                in_new = d2 < r2q;
+                flip = in_new != (dist2_sphere(x, y, z, co, P.nx, P.ny, P.nz) < r2q);
+                near_surface = fabs(sqrt((double)d2) - (double)rq) * (1.0 / 1048576.0) < tau;
+            }
+            const int slot = block_compact(near_surface, nc, lds);
+            if (near_surface && slot < CAND_CAP) cd[slot] = (int32_t)n;
+            settle(flip, in_new, n, x, y, z);
+        }
         if (threadIdx.x == 0) {
-            D.cov_cnt[p] = 0;
-            D.unc_cnt[p] = 0;
-            D.changed[p] = 0;
-        }
-        return;
-    }
-    int lo[3], ext[3];
-    union_box(P, D, p, 0, lo, ext);
-    const BoxWalk bw(P, lo, ext);
-    const int V = bw.size();
-    const int off = D.ev_off[p], cap = D.ev_cap[p];
-    int ncov = 0, nunc = 0;
-    int moved = 0;  // a site passing between two spheres is no event but changes both maps
-    for (int start = 0; start < V; start += BLOCK) {
-        const int k = start + threadIdx.x;
-        bool cov = false, unc = false;
-        long long n = 0;
-        if (k < V) {
-            int u[3], x, y, z;
-            bw.site(k, P, u, x, y, z);
-            n = site_of(x, y, z, P);
-            const int32_t o = owner[n], s = stage[n];
-            cov = (o == OWN_FLUID && s == p);
-            unc = (o == p && s == STAGE_NONE);
-            moved |= (o >= 0 && o != p && s == p) || (o == p && s != STAGE_NONE && s != p);
-        }
-        // events are rare: most chunks have none and skip the two compactions
-        if (__syncthreads_or(cov || unc)) {
-            int slot = block_compact(cov, ncov, lds);
-            if (cov && slot < cap) D.cov[off + slot] = (int32_t)n;
-            slot = block_compact(unc, nunc, lds);
-            if (unc && slot < cap) D.unc[off + slot] = (int32_t)n;
+            D.ncand[p] = min(nc, CAND_CAP);
+            D.margin[p] = nc <= CAND_CAP ? tau : 0.0;
+            for (int a = 0; a < 3; ++a) D.Rscan[3 * p + a] = D.R[3 * p + a];
         }
     }
-    const bool changed = __syncthreads_or(moved) != 0 || ncov > 0 || nunc > 0;
-    if (changed) {
-        __shared__ AxisCells ac;
-        if (threadIdx.x == 0) axis_cells(P, lo, ext, ac);
-        __syncthreads();
-        mark_dirty(P, D, ac);
-    }
+    __syncthreads();  // every thread has read Rprev
     if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) D.Rprev[3 * p + a] = D.R[3 * p + a];
         D.cov_cnt[p] = ncov;
         D.unc_cnt[p] = nunc;
-        D.changed[p] = changed ? 1 : 0;
-        if (ncov > cap || nunc > cap) atomicOr(&st->overflow, 4);
+        D.chg_cnt[p] = nchg;
+        if (ncov > ecap || nunc > ecap || nchg > ccap) atomicOr(&st->overflow, 4);
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_map_events(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                                      const int32_t *__restrict__ stage, DevState *st) {
-    map_events_body(P, D, owner, stage, st, own_grid());
+__global__ __launch_bounds__(BLOCK) void k_map_flip(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
+                                                    int32_t *__restrict__ stage, DevState *st) {
+    map_flip_body(P, D, owner, stage, st, own_grid());
 }
 
 // Covering, Eq. (18): the fluid of a covered site is removed and its momentum
@@ -1006,13 +1058,11 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
     cover_refill_body<S>(P, D, f, owner, stage, st, own_grid());
 }
 
-// new owners of the sites in the box (identical values from every block)
-__device__ __forceinline__ void map_commit_body(DevParams P, DevParticles D, int32_t *__restrict__ owner,
-                                                      const int32_t *__restrict__ stage, int full, const Grid &g) {
+// owners after a full classification: the marks of the box (identical values
+// from every block)
+__device__ __forceinline__ void map_commit_full_body(DevParams P, DevParticles D, int32_t *__restrict__ owner,
+                                                     const int32_t *__restrict__ stage, const Grid &g) {
     const int p = g.bid;
-    // an unchanged sphere's box holds no change of its own; changes of other
-    // spheres inside it are written by their blocks
-    if (!full && !D.changed[p]) return;
     int lo[3], ext[3];
     union_box(P, D, p, 0, lo, ext);
     const BoxWalk bw(P, lo, ext);
@@ -1021,85 +1071,53 @@ __device__ __forceinline__ void map_commit_body(DevParams P, DevParticles D, int
         int u[3], x, y, z;
         bw.site(k, P, u, x, y, z);
         const long long n = site_of(x, y, z, P);
-        const int32_t s = stage[n], o = owner[n];
-        // a frozen sphere did not mark, and still holds the sites it owns
-        // (no sphere shares them); the lowest index wins as ever.  Every block
-        // writes the same value, whichever it reads first.
-        owner[n] = (o >= 0 && D.frozen[o]) ? min(o, s) : (s == STAGE_NONE ? OWN_FLUID : s);
+        const int32_t s = stage[n];
+        owner[n] = s == STAGE_NONE ? OWN_FLUID : s;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_map_commit_full(DevParams P, DevParticles D, int32_t *__restrict__ owner,
+                                                           const int32_t *__restrict__ stage) {
+    map_commit_full_body(P, D, owner, stage, own_grid());
+}
+
+// the new owners of the sites in p's change list (a site listed by two spheres
+// gets the same value twice)
+__device__ __forceinline__ void map_commit_body(DevParams P, DevParticles D, int32_t *__restrict__ owner,
+                                                const int32_t *__restrict__ stage, const Grid &g) {
+    const int p = g.bid;
+    const int off = 2 * D.ev_off[p], n = min(D.chg_cnt[p], 2 * D.ev_cap[p]);
+    for (int k = threadIdx.x; k < n; k += BLOCK) {
+        const int32_t s = D.chg[off + k];
+        const int32_t v = stage[s];
+        owner[s] = v == STAGE_FLUID ? OWN_FLUID : v;
     }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_map_commit(DevParams P, DevParticles D, int32_t *__restrict__ owner,
-                                                      const int32_t *__restrict__ stage, int full) {
-    map_commit_body(P, D, owner, stage, full, own_grid());
+                                                      const int32_t *__restrict__ stage) {
+    map_commit_body(P, D, owner, stage, own_grid());
 }
 
-// class words around the moved sphere; clears its marks in stage[]
+// the class words of the changed sites and their 18 neighbours (the words
+// that read a changed owner), the coarse cells they lie in marked dirty; the
+// change marks in stage[] are cleared
 __device__ __forceinline__ void map_info_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                                    uint32_t *__restrict__ info, int32_t *__restrict__ stage, const Grid &g) {
+                                              uint32_t *__restrict__ info, int32_t *__restrict__ stage,
+                                              const Grid &g) {
     const int p = g.bid;
-    if (D.frozen[p]) return;  // no change and no marks (uniform over the block)
-    int lo[3], ext[3];
-    int V;
-    if (D.changed[p]) {
-        union_box(P, D, p, 1, lo, ext);
-        const BoxWalk bw(P, lo, ext);
-        V = bw.size();
-        // the owners of the box and its one-site rim, read once into LDS; each
-        // class word is then formed from its 18 neighbours there (boxes too
-        // large for the tile take them from global memory)
-        __shared__ int32_t tile[INFO_TILE];
-        const int gext[3] = {ext[0] + 2, ext[1] + 2, ext[2] + 2};
-        const int glo[3] = {lo[0] - 1, lo[1] - 1, lo[2] - 1};
-        const int TV = gext[0] * gext[1] * gext[2];
-        if (TV <= INFO_TILE) {
-            const BoxWalk tw(P, glo, gext);
-            for (int k = threadIdx.x; k < TV; k += BLOCK) {
-                int u[3], x, y, z;
-                tw.site(k, P, u, x, y, z);
-                tile[k] = owner[site_of(x, y, z, P)];
-            }
-            __syncthreads();
-            for (int k = threadIdx.x; k < V; k += BLOCK) {
-                int u[3], x, y, z;
-                bw.site(k, P, u, x, y, z);
-                const int c = ((u[2] - glo[2]) * gext[1] + (u[1] - glo[1])) * gext[0] + (u[0] - glo[0]);
-                const int32_t own = tile[c];
-                uint32_t word;
-                if (own == OWN_WALL_LO || own == OWN_WALL_HI) {
-                    word = (uint32_t)CLS_WALL << CLS_SHIFT;
-                } else {
-                    uint32_t mask = 0;
-                    bool any_fluid = false;
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        const int32_t o = tile[c + (cz(i) * gext[1] + cy(i)) * gext[0] + cx(i)];
-                        if (o != OWN_FLUID) mask |= 1u << i;
-                        else any_fluid = true;
-                    }
-                    word = own == OWN_FLUID ? mask
-                                            : (any_fluid ? ((uint32_t)CLS_SHELL << CLS_SHIFT) | mask
-                                                         : (uint32_t)CLS_SOLID << CLS_SHIFT);
-                }
-                info[site_of(x, y, z, P)] = word;
-            }
-        } else {
-            for (int k = threadIdx.x; k < V; k += BLOCK) {
-                int u[3], x, y, z;
-                bw.site(k, P, u, x, y, z);
-                const long long n = site_of(x, y, z, P);
-                info[n] = compute_info_at(n, x, y, z, P, owner);
-            }
-        }
+    const int off = 2 * D.ev_off[p], n = min(D.chg_cnt[p], 2 * D.ev_cap[p]);
+    for (int k = threadIdx.x; k < n * Q; k += BLOCK) {
+        const int e = k / Q, i = k - e * Q;
+        const long long s = D.chg[off + e];
+        int x, y, z;
+        site_xyz(s, P, x, y, z);
+        const int xx = wrapc(x + cx(i), P.nx), yy = wrapc(y + cy(i), P.ny), zz = wrapc(z + cz(i), P.nz);
+        const long long m = site_of(xx, yy, zz, P);
+        info[m] = compute_info_at(m, xx, yy, zz, P, owner);
+        D.dirty[cell_of(D, xx, yy, zz)] = 1;
     }
-    new_box(P, D, p, lo, ext);
-    const BoxWalk bw(P, lo, ext);
-    V = bw.size();
-    for (int k = threadIdx.x; k < V; k += BLOCK) {
-        int u[3], x, y, z;
-        bw.site(k, P, u, x, y, z);
-        stage[site_of(x, y, z, P)] = STAGE_NONE;
-    }
+    for (int k = threadIdx.x; k < n; k += BLOCK) stage[D.chg[off + k]] = STAGE_NONE;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
@@ -1202,15 +1220,15 @@ void launch_integrate(lb_handle *h) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
-void launch_map_mark(lb_handle *h, bool full) {
+void launch_map_mark(lb_handle *h) {
     if (!h->np) return;
-    k_map_mark<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->stage, full ? 1 : 0);
+    k_map_mark<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->stage);
     LB_HIP_CHECK(hipGetLastError());
 }
 
-void launch_map_events(lb_handle *h) {
+void launch_map_flip(lb_handle *h) {
     if (!h->np) return;
-    k_map_events<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage, h->dstate);
+    k_map_flip<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage, h->dstate);
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -1225,7 +1243,10 @@ void launch_cover_refill(lb_handle *h, void *fout) {
 
 void launch_map_commit(lb_handle *h, bool full) {
     if (!h->np) return;
-    k_map_commit<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage, full ? 1 : 0);
+    if (full)
+        k_map_commit_full<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage);
+    else
+        k_map_commit<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage);
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -1283,15 +1304,10 @@ __global__ void kb_integrate(BatchPlan B) {
     const BatchMember &M = B.m[batch_member(B, BM_SPHERE256, g)];
     integrate_body(M.P, M.D, M.dstate, g);
 }
-__global__ __launch_bounds__(BLOCK) void kb_map_mark(BatchPlan B) {
+__global__ __launch_bounds__(BLOCK) void kb_map_flip(BatchPlan B) {
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
-    map_mark_body(M.P, M.D, M.stage, 0, g);
-}
-__global__ __launch_bounds__(BLOCK) void kb_map_events(BatchPlan B) {
-    Grid g;
-    const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
-    map_events_body(M.P, M.D, M.owner, M.stage, M.dstate, g);
+    map_flip_body(M.P, M.D, M.owner, M.stage, M.dstate, g);
 }
 template <typename S>
 __global__ __launch_bounds__(BLOCK) void kb_cover_refill(BatchPlan B) {
@@ -1302,7 +1318,7 @@ __global__ __launch_bounds__(BLOCK) void kb_cover_refill(BatchPlan B) {
 __global__ __launch_bounds__(BLOCK) void kb_map_commit(BatchPlan B) {
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
-    map_commit_body(M.P, M.D, M.owner, M.stage, 0, g);
+    map_commit_body(M.P, M.D, M.owner, M.stage, g);
 }
 __global__ __launch_bounds__(BLOCK) void kb_map_info(BatchPlan B) {
     Grid g;
@@ -1333,8 +1349,7 @@ void launch_batch_particles(const BatchLaunch &L, int parity, hipStream_t s) {
     }
     if (L.total[BM_PAIR_SPHERE] > 0) kb_pair_forces<<<(unsigned)L.total[BM_PAIR_SPHERE], BLOCK, 0, s>>>(B);
     kb_integrate<<<(unsigned)L.total[BM_SPHERE256], BLOCK, 0, s>>>(B);
-    kb_map_mark<<<nsph, BLOCK, 0, s>>>(B);
-    kb_map_events<<<nsph, BLOCK, 0, s>>>(B);
+    kb_map_flip<<<nsph, BLOCK, 0, s>>>(B);
     with_storage(L.prm, [&](auto tag) {
         using S = typename decltype(tag)::type;
         kb_cover_refill<S><<<nsph, BLOCK, 0, s>>>(B);
