@@ -171,7 +171,7 @@ size_t fluid_bytes(const lb_params *p) {
 size_t particle_bytes(const lb_params *p, int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
     const size_t cells = (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
-    size_t b = (size_t)np * (41 * 8 + (21 + MAX_LUB_CONTACTS + CAND_CAP + NB_CAP) * 4 + MAX_LUB_CONTACTS * 32) +
+    size_t b = (size_t)np * (44 * 8 + (21 + MAX_LUB_CONTACTS + CAND_CAP + NB_CAP) * 4 + MAX_LUB_CONTACTS * 32) +
                4 * cells;
     const double reach = 2.0 * max_r + std::max(p->lub_hc, NB_REACH);  // cell list of the pair search
     b += 8 * (size_t)(p->nx / reach + 1) * (size_t)(p->ny / reach + 1) * (size_t)(p->nz / reach + 1);
@@ -182,6 +182,7 @@ size_t particle_bytes(const lb_params *p, int np, double max_r) {
 // rebuild the solid map, the class words and the per-sphere lists from the
 // current positions without touching the fluid
 void rebuild_map(lb_handle *h) {
+    launch_fold_events(h);
     launch_owner_reset(h);
     launch_fill_int(h, h->stage, h->N, STAGE_NONE);
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.Rprev, h->dpart.R, sizeof(double) * 3 * h->np, hipMemcpyDeviceToDevice,
@@ -553,6 +554,7 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
         esum += sc;
     }
     if (ssum > 0x7fffffffLL) return fail(h, LB_EINVAL, "too many spheres for the list capacity");
+    launch_fold_events(h);  // the old spheres' event counts into the totals first
     free_particles(h);
     h->np = tot;
     DevParticles &D = h->dpart;
@@ -642,6 +644,9 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.cov = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.unc = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.chg = (int32_t *)dev_alloc(h, sizeof(int32_t) * 2 * esum);
+    D.evtot = (unsigned long long *)dev_alloc(h, sizeof(unsigned long long) * 3 * (size_t)tot);
+    LB_HIP_CHECK(hipMemsetAsync(D.evtot, 0, sizeof(unsigned long long) * 3 * (size_t)tot, h->stream));
+    h->part_allocs.push_back(D.evtot);
     h->part_allocs.push_back(D.shell);
     h->part_allocs.push_back(D.cov);
     h->part_allocs.push_back(D.unc);
@@ -704,6 +709,7 @@ int lb_observables(lb_handle *h, lb_observables_t *out) {
     LB_API_BEGIN
     std::memset(out, 0, sizeof(*out));
     launch_sums(h, h->f[h->cur]);
+    launch_fold_events(h);
     std::vector<double> part((size_t)5 * h->n_partial);
     LB_HIP_CHECK(hipMemcpyAsync(part.data(), h->partial, part.size() * 8, hipMemcpyDeviceToHost, h->stream));
     DevState st;
@@ -881,6 +887,7 @@ int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
     const int64_t st = h->step;
     std::memcpy(o, &st, 8);
     o += 8;
+    launch_fold_events(h);
     LB_HIP_CHECK(hipMemcpyAsync(o, h->dstate, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     o += sizeof(DevState);
     LB_HIP_CHECK(hipMemcpyAsync(o, h->f[h->cur], fsz, hipMemcpyDeviceToHost, h->stream));

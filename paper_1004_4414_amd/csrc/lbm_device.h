@@ -313,6 +313,8 @@ struct DevParticles {
     // class words changed
     int32_t *chg_cnt, *chg;
     int32_t *dirty;
+    // running covered, uncovered and refill-fallback counts per sphere (np x 3)
+    unsigned long long *evtot;
     int32_t *lbox;  // np x 6: box (lo, ext) of the last list build
     // lubrication contacts (index order) and the velocities after every other force
     int32_t *ncont, *cont;    // np, np x MAX_LUB_CONTACTS

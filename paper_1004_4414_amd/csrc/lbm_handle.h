@@ -118,6 +118,7 @@ void launch_map_flip(lb_handle *h);  // per-step update: changed sites and event
 void launch_cover_refill(lb_handle *h, void *fout);
 void launch_map_commit(lb_handle *h, bool full);
 void launch_map_info(lb_handle *h);
+void launch_fold_events(lb_handle *h);  // per-sphere event counts into DevState
 void launch_build_lists(lb_handle *h, bool full);
 
 // a batch advanced by shared launches: one launch per stage of the step for

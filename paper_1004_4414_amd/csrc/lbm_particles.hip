@@ -722,6 +722,28 @@ __global__ void k_integrate(DevParams P, DevParticles D, DevState *st) {
     integrate_body(P, D, st, own_grid());
 }
 
+// exclusive prefix sum of v over the block (in thread order) and its total;
+// lds: at least BLOCK/64 ints
+__device__ __forceinline__ int block_scan_excl(int v, int &total, int *lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) {
+        const int c = lds[w];
+        if (w < wave) before += c;
+        total += c;
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
 // ---------------------------------------------------------------------------
 // Solid map (Sec. III): a site belongs to the lowest-index sphere whose
 // centre, rounded to 2^-20, is closer than its rounded radius.
@@ -859,12 +881,15 @@ __device__ __forceinline__ void map_flip_body(DevParams P, DevParticles D, const
             unc = chg && o == p && nw == OWN_FLUID;
             if (chg) stage[n] = nw == OWN_FLUID ? STAGE_FLUID : nw;  // the same value from every block
         }
-        int slot = block_compact(chg, nchg, lds);
-        if (chg && slot < ccap) D.chg[coff + slot] = (int32_t)n;
-        slot = block_compact(cov, ncov, lds);
-        if (cov && slot < ecap) D.cov[eoff + slot] = (int32_t)n;
-        slot = block_compact(unc, nunc, lds);
-        if (unc && slot < ecap) D.unc[eoff + slot] = (int32_t)n;
+        // the three list slots from one block scan of packed 10-bit flags
+        int total;
+        const int pre = block_scan_excl((int)chg | ((int)cov << 10) | ((int)unc << 20), total, lds);
+        if (chg && nchg + (pre & 1023) < ccap) D.chg[coff + nchg + (pre & 1023)] = (int32_t)n;
+        if (cov && ncov + ((pre >> 10) & 1023) < ecap) D.cov[eoff + ncov + ((pre >> 10) & 1023)] = (int32_t)n;
+        if (unc && nunc + (pre >> 20) < ecap) D.unc[eoff + nunc + (pre >> 20)] = (int32_t)n;
+        nchg += total & 1023;
+        ncov += (total >> 10) & 1023;
+        nunc += total >> 20;
     };
     if (cand_ok) {  // uniform over the block
         const int nc = D.ncand[p];
@@ -1039,15 +1064,21 @@ __device__ __forceinline__ void cover_refill_body(DevParams P, DevParticles D, S
             v[5] -= r[0] * mom[1] - r[1] * mom[0];
         }
     }
-    if (fallback) atomicAdd(&st->refill_fallback, (unsigned long long)fallback);
+    __shared__ int nfall;
+    if (threadIdx.x == 0) nfall = 0;
+    __syncthreads();
+    if (fallback) atomicAdd(&nfall, fallback);  // LDS, integer
     block_sum<6>(v, lds);
     if (threadIdx.x == 0) {
         for (int a = 0; a < 3; ++a) {
             D.P[3 * p + a] += v[a];
             D.PT[3 * p + a] += v[3 + a];
         }
-        atomicAdd(&st->covered_total, (unsigned long long)nc);
-        atomicAdd(&st->uncovered_total, (unsigned long long)nu);
+        // the sphere's own running counts (one writer, no atomics on a
+        // shared counter); k_fold_events moves them into the totals
+        D.evtot[3 * p] += (unsigned long long)nc;
+        D.evtot[3 * p + 1] += (unsigned long long)nu;
+        D.evtot[3 * p + 2] += (unsigned long long)nfall;
     }
 }
 
@@ -1056,6 +1087,36 @@ __global__ __launch_bounds__(BLOCK) void k_cover_refill(DevParams P, DevParticle
                                                         const int32_t *__restrict__ owner,
                                                         const int32_t *__restrict__ stage, DevState *st) {
     cover_refill_body<S>(P, D, f, owner, stage, st, own_grid());
+}
+
+// the spheres' running event counts added to the totals, and cleared (one
+// block; integer sums)
+__global__ __launch_bounds__(BLOCK) void k_fold_events(DevParticles D, int np, DevState *st) {
+    __shared__ unsigned long long red[3][BLOCK];
+    unsigned long long c[3] = {0, 0, 0};
+    for (int p = threadIdx.x; p < np; p += BLOCK)
+        for (int k = 0; k < 3; ++k) {
+            c[k] += D.evtot[3 * p + k];
+            D.evtot[3 * p + k] = 0;
+        }
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = c[k];
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->covered_total += red[0][0];
+        st->uncovered_total += red[1][0];
+        st->refill_fallback += red[2][0];
+    }
+}
+
+void launch_fold_events(lb_handle *h) {
+    if (!h->np) return;
+    k_fold_events<<<1, BLOCK, 0, h->stream>>>(h->dpart, h->np, h->dstate);
+    LB_HIP_CHECK(hipGetLastError());
 }
 
 // owners after a full classification: the marks of the box (identical values

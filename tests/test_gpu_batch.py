@@ -220,3 +220,62 @@ def test_jobs_without_steps_are_refused():
     j = S.Job(W.params(nx=16, ny=16, nz=16), W.empty_particles(), 0, name="empty")
     with pytest.raises(ValueError):
         S.Server(1 << 40, precision="fp32", steps_per_launch=10).run([j])
+
+
+def _oracle_compare(lat, ref, p, parts):
+    g, r = lat.fields(), ref.fields()
+    rbar = np.array(p["rho_init"])
+    for c in range(2):
+        assert np.abs(g["rho"][c] - r["rho"][c]).max() / rbar[c] < 1e-9
+    assert np.abs(g["u"] - r["u"]).max() / max(np.abs(r["u"]).max(), 1e-30) < 1e-8
+    assert np.array_equal(lat.owner(), ref.owner())
+    if parts is not None:
+        Pg, Pr = lat.particles(), ref.particles()
+        for k in ("R", "U", "W", "Ffluid", "Tfluid"):
+            assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+
+
+def test_batch_members_fp64_match_the_oracle():
+    """Two FP64 members (moving coloured spheres; a sphere-free box) advanced
+    only by graph launches of a batch, then each compared with the oracle end
+    to end: densities 1e-9, velocities 1e-8, the solid map exactly, sphere
+    positions, velocities, forces and torques 1e-9."""
+    from oracle.oracle import Oracle
+    p1 = W.params(nx=20, ny=20, nz=20, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=31)
+    parts = W.make_particles([[5.2, 5.5, 6.1], [14.3, 6.2, 13.7]], [3.0, 2.6],
+                             vel=[[0.04, 0.03, -0.02], [-0.03, 0.05, 0.01]], color=[0.05, -0.05],
+                             density=[0.8, 1.2])
+    p2 = W.params(nx=16, ny=12, nz=10, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.09, seed=32)
+    lats = [lbm().Lattice(p1, precision="fp64"), lbm().Lattice(p2, precision="fp64")]
+    lats[0].add_particles(parts)
+    batch = lbm().Batch(lats, steps_per_launch=4)
+    batch.step(10)
+    batch.close()
+    for lat, p, pr in zip(lats, (p1, p2), (parts, None)):
+        ref = Oracle(p)
+        if pr is not None:
+            assert ref.add_particles(pr) == 0
+        ref.step(40)
+        assert lat.observables()["step"] == 40
+        _oracle_compare(lat, ref, p, pr)
+
+
+def test_served_job_fp64_matches_the_oracle():
+    """A job served in FP64 beside another (both resident, advanced by shared
+    graph launches) ends with the densities the oracle computes for it alone
+    (1e-9 relative)."""
+    from oracle.oracle import Oracle
+    from paper_1004_4414_amd import serving as S
+    p1 = W.params(nx=20, ny=18, nz=16, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.06, seed=33)
+    a = S.Job(p1, W.make_particles([[6.2, 7.1, 8.3]], 3.0, vel=[[0.03, -0.02, 0.01]]), 30, arrival=0.0,
+              contact_angle=70.0, name="a")
+    p2 = W.params(nx=24, ny=16, nz=16, seed=34)
+    b = S.Job(p2, W.make_particles([[12.0, 8.0, 8.0]], 4.0), 60, arrival=0.0, name="b")
+    srv = S.Server(1 << 40, precision="fp64", steps_per_launch=10, keep_density=("a",))
+    res = {r.name: r for r in srv.run([a, b], clock=_FakeClock(0.01))}
+    ref = Oracle(p1)
+    assert ref.add_particles(S.coloured(a)) == 0
+    ref.step(30)
+    rho = ref.fields()["rho"]
+    for c in range(2):
+        assert np.abs(res["a"].extra["rho"][c] - rho[c]).max() / p1["rho_init"][c] < 1e-9
