@@ -96,7 +96,9 @@ typedef struct {
     double k_hertz;          /* K_Hertz of Eq. (21) */
     double lub_hc, lub_hmin; /* lubrication cut-off and clamp gaps of Eq. (22); hc <= 0: off */
     int32_t kernel;          /* LB_KERNEL_* */
-    int32_t tile[3];         /* tile edge lengths of the fused kernel; 0 = automatic */
+    int32_t tile[3];         /* tile of the fused kernel: x is 64, y 4 or 8 (FP64: 4), z the
+                                planes of one segment (clamped to nz); other or 0 values
+                                take 64, 4, 64 */
     int32_t lub_mode;        /* how Eq. (22) enters the leap-frog of Eqs. (9), (10), which the
                                 paper does not fix for a velocity-dependent force:
                                 0: explicit force from the velocities U(t - 1/2), as printed;

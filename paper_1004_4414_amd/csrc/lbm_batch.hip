@@ -10,6 +10,7 @@
 // capture each member's own launches on a stream of its own, forked from and
 // joined into the capture stream (independent branches).  Either way a
 // member's result is bitwise the same alone and in a batch.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 
@@ -260,14 +261,18 @@ int lb_autotune(lb_params *p, int32_t n, const lb_particle *parts, int32_t trial
     };
     std::vector<Cand> cands;
     cands.push_back({LB_KERNEL_TWOPASS, 0, 0, 0});
-    const bool wide = p->precision == LB_FP64 || p->precision == LB_FP32;
-    if (wide && lbm::fused_supported(*p)) {
-        const int shapes[4][2] = {{64, 4}, {32, 8}, {32, 4}, {16, 8}};
-        for (auto &sh : shapes) {
-            if (p->precision == LB_FP64 && !((sh[0] == 32 && sh[1] == 4) || (sh[0] == 16 && sh[1] == 8))) continue;
-            if (sh[0] > p->nx - 2 || sh[1] > p->ny - 2) continue;
-            for (int tz : {8, 16, 32, 64})
-                if (tz < p->nz) cands.push_back({LB_KERNEL_FUSED, sh[0], sh[1], tz});
+    if (lbm::fused_supported(*p)) {
+        // the fused sweep's tiles: 64 x TY columns (TY = 4 or 8; FP64 4) and
+        // z segments of TZ planes (five extra planes start each segment)
+        for (int ty : {4, 8}) {
+            if (p->precision == LB_FP64 && ty != 4) continue;
+            int last = 0;
+            for (int tz : {32, 64, 128, 256}) {
+                const int z = std::min(tz, p->nz);
+                if (z == last) continue;
+                last = z;
+                cands.push_back({LB_KERNEL_FUSED, 64, ty, z});
+            }
         }
     }
     double best = 1e300;
