@@ -281,6 +281,19 @@ void choose_fused_tile(lb_handle *h) {
 void enqueue_step(lb_handle *h) {
     void *fin = h->f[h->cur], *fout = h->f[1 - h->cur];
     hipEvent_t t_step = h->timing_begin(2);
+    // The pair search and forces read only the spheres' positions and
+    // velocities, which nothing changes before the integration: outside a
+    // stream capture they run on a second stream beside the fluid sweep and
+    // the link sums (a captured step keeps them on the one stream).
+    hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+    LB_HIP_CHECK(hipStreamIsCapturing(h->stream, &capturing));
+    const bool fork = h->np && capturing == hipStreamCaptureStatusNone;
+    if (fork) {
+        LB_HIP_CHECK(hipEventRecord(h->ev_fork, h->stream));
+        LB_HIP_CHECK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+        launch_pair_forces(h, h->side);
+        LB_HIP_CHECK(hipEventRecord(h->ev_join, h->side));
+    }
     if (h->kernel == LB_KERNEL_FUSED) {
         hipEvent_t t_col = h->timing_begin(0);
         launch_fused(h, fin, fout);
@@ -299,7 +312,9 @@ void enqueue_step(lb_handle *h) {
     launch_wall_links(h, fout);
     if (h->np) {
         launch_particle_fluid_force(h, fout);
-        launch_pair_forces(h);
+        if (fork) LB_HIP_CHECK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
+        else launch_pair_forces(h, h->stream);
+        launch_forces_total(h);
         launch_integrate(h);
         launch_map_flip(h);  // also clears the dirty cells
         launch_cover_refill(h, fout);
@@ -433,6 +448,9 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
                                  ((p->ny + h->fused_ty - 1) / h->fused_ty) * ((p->nz + h->fused_tz - 1) / h->fused_tz);
         h->partial = (double *)dev_alloc(h, (size_t)std::max(8LL * h->n_partial, 2 * nfused + 16) * 8);
         h->dstate = (DevState *)dev_alloc(h, sizeof(DevState));
+        LB_HIP_CHECK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        LB_HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        LB_HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
         LB_HIP_CHECK(hipMemsetAsync(h->dstate, 0, sizeof(DevState), h->stream));
         LB_HIP_CHECK(hipMemsetAsync(h->f[1], 0, fsz, h->stream));
         launch_fill_int(h, h->stage, h->N, STAGE_NONE);
@@ -454,6 +472,12 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
 void lb_destroy(lb_handle *h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     release_events(h);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     h->ev_pool.clear();

@@ -13,6 +13,10 @@ struct lb_handle {
     lb_params prm{};
     lbm::DevParams dp{};
     hipStream_t stream = nullptr;
+    // the pair search runs on a stream of its own, forked from `stream` at the
+    // start of a step and joined before the sphere forces are summed
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;  // the device current at lb_create
     lb_allocator alloc{};
     bool have_alloc = false;
@@ -111,7 +115,8 @@ void launch_owner_reset(lb_handle *h);
 
 // particles (lbm_particles.hip)
 void launch_particle_fluid_force(lb_handle *h, void *fout);
-void launch_pair_forces(lb_handle *h);
+void launch_pair_forces(lb_handle *h, hipStream_t s);
+void launch_forces_total(lb_handle *h);
 void launch_integrate(lb_handle *h);
 void launch_map_mark(lb_handle *h);  // full classification (marks in stage[])
 void launch_map_flip(lb_handle *h);  // per-step update: changed sites and events

@@ -447,9 +447,7 @@ __device__ __forceinline__ void pair_forces_body(DevParams P, DevParticles D, De
         D.ncont[p] = P.lub_mode == 0 ? 0 : min(ncont, MAX_LUB_CONTACTS);
         if (P.lub_mode != 0 && ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
-            D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + F[a];
-            D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
-            D.vs[3 * p + a] = D.U[3 * p + a] + (D.prescribed[p] ? 0.0 : D.Ftot[3 * p + a] / D.mass[p]);
+            D.Ftot[3 * p + a] = F[a];  // the pair forces; k_forces_total adds the rest
         }
     }
 }
@@ -568,6 +566,7 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
         if (t == 0) {
             D.ncont[p] = 0;
             D.nnbr[p] = NB_CAP + 1;  // unknown: the map update tests every sphere
+            for (int a = 0; a < 3; ++a) D.Ftot[3 * p + a] = 0.0;
             atomicOr(&st->overflow, 16);
         }
         return;
@@ -665,15 +664,30 @@ __device__ __forceinline__ void pair_forces_cells_body(DevParams P, DevParticles
         D.ncont[p] = P.lub_mode == 0 ? 0 : min(ncont, MAX_LUB_CONTACTS);
         if (P.lub_mode != 0 && ncont > MAX_LUB_CONTACTS) atomicOr(&st->overflow, 16);
         for (int a = 0; a < 3; ++a) {
-            D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + F[a];
-            D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
-            D.vs[3 * p + a] = D.U[3 * p + a] + (D.prescribed[p] ? 0.0 : D.Ftot[3 * p + a] / D.mass[p]);
+            D.Ftot[3 * p + a] = F[a];  // the pair forces; k_forces_total adds the rest
         }
     }
 }
 
 __global__ __launch_bounds__(64) void k_pair_forces_cells(DevParams P, DevParticles D, DevState *st) {
     pair_forces_cells_body(P, D, st, own_grid());
+}
+
+// total force and torque of each sphere (fluid, pending impulses, pair forces
+// in that order of summation) and its velocity after every force but the
+// lubrication impulses
+__device__ __forceinline__ void forces_total_body(DevParams P, DevParticles D, const Grid &g) {
+    const int p = g.bid * BLOCK + threadIdx.x;
+    if (p >= P.np) return;
+    for (int a = 0; a < 3; ++a) {
+        D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + D.Ftot[3 * p + a];
+        D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
+        D.vs[3 * p + a] = D.U[3 * p + a] + (D.prescribed[p] ? 0.0 : D.Ftot[3 * p + a] / D.mass[p]);
+    }
+}
+
+__global__ void k_forces_total(DevParams P, DevParticles D) {
+    forces_total_body(P, D, own_grid());
 }
 
 // lubrication impulses, then the leap-frog of Eqs. (9), (10):
@@ -1186,6 +1200,8 @@ __global__ __launch_bounds__(BLOCK) void k_map_info(DevParams P, DevParticles D,
     map_info_body(P, D, owner, info, stage, own_grid());
 }
 
+constexpr int LIST_ROWS = 1024;  // box rows of the banded list walk (larger boxes scan whole)
+
 // virtual-fluid sites of sphere p on the new map, in scan order of its box,
 // and the number of its bounce-back links (fluid neighbours of those sites)
 __device__ __forceinline__ void build_lists_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
@@ -1212,24 +1228,107 @@ __device__ __forceinline__ void build_lists_body(DevParams P, DevParticles D, co
         lb[threadIdx.x] = lo[threadIdx.x];
         lb[3 + threadIdx.x] = ext[threadIdx.x];
     }
-    const BoxWalk bw(P, lo, ext);
-    const int V = bw.size();
     const int soff = D.shell_off[p], scap = D.shell_cap[p];
     int nshell = 0, nlink = 0;
-    for (int start = 0; start < V; start += BLOCK) {
-        const int k = start + threadIdx.x;
-        bool sh = false;
-        long long n = 0;
-        if (k < V) {
-            int u[3], x, y, z;
-            bw.site(k, P, u, x, y, z);
-            n = site_of(x, y, z, P);
-            const uint32_t inf = info[n];
-            sh = owner[n] == p && site_class(inf) == CLS_SHELL;
-            if (sh) nlink += __popc(~inf & 0x7fffeu);
+    const int nrow = ext[1] * ext[2];
+    if (nrow <= LIST_ROWS) {
+        // Only sites with r - 1.5 < |x - R| < r + 0.01 can qualify: a site of p
+        // lies inside p, and a fluid neighbour (at most sqrt(2) away) lies
+        // outside it.  In each box row (y, z) they form at most two x ranges
+        // (rounded outwards); the walk visits them in the box's scan order, so
+        // the list is the one a scan of the whole box gives.
+        __shared__ int roff[LIST_ROWS + 1];
+        __shared__ short rx[LIST_ROWS][4];  // [rx0, rx1) and [rx2, rx3), relative to lo[0]
+        long long cq[3];
+        for (int a = 0; a < 3; ++a) cq[a] = fixed20(D.R[3 * p + a]);
+        const double S = 1048576.0;
+        const double rq = (double)fixed20(D.rad[p]);
+        const double ro = rq + 0.01 * S, ri = fmax(0.0, rq - 1.5 * S);
+        const double xc = (double)cq[0] / S;
+        const int per = (nrow + BLOCK - 1) / BLOCK;
+        int cnt = 0;
+        for (int j = 0; j < per; ++j) {
+            const int r = (int)threadIdx.x * per + j;
+            if (r >= nrow) break;
+            const long long uy = lo[1] + r % ext[1], uz = lo[2] + r / ext[1];
+            const double dy = (double)((uy << 20) - cq[1]), dz = (double)((uz << 20) - cq[2]);
+            const double h2 = dy * dy + dz * dz;
+            int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+            if (h2 < ro * ro) {
+                const double xa = sqrt(ro * ro - h2) / S, xb = h2 < ri * ri ? sqrt(ri * ri - h2) / S : 0.0;
+                int l0 = (int)floor(xc - xa), l1 = (int)ceil(xc - xb) + 1;
+                int r0 = (int)floor(xc + xb), r1 = (int)ceil(xc + xa) + 1;
+                if (l1 >= r0) {  // one range
+                    l1 = r1;
+                    r0 = r1;
+                }
+                const int e0 = lo[0], e1 = lo[0] + ext[0];
+                l0 = max(l0, e0);
+                l1 = max(min(l1, e1), l0);
+                r0 = max(r0, l1);
+                r1 = max(min(r1, e1), r0);
+                a0 = l0 - e0;
+                a1 = l1 - e0;
+                b0 = r0 - e0;
+                b1 = r1 - e0;
+            }
+            rx[r][0] = (short)a0;
+            rx[r][1] = (short)a1;
+            rx[r][2] = (short)b0;
+            rx[r][3] = (short)b1;
+            cnt += (a1 - a0) + (b1 - b0);
         }
-        const int slot = block_compact(sh, nshell, lds);
-        if (sh && slot < scap) D.shell[soff + slot] = (int32_t)n;
+        int tot;
+        int base = block_scan_excl(cnt, tot, lds);  // barrier: every rx row is written
+        for (int j = 0; j < per; ++j) {
+            const int r = (int)threadIdx.x * per + j;
+            if (r >= nrow) break;
+            roff[r] = base;
+            base += (rx[r][1] - rx[r][0]) + (rx[r][3] - rx[r][2]);
+        }
+        if (threadIdx.x == 0) roff[nrow] = tot;
+        __syncthreads();
+        for (int start = 0; start < tot; start += BLOCK) {
+            const int k = start + threadIdx.x;
+            bool sh = false;
+            long long n = 0;
+            if (k < tot) {
+                int rl = 0, rh = nrow;  // roff[rl] <= k < roff[rh]
+                while (rh - rl > 1) {
+                    const int mid = (rl + rh) >> 1;
+                    if (roff[mid] <= k) rl = mid;
+                    else rh = mid;
+                }
+                const int off = k - roff[rl], la = rx[rl][1] - rx[rl][0];
+                const int dx = off < la ? rx[rl][0] + off : rx[rl][2] + (off - la);
+                const int x = wrapany(lo[0] + dx, P.nx), y = wrapany(lo[1] + rl % ext[1], P.ny),
+                          z = wrapany(lo[2] + rl / ext[1], P.nz);
+                n = site_of(x, y, z, P);
+                const uint32_t inf = info[n];
+                sh = owner[n] == p && site_class(inf) == CLS_SHELL;
+                if (sh) nlink += __popc(~inf & 0x7fffeu);
+            }
+            const int slot = block_compact(sh, nshell, lds);
+            if (sh && slot < scap) D.shell[soff + slot] = (int32_t)n;
+        }
+    } else {
+        const BoxWalk bw(P, lo, ext);
+        const int V = bw.size();
+        for (int start = 0; start < V; start += BLOCK) {
+            const int k = start + threadIdx.x;
+            bool sh = false;
+            long long n = 0;
+            if (k < V) {
+                int u[3], x, y, z;
+                bw.site(k, P, u, x, y, z);
+                n = site_of(x, y, z, P);
+                const uint32_t inf = info[n];
+                sh = owner[n] == p && site_class(inf) == CLS_SHELL;
+                if (sh) nlink += __popc(~inf & 0x7fffeu);
+            }
+            const int slot = block_compact(sh, nshell, lds);
+            if (sh && slot < scap) D.shell[soff + slot] = (int32_t)n;
+        }
     }
     atomicAdd(&nlink_block, nlink);  // integer sum: order does not matter
     __syncthreads();
@@ -1261,17 +1360,23 @@ void launch_particle_fluid_force(lb_handle *h, void *fout) {
 
 // the cell list (PAIR_CELLS_MIN_SPHERES) pays off from about a thousand
 // spheres; fewer take the all-pairs kernel (one launch instead of four)
-void launch_pair_forces(lb_handle *h) {
+void launch_pair_forces(lb_handle *h, hipStream_t s) {
     if (!h->np) return;
     if (h->dpart.pgx > 0 && h->np >= PAIR_CELLS_MIN_SPHERES) {
         const unsigned nb = (unsigned)((h->np + BLOCK - 1) / BLOCK);
-        k_pcell_count<<<nb, BLOCK, 0, h->stream>>>(h->dp, h->dpart);
-        k_pcell_scan<<<1, PCS_THREADS, 0, h->stream>>>(h->dpart);
-        k_pcell_fill<<<nb, BLOCK, 0, h->stream>>>(h->dp, h->dpart);
-        k_pair_forces_cells<<<h->np, 64, 0, h->stream>>>(h->dp, h->dpart, h->dstate);
+        k_pcell_count<<<nb, BLOCK, 0, s>>>(h->dp, h->dpart);
+        k_pcell_scan<<<1, PCS_THREADS, 0, s>>>(h->dpart);
+        k_pcell_fill<<<nb, BLOCK, 0, s>>>(h->dp, h->dpart);
+        k_pair_forces_cells<<<h->np, 64, 0, s>>>(h->dp, h->dpart, h->dstate);
     } else {
-        k_pair_forces<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->dstate);
+        k_pair_forces<<<h->np, BLOCK, 0, s>>>(h->dp, h->dpart, h->dstate);
     }
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_forces_total(lb_handle *h) {
+    if (!h->np) return;
+    k_forces_total<<<(h->np + BLOCK - 1) / BLOCK, BLOCK, 0, h->stream>>>(h->dp, h->dpart);
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -1360,6 +1465,11 @@ __global__ __launch_bounds__(BLOCK) void kb_pair_forces(BatchPlan B) {
     const BatchMember &M = B.m[batch_member(B, BM_PAIR_SPHERE, g)];
     pair_forces_body(M.P, M.D, M.dstate, g);
 }
+__global__ void kb_forces_total(BatchPlan B) {
+    Grid g;
+    const BatchMember &M = B.m[batch_member(B, BM_SPHERE256, g)];
+    forces_total_body(M.P, M.D, g);
+}
 __global__ void kb_integrate(BatchPlan B) {
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_SPHERE256, g)];
@@ -1409,6 +1519,7 @@ void launch_batch_particles(const BatchLaunch &L, int parity, hipStream_t s) {
         kb_pair_forces_cells<<<(unsigned)L.total[BM_CELL_SPHERE], 64, 0, s>>>(B);
     }
     if (L.total[BM_PAIR_SPHERE] > 0) kb_pair_forces<<<(unsigned)L.total[BM_PAIR_SPHERE], BLOCK, 0, s>>>(B);
+    kb_forces_total<<<(unsigned)L.total[BM_SPHERE256], BLOCK, 0, s>>>(B);
     kb_integrate<<<(unsigned)L.total[BM_SPHERE256], BLOCK, 0, s>>>(B);
     kb_map_flip<<<nsph, BLOCK, 0, s>>>(B);
     with_storage(L.prm, [&](auto tag) {
