@@ -108,6 +108,12 @@ typedef struct {
                                 1 (default): pair impulses J = c w / (1 + c (k_p/m_p + k_q/m_q))
                                    from the velocities after every other force (k: lubrication
                                    contacts of a sphere), backward Euler for an isolated pair */
+    int32_t link_writes;     /* where the bounced populations of sphere links (Eq. (16)) are
+                                formed, with bitwise the same result: 1 (default): the link
+                                kernel writes every one into the solid site's slot; 0: with the
+                                two-pass sweep, outside a stream capture, the next step's density
+                                sweep forms each from the fluid site's own slot (only links next
+                                to a map change are written out by the map update) */
 } lb_params;
 
 typedef struct {

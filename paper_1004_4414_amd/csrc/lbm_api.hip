@@ -103,6 +103,8 @@ void set_dev_params(lb_handle *h) {
     d.eq_order = p.eq_order;
     d.wall_axis = p.wall_axis;
     d.lub_mode = p.lub_mode;
+    d.link_write = 1;  // set per step by the step's launcher
+    d.redirect = 0;
     d.any_color = 0;
     for (double c : h->h_color) d.any_color |= c != 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -128,6 +130,7 @@ int validate_params(const lb_params *p, std::string &msg) {
     if (p->velocity_mode != 0 && p->velocity_mode != 1) return msg = "velocity_mode must be 0 or 1", LB_EINVAL;
     if (p->eq_order != 2 && p->eq_order != 3) return msg = "eq_order must be 2 or 3", LB_EINVAL;
     if (p->lub_mode != 0 && p->lub_mode != 1) return msg = "lub_mode must be 0 or 1", LB_EINVAL;
+    if (p->link_writes != 0 && p->link_writes != 1) return msg = "link_writes must be 0 or 1", LB_EINVAL;
     if (p->wall_axis < -1 || p->wall_axis > 2) return msg = "wall_axis must be -1, 0, 1 or 2", LB_EINVAL;
     if (p->wall_axis >= 0 && (p->wall_axis == 0 ? p->nx : (p->wall_axis == 1 ? p->ny : p->nz)) < 3)
         return msg = "a box with walls needs at least 3 sites along the wall axis", LB_EINVAL;
@@ -162,7 +165,7 @@ size_t fluid_bytes(const lb_params *p) {
     size_t b = 0;
     const size_t Np = padded_sites(N);
     b += 2 * (size_t)(2 * Q) * Np * ts;  // two population buffers
-    b += 8 * Np * tc;                    // densities, Psi, shell force (padded to 4)
+    b += 10 * Np * tc;                   // densities of two steps, Psi, shell force (padded to 4)
     b += 3 * (size_t)N * 4;             // info, owner, stage
     b += 8 * (size_t)nblk(N) * 8 + 4096;
     return b;
@@ -171,17 +174,19 @@ size_t fluid_bytes(const lb_params *p) {
 size_t particle_bytes(const lb_params *p, int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
     const size_t cells = (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
-    size_t b = (size_t)np * (44 * 8 + (21 + MAX_LUB_CONTACTS + CAND_CAP + NB_CAP) * 4 + MAX_LUB_CONTACTS * 32) +
+    size_t b = (size_t)np * (53 * 8 + (22 + MAX_LUB_CONTACTS + CAND_CAP + NB_CAP) * 4 + MAX_LUB_CONTACTS * 32) +
                4 * cells;
     const double reach = 2.0 * max_r + std::max(p->lub_hc, NB_REACH);  // cell list of the pair search
     b += 8 * (size_t)(p->nx / reach + 1) * (size_t)(p->ny / reach + 1) * (size_t)(p->nz / reach + 1);
-    b += (size_t)np * sc * (4 + 4 * 4);  // virtual-fluid sites; covered, uncovered and changed sites
+    b += (size_t)np * sc * (4 + 6 * 4);  // virtual-fluid sites; covered, uncovered and two steps' changed sites
     return b + 4096;
 }
 
 // rebuild the solid map, the class words and the per-sphere lists from the
 // current positions without touching the fluid
 void rebuild_map(lb_handle *h) {
+    settle_bounces(h);  // on the map they belong to
+    h->flags_tracked = false;
     launch_fold_events(h);
     launch_owner_reset(h);
     launch_fill_int(h, h->stage, h->N, STAGE_NONE);
@@ -278,6 +283,28 @@ void choose_fused_tile(lb_handle *h) {
     h->fused_tz = std::max(1, std::min(tz, p.nz));
 }
 
+// Bounced populations of sphere links, Eq. (16).  The link kernel reads f*_i(x)
+// from the fluid site's slot (i, x) for the momentum sums; writing the bounced
+// pair into the solid site's slot (opp(i), x + c_i) is a scattered 8-byte store
+// into a line the sweep wrote in full long before, per link.  With the
+// two-pass sweep (sweep_bounce), the next step's density and collide sweeps
+// form the pair themselves from slot (i, x), the density deviations of x of
+// the bounce's step (rho_prev) and the sphere state the link kernel used,
+// and the solid slot is left at the zero the sweep stored there.  The map
+// update changes links: for the fluid sites within one site of a site whose
+// owner changes, the fix-up writes the bounced pairs out before covering and
+// refilling read or overwrite those slots, and the class-word kernel flags
+// their words, so the next sweep pulls them plainly.  Readers of the stored
+// populations outside the sweeps (observables, fields, checkpoints, batches,
+// a full map rebuild) first write out every pending pair (settle_bounces).
+// This is the lb_params.link_writes = 0 option: measured at 256^3 with 4806
+// spheres, the density sweep's extra dependent loads at boundary sites (most
+// wavefronts have some) cost more than the scattered stores it saves, so the
+// link kernel writes the pairs by default.
+bool sweep_bounce(const lb_handle *h, bool capturing) {
+    return h->np > 0 && h->kernel == LB_KERNEL_TWOPASS && !capturing && h->prm.link_writes == 0;
+}
+
 void enqueue_step(lb_handle *h) {
     void *fin = h->f[h->cur], *fout = h->f[1 - h->cur];
     hipEvent_t t_step = h->timing_begin(2);
@@ -288,6 +315,23 @@ void enqueue_step(lb_handle *h) {
     hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
     LB_HIP_CHECK(hipStreamIsCapturing(h->stream, &capturing));
     const bool fork = h->np && capturing == hipStreamCaptureStatusNone;
+    const bool sb = sweep_bounce(h, capturing != hipStreamCaptureStatusNone);
+    if (!sb) settle_bounces(h);
+    if (sb) {
+        std::swap(h->rho, h->rho_prev);
+        std::swap(h->dpart.chg, h->dpart.chg_prev);
+        std::swap(h->dpart.chg_cnt, h->dpart.chg_prev_cnt);
+        // without the previous update's lists every flag is cleared here (no
+        // bounce is pending then: the previous step wrote its links)
+        if (!h->flags_tracked) launch_clear_flags(h);
+        h->dpart.track_flags = h->flags_tracked ? 1 : 0;
+        h->dp.redirect = h->bounce_pending ? 1 : 0;
+        h->dp.link_write = 0;
+    } else {
+        h->dpart.track_flags = 0;
+        h->dp.redirect = 0;
+        h->dp.link_write = 1;
+    }
     if (fork) {
         LB_HIP_CHECK(hipEventRecord(h->ev_fork, h->stream));
         LB_HIP_CHECK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
@@ -316,7 +360,8 @@ void enqueue_step(lb_handle *h) {
         else launch_pair_forces(h, h->stream);
         launch_forces_total(h);
         launch_integrate(h);
-        launch_map_flip(h);  // also clears the dirty cells
+        launch_map_flip(h);  // also clears the dirty cells (and the previous update's flags)
+        if (sb) launch_map_fixup(h, fout);
         launch_cover_refill(h, fout);
         launch_map_commit(h, false);
         launch_map_info(h);
@@ -325,6 +370,10 @@ void enqueue_step(lb_handle *h) {
     h->timing_end(2, t_step);
     h->cur = 1 - h->cur;
     ++h->step;
+    h->bounce_pending = sb;
+    h->flags_tracked = sb;
+    h->dp.redirect = 0;  // other launches between steps pull plainly
+    h->dp.link_write = 1;
 }
 
 void release_events(lb_handle *h) {
@@ -340,6 +389,12 @@ void release_events(lb_handle *h) {
 }  // namespace
 
 void lbm::one_step(lb_handle *h) { enqueue_step(h); }
+
+void lbm::settle_bounces(lb_handle *h) {
+    if (!h->bounce_pending) return;
+    launch_materialize(h, h->f[h->cur]);
+    h->bounce_pending = false;
+}
 
 hipEvent_t lb_handle::timing_begin(int) {
     if (!timing) return nullptr;
@@ -391,6 +446,7 @@ void lb_default_params(lb_params *p) {
     p->lub_hmin = 0.1;
     p->kernel = LB_KERNEL_AUTO;
     p->lub_mode = 1;
+    p->link_writes = 1;
 }
 
 // message of the last failed lb_create on this thread (lb_last_error(NULL))
@@ -438,6 +494,7 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         h->f[0] = dev_alloc(h, fsz);
         h->f[1] = dev_alloc(h, fsz);
         h->rho = dev_alloc(h, (size_t)2 * Np * h->csize);
+        h->rho_prev = dev_alloc(h, (size_t)2 * Np * h->csize);
         h->psi = dev_alloc(h, (size_t)2 * Np * h->csize);
         h->fsc = dev_alloc(h, (size_t)4 * Np * h->csize);
         h->info = (uint32_t *)dev_alloc(h, (size_t)h->N * 4);
@@ -668,6 +725,16 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.cov = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.unc = (int32_t *)dev_alloc(h, sizeof(int32_t) * esum);
     D.chg = (int32_t *)dev_alloc(h, sizeof(int32_t) * 2 * esum);
+    D.chg_prev = (int32_t *)dev_alloc(h, sizeof(int32_t) * 2 * esum);
+    D.chg_prev_cnt = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
+    D.Rl = (double *)dev_alloc(h, sizeof(double) * 9 * (size_t)tot);
+    D.Ul = D.Rl + 3 * tot;
+    D.Wl = D.Rl + 6 * tot;
+    D.track_flags = 0;
+    LB_HIP_CHECK(hipMemsetAsync(D.chg_prev_cnt, 0, sizeof(int32_t) * (size_t)tot, h->stream));
+    h->part_allocs.push_back(D.chg_prev);
+    h->part_allocs.push_back(D.chg_prev_cnt);
+    h->part_allocs.push_back(D.Rl);
     D.evtot = (unsigned long long *)dev_alloc(h, sizeof(unsigned long long) * 3 * (size_t)tot);
     LB_HIP_CHECK(hipMemsetAsync(D.evtot, 0, sizeof(unsigned long long) * 3 * (size_t)tot, h->stream));
     h->part_allocs.push_back(D.evtot);
@@ -731,6 +798,7 @@ int lb_synchronize(lb_handle *h) {
 int lb_observables(lb_handle *h, lb_observables_t *out) {
     if (!h || !out) return LB_EINVAL;
     LB_API_BEGIN
+    settle_bounces(h);
     std::memset(out, 0, sizeof(*out));
     launch_sums(h, h->f[h->cur]);
     launch_fold_events(h);
@@ -776,6 +844,7 @@ int lb_observables(lb_handle *h, lb_observables_t *out) {
 int lb_get_fields(lb_handle *h, double *rho, double *j, double *force, double *u) {
     if (!h) return LB_EINVAL;
     LB_API_BEGIN
+    settle_bounces(h);
     const long long N = h->N;
     if (!h->fields) h->fields = (double *)dev_alloc(h, sizeof(double) * 17 * N);
     launch_density(h, h->f[h->cur], false);
@@ -793,6 +862,7 @@ int lb_get_fields(lb_handle *h, double *rho, double *j, double *force, double *u
 int lb_get_populations(lb_handle *h, double *f) {
     if (!h || !f) return LB_EINVAL;
     LB_API_BEGIN
+    settle_bounces(h);
     with_storage(h->prm, [&](auto tag) { to_host_populations<typename decltype(tag)::type>(h, f); });
     return LB_OK;
     LB_API_END
@@ -801,6 +871,7 @@ int lb_get_populations(lb_handle *h, double *f) {
 int lb_set_populations(lb_handle *h, const double *f) {
     if (!h || !f) return LB_EINVAL;
     LB_API_BEGIN
+    h->bounce_pending = false;  // the given populations replace every slot a sweep reads
     with_storage(h->prm, [&](auto tag) { from_host_populations<typename decltype(tag)::type>(h, f); });
     return LB_OK;
     LB_API_END
@@ -911,6 +982,7 @@ int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
     const int64_t st = h->step;
     std::memcpy(o, &st, 8);
     o += 8;
+    settle_bounces(h);
     launch_fold_events(h);
     LB_HIP_CHECK(hipMemcpyAsync(o, h->dstate, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     o += sizeof(DevState);
@@ -1028,6 +1100,7 @@ int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
         if (rc != LB_OK) return rc;
     }
     LB_HIP_CHECK(hipMemcpyAsync(h->f[h->cur], pops, fsz, hipMemcpyHostToDevice, h->stream));
+    h->bounce_pending = false;  // a checkpoint holds every bounced population in its slot
     LB_HIP_CHECK(hipMemcpyAsync(h->dstate, dstate, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
     h->step = st;

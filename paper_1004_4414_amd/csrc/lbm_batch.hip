@@ -91,6 +91,10 @@ void build_shared(lb_batch *b, lbm::BatchLaunch &L) {
             const int c = h->cur ^ par;
             M.P = h->dp;
             M.D = h->dpart;
+            // a batch writes every bounced population from the link kernel
+            M.P.link_write = 1;
+            M.P.redirect = 0;
+            M.D.track_flags = 0;
             M.fin = h->f[c];
             M.fout = h->f[1 - c];
             M.rho = h->rho;
@@ -148,7 +152,11 @@ int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, vo
     std::vector<hipEvent_t> joins;
     hipEvent_t fork = nullptr;
     try {
-        for (lb_handle *h : b->m) BATCH_CHECK(hipStreamSynchronize(h->stream));
+        for (lb_handle *h : b->m) {
+            lbm::settle_bounces(h);  // the graph's first sweep pulls plainly
+            h->flags_tracked = false;
+            BATCH_CHECK(hipStreamSynchronize(h->stream));
+        }
         b->branch.resize(n);
         b->ev_member.resize(n);
         for (int i = 0; i < n; ++i) {
@@ -221,8 +229,11 @@ int lb_batch_step(lb_batch *b, int32_t nlaunches) {
         if (b->m[i]->cur != b->cur0[i])
             return bfail(b, LB_ESTATE, "member " + std::to_string(i) + " was stepped an odd number of times outside the batch");
     try {
-        // after whatever the members' own streams hold ...
+        // after whatever the members' own streams hold (bounced populations
+        // left by steps outside the batch written out first) ...
         for (int i = 0; i < n; ++i) {
+            lbm::settle_bounces(b->m[i]);
+            b->m[i]->flags_tracked = false;
             BATCH_CHECK(hipEventRecord(b->ev_member[i], b->m[i]->stream));
             BATCH_CHECK(hipStreamWaitEvent(b->stream, b->ev_member[i], 0));
         }

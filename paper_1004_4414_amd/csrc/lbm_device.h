@@ -138,6 +138,7 @@ struct Storage<double> {
         const NtD2 v = __builtin_nontemporal_load(reinterpret_cast<const NtD2 *>(a + k));
         return make_double2(v.x, v.y);
     }
+    __device__ static double rt(double x) { return x; }
     __device__ static void store(double *a, size_t k, double x, double y) { nt_store(a + k, NtD2{x, y}); }
     __device__ static void store_keep(double *a, size_t k, double x, double y) {
         *reinterpret_cast<double2 *>(a + k) = make_double2(x, y);
@@ -151,6 +152,7 @@ struct Storage<float> {
         const NtF2 v = __builtin_nontemporal_load(reinterpret_cast<const NtF2 *>(a + k));
         return make_float2(v.x, v.y);
     }
+    __device__ static float rt(float x) { return x; }
     __device__ static void store(float *a, size_t k, float x, float y) { nt_store(a + k, NtF2{x, y}); }
     __device__ static void store_keep(float *a, size_t k, float x, float y) {
         *reinterpret_cast<float2 *>(a + k) = make_float2(x, y);
@@ -170,6 +172,8 @@ struct Storage<__half> {
     __device__ static void store(__half *a, size_t k, float x, float y) {
         nt_store(a + k, pack16(__half_as_ushort(__float2half_rn(x)), __half_as_ushort(__float2half_rn(y))));
     }
+    // the value a store_keep followed by a load gives back
+    __device__ static float rt(float x) { return __half22float2(__floats2half2_rn(x, x)).x; }
     __device__ static void store_keep(__half *a, size_t k, float x, float y) {
         *reinterpret_cast<__half2 *>(a + k) = __floats2half2_rn(x, y);
     }
@@ -188,6 +192,7 @@ struct Storage<__hip_bfloat16> {
     __device__ static void store(__hip_bfloat16 *a, size_t k, float x, float y) {
         nt_store(a + k, pack16(__bfloat16_as_ushort(__float2bfloat16(x)), __bfloat16_as_ushort(__float2bfloat16(y))));
     }
+    __device__ static float rt(float x) { return __bfloat1622float2(__float22bfloat162_rn(make_float2(x, x))).x; }
     __device__ static void store_keep(__hip_bfloat16 *a, size_t k, float x, float y) {
         *reinterpret_cast<__hip_bfloat162 *>(a + k) = __float22bfloat162_rn(make_float2(x, y));
     }
@@ -235,6 +240,12 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv &f) {
 // virtual-fluid sites: the complement of the fluid neighbours), bits 29..30
 // hold the class
 enum : uint32_t { CLS_FLUID = 0, CLS_SHELL = 1, CLS_SOLID = 2, CLS_WALL = 3 };
+// bit 0 of a class word: the word was recomputed by the last map update (its
+// site or a neighbour changed owner); no direction uses bit 0
+constexpr uint32_t INFO_FLAG = 1u;
+// bit 19 of a fluid site's class word: its solid neighbours belong to more
+// than one sphere
+constexpr uint32_t INFO_MULTI = 1u << 19;
 constexpr int CLS_SHIFT = 29;
 __host__ __device__ inline uint32_t site_class(uint32_t info) { return (info >> CLS_SHIFT) & 3u; }
 
@@ -250,7 +261,11 @@ struct DevParams {
     double tau[2];
     double g, rho0, w_face, w_edge;
     int velocity_mode, eq_order, wall_axis, lub_mode;
-    int any_color, pad2;  // any sphere with a non-zero colour (Sec. IV)
+    int any_color;  // any sphere with a non-zero colour (Sec. IV)
+    // bounce-back of sphere links (set per launch): link_write = the link
+    // kernel writes every bounced population into the solid site's slot;
+    // otherwise redirect = this sweep forms them itself (sweep_bounce)
+    int link_write, redirect, pad2;
     double rho_init[2];
     double rho_ref[2];  // populations are stored as f_i - zeta_i rho_ref^c
     double psi_e[2];    // rho0 exp(-rho_ref^c / rho0): Psi(rho_ref + d) - Psi(rho_ref) = -psi_e expm1(-d/rho0)
@@ -315,6 +330,13 @@ struct DevParticles {
     int32_t *dirty;
     // running covered, uncovered and refill-fallback counts per sphere (np x 3)
     unsigned long long *evtot;
+    // the previous step's change lists (for clearing its class-word flags);
+    // track_flags: they are valid and the flags are cleared through them
+    int32_t *chg_prev_cnt, *chg_prev;
+    int track_flags;
+    // the sphere state the link kernel used (np x 3 each): the moving-wall
+    // term of a bounce formed later uses the same velocities and centre
+    double *Rl, *Ul, *Wl;
     int32_t *lbox;  // np x 6: box (lo, ext) of the last list build
     // lubrication contacts (index order) and the velocities after every other force
     int32_t *ncont, *cont;    // np, np x MAX_LUB_CONTACTS
@@ -598,15 +620,21 @@ __device__ __forceinline__ uint32_t compute_info_at(long long n, int x, int y, i
     const int32_t own = owner[n];
     if (own == OWN_WALL_LO || own == OWN_WALL_HI) return (uint32_t)CLS_WALL << CLS_SHIFT;
     uint32_t mask = 0;
-    bool any_fluid = false;
+    bool any_fluid = false, multi = false;
+    int32_t first = OWN_FLUID;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const long long m = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
         const int32_t o = owner[m];
-        if (o != OWN_FLUID) mask |= 1u << i;
-        else any_fluid = true;
+        if (o != OWN_FLUID) {
+            mask |= 1u << i;
+            multi = multi || (first != OWN_FLUID && o != first);
+            first = o;
+        } else {
+            any_fluid = true;
+        }
     }
-    if (own == OWN_FLUID) return mask;
+    if (own == OWN_FLUID) return multi ? mask | INFO_MULTI : mask;
     return any_fluid ? ((uint32_t)CLS_SHELL << CLS_SHIFT) | mask : (uint32_t)CLS_SOLID << CLS_SHIFT;
 }
 
@@ -631,6 +659,45 @@ __device__ __forceinline__ void solid_velocity(const DevParams &P, const DevPart
             rb[a] = 0.0;
         }
     }
+}
+
+// c_i . u for the link from fluid site (x, y, z) along c_i into a sphere with
+// centre R, velocity U and angular velocity W: u is the rigid velocity at x,
+// which has the same component along c_i as at the link midpoint x + c_i/2
+// (c_i . (W x c_i) = 0), Eq. (16)
+__device__ __forceinline__ void rigid_u(const DevParams &P, const double R[3], const double U[3], const double W[3],
+                                        int x, int y, int z, double u[3]) {
+    // no contraction: every kernel that forms a bounced pair rounds alike
+#pragma clang fp contract(off)
+    const double r[3] = {minimg(x - R[0], (double)P.nx), minimg(y - R[1], (double)P.ny),
+                         minimg(z - R[2], (double)P.nz)};
+    u[0] = U[0] + (W[1] * r[2] - W[2] * r[1]);
+    u[1] = U[1] + (W[2] * r[0] - W[0] * r[2]);
+    u[2] = U[2] + (W[0] * r[1] - W[1] * r[0]);
+}
+__device__ __forceinline__ double cu_dot(int i, const double u[3]) {
+#pragma clang fp contract(off)
+    return (double)cx(i) * u[0] + (double)cy(i) * u[1] + (double)cz(i) * u[2];
+}
+__device__ __forceinline__ double rigid_cu(const DevParams &P, const double R[3], const double U[3], const double W[3],
+                                           int x, int y, int z, int i) {
+    double u[3];
+    rigid_u(P, R, U, W, x, y, z, u);
+    return cu_dot(i, u);
+}
+
+// the bounced pair of a link, Eq. (16): f*_i(x) - w^c with w^c = 6 zeta_i
+// rho^c(x) (c_i . u_b), in stored (deviation) form: the reference parts of
+// directions i and opp(i) are equal.  dr: the density deviations of x.
+template <typename T>
+__device__ __forceinline__ void bounce_pair(const DevParams &P, double cub, int i, T raw0, T raw1, T dr0, T dr1,
+                                            T &b0, T &b1, T &w0, T &w1) {
+#pragma clang fp contract(off)
+    const T wz = (T)(6.0 * zeta(i) * cub);
+    w0 = wz * (dr0 + (T)P.rho_ref[0]);
+    w1 = wz * (dr1 + (T)P.rho_ref[1]);
+    b0 = raw0 - w0;
+    b1 = raw1 - w1;
 }
 
 // moments of one component from its stored values d_i = f_i - zeta_i rho_ref:

@@ -77,6 +77,11 @@ __global__ void k_owner_reset(DevParams P, int32_t *owner) {
     if (owner[n] >= 0) owner[n] = OWN_FLUID;
 }
 
+__global__ void k_clear_flags(uint32_t *info, long long n) {
+    const long long k = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (k < n) info[k] &= ~INFO_FLAG;
+}
+
 __global__ void k_fill_int(int32_t *p, long long n, int32_t v) {
     const long long k = (long long)blockIdx.x * BLOCK + threadIdx.x;
     if (k < n) p[k] = v;
@@ -89,26 +94,121 @@ __global__ void k_fill_int(int32_t *p, long long n, int32_t v) {
 // wavefront waits for the others of its block)
 // ---------------------------------------------------------------------------
 // ROWS: row-aligned addressing (nx a multiple of 64)
-template <typename S, bool ROWS, typename T = Cmp<S>>
-__device__ __forceinline__ void density_body(const DevParams &P, const S *__restrict__ f,
+// Bounced populations formed by the density sweep (sweep_bounce in
+// lbm_api.hip): the link kernel of the previous step left the solid sites'
+// slots of the links of fluid site n unwritten; the density sweep puts in
+// place of each such pull the pair formed from n's own slot (i, n), n's
+// density deviations of that step (rho_prev) and the sphere state of the
+// bounce, bitwise the value the link kernel would have written, and stores
+// it into the slot it has just pulled, for the collide sweep.  A flagged
+// class word marks a site whose links the map update wrote out.
+template <typename S, typename T>
+__device__ __forceinline__ bool sweep_bounces_here(const DevParams &P, uint32_t inf) {
+    return P.redirect && site_class(inf) == CLS_FLUID && !(inf & INFO_FLAG) && (inf & 0x7fffeu);
+}
+template <typename S, typename T>
+__device__ __forceinline__ void sweep_bounce_put(const DevParams &P, const DevParticles &D, S *f,
+                                                 const T *__restrict__ rho_prev, const int32_t *__restrict__ owner,
+                                                 unsigned n, int x, int y, int z, uint32_t inf, T (&fv)[2][Q]) {
+    const uint32_t bits = inf & 0x7fffeu;
+    // every load at once: the site's own slots of its link directions (other
+    // lanes of the instruction read slot 0), its densities of the bounce's
+    // step and the sphere of its first link (of every link when they belong
+    // to several spheres)
+    Pair<T> raw[Q - 1];
+    Unroll<Q - 1>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value + 1;
+        raw[i - 1] = load_pop(f, pidx(0, ((bits >> i) & 1u) ? i : 0, n));
+    });
+    const Pair<T> dr = load_pair(rho_prev, sidx(0, n));
+    const int i0 = __ffs(bits) - 1;
+    const int32_t q0 =
+        owner[site_of(wrapc(x + cx(i0), P.nx), wrapc(y + cy(i0), P.ny), wrapc(z + cz(i0), P.nz), P)];
+    double u[3] = {0.0, 0.0, 0.0};
+    if (q0 >= 0) {  // a sphere (lattices with spheres have no walls)
+        double R[3], U[3], W[3];
+        for (int a = 0; a < 3; ++a) {
+            R[a] = D.Rl[3 * q0 + a];
+            U[a] = D.Ul[3 * q0 + a];
+            W[a] = D.Wl[3 * q0 + a];
+        }
+        rigid_u(P, R, U, W, x, y, z, u);
+    }
+    const bool multi = (inf & INFO_MULTI) != 0u;
+    Unroll<Q - 1>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value + 1;
+        if ((bits >> i) & 1u) {
+            const long long sn = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
+            double ui[3] = {u[0], u[1], u[2]};
+            int32_t q = q0;
+            if (multi) {
+                q = owner[sn];
+                if (q >= 0 && q != q0) {
+                    double R[3], U[3], W[3];
+                    for (int a = 0; a < 3; ++a) {
+                        R[a] = D.Rl[3 * q + a];
+                        U[a] = D.Ul[3 * q + a];
+                        W[a] = D.Wl[3 * q + a];
+                    }
+                    rigid_u(P, R, U, W, x, y, z, ui);
+                }
+            }
+            if (q >= 0) {
+                T b0, b1, w0, w1;
+                bounce_pair<T>(P, cu_dot(i, ui), i, raw[i - 1].x, raw[i - 1].y, dr.x, dr.y, b0, b1, w0, w1);
+                fv[0][opp(i)] = Storage<S>::rt(b0);  // as stored and loaded back
+                fv[1][opp(i)] = Storage<S>::rt(b1);
+                // into the slot this thread has just pulled (its one reader),
+                // a line the caches still hold: the collide sweep pulls it
+                store_pop_keep(f, pidx(0, opp(i), (unsigned)sn), b0, b1);
+            }
+        }
+    });
+}
+
+template <typename S, bool ROWS, bool BOUNCE = false, typename T = Cmp<S>>
+__device__ __forceinline__ void density_body(const DevParams &P, const S *f,
                                              const uint32_t *__restrict__ info, T *__restrict__ rho,
-                                             T *__restrict__ psi, double *__restrict__ partial, const Grid &g) {
+                                             T *__restrict__ psi, double *__restrict__ partial, const Grid &g,
+                                             const DevParticles &D, const int32_t *__restrict__ owner,
+                                             const T *__restrict__ rho_prev) {
     double m[2] = {0.0, 0.0};
     unsigned n;
     int x, y, z;
     if (ROWS ? dense_site_rows(P, g, n, x, y, z) : dense_site(P, g, n, x, y, z)) {
         // the pulls are issued before the class word arrives (every address is
         // in the lattice); non-fluid sites discard the sum
-        T s0, s1;
-        if constexpr (ROWS) {
-            const RowView<S> rv(P, x, y, z);
-            pull_sum_rows(f, rv, s0, s1);
+        T s0 = 0, s1 = 0;  // in direction order, as every density sum of the step
+        uint32_t inf;
+        if constexpr (BOUNCE) {
+            T fv[2][Q];
+            if constexpr (ROWS) {
+                const RowView<S> rv(P, x, y, z);
+                pull_load_rows(f, rv, fv);
+            } else {
+                const NbrOffsets o(P, x, y, z);
+                pull_load(f, n, o, fv);
+            }
+            inf = __builtin_nontemporal_load(info + n);
+            if (sweep_bounces_here<S, T>(P, inf))
+                sweep_bounce_put<S, T>(P, D, const_cast<S *>(f), rho_prev, owner, n, x, y, z, inf, fv);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                s0 += fv[0][i];
+                s1 += fv[1][i];
+            }
         } else {
-            const NbrOffsets o(P, x, y, z);
-            pull_sum(f, n, o, s0, s1);
+            if constexpr (ROWS) {
+                const RowView<S> rv(P, x, y, z);
+                pull_sum_rows(f, rv, s0, s1);
+            } else {
+                const NbrOffsets o(P, x, y, z);
+                pull_sum(f, n, o, s0, s1);
+            }
+            // the class word is read once per sweep: streamed like the pulls
+            inf = __builtin_nontemporal_load(info + n);
         }
-        // the class word is read once per sweep: streamed like the pulls
-        const bool fluid = site_class(__builtin_nontemporal_load(info + n)) == CLS_FLUID;
+        const bool fluid = site_class(inf) == CLS_FLUID;
         const T irho0 = (T)P.inv_rho0;
         T dr[2] = {-(T)P.rho_ref[0], -(T)P.rho_ref[1]};
         if (fluid) {
@@ -133,11 +233,12 @@ __device__ __forceinline__ void density_body(const DevParams &P, const S *__rest
         }
     }
 }
-template <typename S, bool ROWS, typename T = Cmp<S>>
-__global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restrict__ f,
+template <typename S, bool ROWS, bool BOUNCE, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *f,
                                                    const uint32_t *__restrict__ info, T *__restrict__ rho,
-                                                   T *__restrict__ psi, double *__restrict__ partial) {
-    density_body<S, ROWS>(P, f, info, rho, psi, partial, own_grid());
+                                                   T *__restrict__ psi, double *__restrict__ partial, DevParticles D,
+                                                   const int32_t *__restrict__ owner, const T *__restrict__ rho_prev) {
+    density_body<S, ROWS, BOUNCE>(P, f, info, rho, psi, partial, own_grid(), D, owner, rho_prev);
 }
 
 // fixed-order sum of the per-block masses: M(t), baseline M(0), sentinel.
@@ -551,17 +652,33 @@ void launch_fill_int(lb_handle *h, int32_t *p, long long n, int32_t v) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
+void launch_clear_flags(lb_handle *h) {
+    k_clear_flags<<<nblocks(h->N), BLOCK, 0, h->stream>>>(h->info, h->N);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
 void launch_density(lb_handle *h, const void *f, bool partial_sums) {
     const unsigned nb = dense_blocks(h);
     double *part = partial_sums ? h->partial : nullptr;
     with_storage(h->prm, [&](auto tag) {
         using S = typename decltype(tag)::type;
         using T = Cmp<S>;
-        if (h->prm.nx % (int)VB == 0)
-            k_density<S, true><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho, (T *)h->psi, part);
-        else
-            k_density<S, false><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho, (T *)h->psi,
-                                                             part);
+        const bool rows = h->prm.nx % (int)VB == 0;
+        const T *rp = (const T *)h->rho_prev;
+        if (h->dp.redirect) {  // the variant that forms the pending bounced populations
+            if (rows)
+                k_density<S, true, true><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho,
+                                                                      (T *)h->psi, part, h->dpart, h->owner, rp);
+            else
+                k_density<S, false, true><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho,
+                                                                       (T *)h->psi, part, h->dpart, h->owner, rp);
+        } else if (rows) {
+            k_density<S, true, false><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho,
+                                                                   (T *)h->psi, part, h->dpart, h->owner, rp);
+        } else {
+            k_density<S, false, false><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho,
+                                                                    (T *)h->psi, part, h->dpart, h->owner, rp);
+        }
     });
     LB_HIP_CHECK(hipGetLastError());
 }
@@ -649,7 +766,8 @@ __global__ __launch_bounds__(BLOCK) void kb_density(BatchPlan B) {
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_DENSE, g)];
     if ((M.rows != 0) != ROWS) return;
-    density_body<S, ROWS>(M.P, (const S *)M.fin, M.info, (T *)M.rho, (T *)M.psi, M.partial, g);
+    density_body<S, ROWS, false>(M.P, (const S *)M.fin, M.info, (T *)M.rho, (T *)M.psi, M.partial, g, M.D, M.owner,
+                                 (const T *)nullptr);
 }
 __global__ __launch_bounds__(FIN_THREADS) void kb_finalize_mass(BatchPlan B) {
     const int m = (int)(blockIdx.x / FIN_BLOCKS);

@@ -29,6 +29,9 @@ struct lb_handle {
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
     void *rho = nullptr;  // T [2][N]: densities (fluid), virtual densities (shell)
+    // the densities of the previous step (swapped with rho at every step in
+    // which the sweep forms bounced populations: their wall term needs them)
+    void *rho_prev = nullptr;
     void *psi = nullptr;  // T [2][N]: Psi - Psi(rho_ref) of the two-pass variant
     void *fsc = nullptr;  // T [3][N]: Shan-Chen force on virtual-fluid sites
     uint32_t *info = nullptr;
@@ -53,6 +56,12 @@ struct lb_handle {
     int n_fused_blocks = 0;
     long long step = 0;
     bool in_batch = false;      // a batch graph holds this lattice's pointers
+    // bounce-back of sphere links (see sweep_bounce in lbm_api.hip):
+    // bounce_pending = the last step left bounced populations for the next
+    // sweep to form; flags_tracked = the class-word flags are exactly those of
+    // the last map update and chg_prev holds its change lists
+    bool bounce_pending = false;
+    bool flags_tracked = false;
     std::vector<void *> owned;  // every device allocation, freed by lb_destroy
 
     // event timing (measurement only): per kind, pairs of recorded events
@@ -67,6 +76,10 @@ namespace lbm {
 
 void *dev_alloc(lb_handle *h, size_t bytes);
 void one_step(lb_handle *h);  // enqueue one time step on h->stream
+// write out every bounced population the last step left to the next sweep
+// (before any other reader of the stored populations)
+void settle_bounces(lb_handle *h);
+void launch_clear_flags(lb_handle *h);  // class-word flags of the map update, all sites
 void dev_free(lb_handle *h, void *p);
 
 // fluid (lbm_fluid.hip)
@@ -120,6 +133,8 @@ void launch_forces_total(lb_handle *h);
 void launch_integrate(lb_handle *h);
 void launch_map_mark(lb_handle *h);  // full classification (marks in stage[])
 void launch_map_flip(lb_handle *h);  // per-step update: changed sites and events
+void launch_map_fixup(lb_handle *h, void *fout);   // links next to this step's map changes, written out
+void launch_materialize(lb_handle *h, void *f);    // every pending bounced population written out
 void launch_cover_refill(lb_handle *h, void *fout);
 void launch_map_commit(lb_handle *h, bool full);
 void launch_map_info(lb_handle *h);

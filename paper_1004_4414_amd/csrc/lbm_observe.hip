@@ -202,6 +202,7 @@ int lb_domain_size(lb_handle *h, double L_out[3]) {
             return LB_EINVAL;
         }
     try {
+        settle_bounces(h);
         launch_phi(h);
         const unsigned nb = (unsigned)((h->N + BLOCK - 1) / BLOCK);
         std::vector<double> part(2 * (size_t)nb);
@@ -249,6 +250,7 @@ int lb_order_parameter_profile(lb_handle *h, int32_t axis, double *out) {
     if (!h || !out || axis < 0 || axis > 2) return LB_EINVAL;
     const int L[3] = {h->prm.nx, h->prm.ny, h->prm.nz};
     try {
+        settle_bounces(h);
         launch_phi(h);
         double *d = (double *)dev_alloc(h, sizeof(double) * (size_t)L[axis]);
         k_phi_profile<<<(unsigned)L[axis], BLOCK, 0, h->stream>>>(h->dp, h->phi, axis, d);
@@ -285,6 +287,7 @@ int lb_order_parameter_profile_noalloc(lb_handle *h, int32_t axis, double *out) 
     }
     try {
         if (cur != h->device) LB_HIP_CHECK(hipSetDevice(h->device));
+        settle_bounces(h);
         double *d = scratch_address(h->device);
         with_storage(h->prm, [&](auto tag) {
             using S = typename decltype(tag)::type;

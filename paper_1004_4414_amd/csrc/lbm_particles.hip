@@ -223,8 +223,12 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
     load3(D.R, p, R);
     load3(D.U, p, U);
     load3(D.W, p, W);
+    if (t < 3) {  // the state of the bounce, for bounced populations formed later
+        D.Rl[3 * p + t] = R[t];
+        D.Ul[3 * p + t] = U[t];
+        D.Wl[3 * p + t] = W[t];
+    }
     const double L[3] = {(double)P.nx, (double)P.ny, (double)P.nz};
-    const T ref0 = (T)P.rho_ref[0], ref1 = (T)P.rho_ref[1];
     const int ns = min(D.shell_cnt[p], D.shell_cap[p]), soff = D.shell_off[p];
     for (int c0 = 0; c0 < ns; c0 += BLOCK) {
         // ---- one virtual-fluid site per thread: Shan-Chen force, link mask
@@ -321,12 +325,13 @@ __device__ __forceinline__ void particle_fluid_force_body(DevParams P, DevPartic
                 // lever arm at the link midpoint s - c_i/2 = s + c_j/2
                 const double rb[3] = {minimg(x + 0.5 * cx(j) - R[0], L[0]), minimg(y + 0.5 * cy(j) - R[1], L[1]),
                                       minimg(z + 0.5 * cz(j) - R[2], L[2])};
-                const double ub[3] = {U[0] + (W[1] * rb[2] - W[2] * rb[1]), U[1] + (W[2] * rb[0] - W[0] * rb[2]),
-                                      U[2] + (W[0] * rb[1] - W[1] * rb[0])};
-                const double cub = (double)cx(i) * ub[0] + (double)cy(i) * ub[1] + (double)cz(i) * ub[2];
-                const T wz = (T)(6.0 * zeta(i) * cub);
-                const T w0 = wz * (r0[u] + ref0), w1 = wz * (r1[u] + ref1);
-                store_pop_keep(fout, pidx(0, j, ss), raw0[u] - w0, raw1[u] - w1);
+                const double cub = rigid_cu(P, R, U, W, wrapc(x + cx(j), P.nx), wrapc(y + cy(j), P.ny),
+                                            wrapc(z + cz(j), P.nz), i);
+                T b0, b1, w0, w1;
+                bounce_pair<T>(P, cub, i, raw0[u], raw1[u], r0[u], r1[u], b0, b1, w0, w1);
+                // the bounced pair goes where x reads direction j at the next
+                // step, unless that sweep forms it itself
+                if (P.link_write) store_pop_keep(fout, pidx(0, j, ss), b0, b1);
                 const double sum = (2.0 * ((double)raw0[u] + zeta(i) * P.rho_ref[0]) - (double)w0) +
                                    (2.0 * ((double)raw1[u] + zeta(i) * P.rho_ref[1]) - (double)w1);
                 const double dp[3] = {cx(i) * sum, cy(i) * sum, cz(i) * sum};
@@ -833,12 +838,22 @@ __global__ __launch_bounds__(BLOCK) void k_map_mark(DevParams P, DevParticles D,
 // one of p's covered sites, a site of p that no sphere takes one of its
 // uncovered sites (Eqs. (18)-(20)).  Lists are in scan order.
 __device__ __forceinline__ void map_flip_body(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                              int32_t *__restrict__ stage, DevState *st, const Grid &g) {
+                                              int32_t *__restrict__ stage, uint32_t *__restrict__ info, DevState *st,
+                                              const Grid &g) {
     const int p = g.bid;
     {  // the blocks also clear the coarse dirty cells of the previous step, a slice each
         const int ncell = D.cgx * D.cgy * D.cgz;
         const int per = (ncell + (int)g.nb - 1) / (int)g.nb;
         for (int c = p * per + threadIdx.x; c < min(ncell, (p + 1) * per); c += BLOCK) D.dirty[c] = 0;
+    }
+    if (D.track_flags) {  // the flags of the words the previous update recomputed
+        const int off = 2 * D.ev_off[p], n = min(D.chg_prev_cnt[p], 2 * D.ev_cap[p]);
+        for (int k = threadIdx.x; k < n * Q; k += BLOCK) {
+            const int e = k / Q, i = k - e * Q;
+            int x, y, z;
+            site_xyz(D.chg_prev[off + e], P, x, y, z);
+            info[site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P)] &= ~INFO_FLAG;
+        }
     }
     long long cn[3], co[3];
     for (int a = 0; a < 3; ++a) {
@@ -965,8 +980,88 @@ __device__ __forceinline__ void map_flip_body(DevParams P, DevParticles D, const
 }
 
 __global__ __launch_bounds__(BLOCK) void k_map_flip(DevParams P, DevParticles D, const int32_t *__restrict__ owner,
-                                                    int32_t *__restrict__ stage, DevState *st) {
-    map_flip_body(P, D, owner, stage, st, own_grid());
+                                                    int32_t *__restrict__ stage, uint32_t *__restrict__ info,
+                                                    DevState *st) {
+    map_flip_body(P, D, owner, stage, info, st, own_grid());
+}
+
+// The bounced pairs of every sphere link of fluid site n (class word inf),
+// written into the solid sites' slots of f as the link kernel writes them:
+// from f*_i(n) in slot (i, n), the density deviations of n in rho, and the
+// sphere state of the bounce.
+template <typename S>
+__device__ __forceinline__ void write_site_bounces(const DevParams &P, const DevParticles &D, S *__restrict__ f,
+                                                   const Cmp<S> *__restrict__ rho, const int32_t *__restrict__ owner,
+                                                   long long n, int x, int y, int z, uint32_t inf) {
+    using T = Cmp<S>;
+    const Pair<T> dr = load_pair(rho, sidx(0, (unsigned)n));
+    uint32_t bits = inf & 0x7fffeu;
+    while (bits) {
+        const int i = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const long long s = site_of(wrapc(x + cx(i), P.nx), wrapc(y + cy(i), P.ny), wrapc(z + cz(i), P.nz), P);
+        const int32_t q = owner[s];
+        if (q < 0) continue;  // walls: the wall kernel writes their links
+        double R[3], U[3], W[3];
+        load3(D.Rl, q, R);
+        load3(D.Ul, q, U);
+        load3(D.Wl, q, W);
+        const Pair<T> raw = load_pop(f, pidx(0, i, (unsigned)n));
+        T b0, b1, w0, w1;
+        bounce_pair<T>(P, rigid_cu(P, R, U, W, x, y, z, i), i, raw.x, raw.y, dr.x, dr.y, b0, b1, w0, w1);
+        store_pop_keep(f, pidx(0, opp(i), (unsigned)s), b0, b1);
+    }
+}
+
+// When the next sweep forms the bounced populations itself, the links of
+// the fluid sites that a map change touches (a changed site and its 18
+// neighbours, fluid on the map of the bounce) are written out here instead,
+// before covering and refilling read or overwrite their slots; the next
+// sweep finds these sites flagged in their class words and pulls plainly.
+template <typename S>
+__device__ __forceinline__ void map_fixup_body(DevParams P, DevParticles D, S *__restrict__ f,
+                                               const Cmp<S> *__restrict__ rho, const int32_t *__restrict__ owner,
+                                               const uint32_t *__restrict__ info, const Grid &g) {
+    const int p = g.bid;
+    const int off = 2 * D.ev_off[p], n = min(D.chg_cnt[p], 2 * D.ev_cap[p]);
+    for (int k = threadIdx.x; k < n * Q; k += BLOCK) {
+        const int e = k / Q, i = k - e * Q;
+        int x, y, z;
+        site_xyz(D.chg[off + e], P, x, y, z);
+        x = wrapc(x + cx(i), P.nx);
+        y = wrapc(y + cy(i), P.ny);
+        z = wrapc(z + cz(i), P.nz);
+        const long long m = site_of(x, y, z, P);
+        if (owner[m] != OWN_FLUID) continue;
+        const uint32_t inf = info[m];
+        if (inf & 0x7fffeu) write_site_bounces<S>(P, D, f, rho, owner, m, x, y, z, inf);
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void k_map_fixup(DevParams P, DevParticles D, S *__restrict__ f,
+                                                     const Cmp<S> *__restrict__ rho,
+                                                     const int32_t *__restrict__ owner,
+                                                     const uint32_t *__restrict__ info) {
+    map_fixup_body<S>(P, D, f, rho, owner, info, own_grid());
+}
+
+// Every pending bounced population written out (before a plain reader of
+// the populations: observables, fields, state, a batch): the fluid sites
+// with links whose class word is not flagged (the flagged ones were written
+// by the fix-up).
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void k_materialize(DevParams P, DevParticles D, S *__restrict__ f,
+                                                       const Cmp<S> *__restrict__ rho,
+                                                       const int32_t *__restrict__ owner,
+                                                       const uint32_t *__restrict__ info) {
+    const long long n = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= P.N) return;
+    const uint32_t inf = info[n];
+    if (site_class(inf) != CLS_FLUID || (inf & INFO_FLAG) || !(inf & 0x7fffeu)) return;
+    int x, y, z;
+    site_xyz(n, P, x, y, z);
+    write_site_bounces<S>(P, D, f, rho, owner, n, x, y, z, inf);
 }
 
 // Covering, Eq. (18): the fluid of a covered site is removed and its momentum
@@ -1189,7 +1284,7 @@ __device__ __forceinline__ void map_info_body(DevParams P, DevParticles D, const
         site_xyz(s, P, x, y, z);
         const int xx = wrapc(x + cx(i), P.nx), yy = wrapc(y + cy(i), P.ny), zz = wrapc(z + cz(i), P.nz);
         const long long m = site_of(xx, yy, zz, P);
-        info[m] = compute_info_at(m, xx, yy, zz, P, owner);
+        info[m] = compute_info_at(m, xx, yy, zz, P, owner) | INFO_FLAG;
         D.dirty[cell_of(D, xx, yy, zz)] = 1;
     }
     for (int k = threadIdx.x; k < n; k += BLOCK) stage[D.chg[off + k]] = STAGE_NONE;
@@ -1394,7 +1489,29 @@ void launch_map_mark(lb_handle *h) {
 
 void launch_map_flip(lb_handle *h) {
     if (!h->np) return;
-    k_map_flip<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage, h->dstate);
+    k_map_flip<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->stage, h->info, h->dstate);
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_map_fixup(lb_handle *h, void *fout) {
+    if (!h->np) return;
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        using T = Cmp<S>;
+        k_map_fixup<S><<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, (S *)fout, (const T *)h->rho, h->owner,
+                                                       h->info);
+    });
+    LB_HIP_CHECK(hipGetLastError());
+}
+
+void launch_materialize(lb_handle *h, void *f) {
+    if (!h->np) return;
+    with_storage(h->prm, [&](auto tag) {
+        using S = typename decltype(tag)::type;
+        using T = Cmp<S>;
+        k_materialize<S><<<(unsigned)((h->N + BLOCK - 1) / BLOCK), BLOCK, 0, h->stream>>>(h->dp, h->dpart, (S *)f, (const T *)h->rho, h->owner,
+                                                              h->info);
+    });
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -1478,7 +1595,7 @@ __global__ void kb_integrate(BatchPlan B) {
 __global__ __launch_bounds__(BLOCK) void kb_map_flip(BatchPlan B) {
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
-    map_flip_body(M.P, M.D, M.owner, M.stage, M.dstate, g);
+    map_flip_body(M.P, M.D, M.owner, M.stage, M.info, M.dstate, g);
 }
 template <typename S>
 __global__ __launch_bounds__(BLOCK) void kb_cover_refill(BatchPlan B) {

@@ -53,6 +53,7 @@ class Params(ctypes.Structure):
         ("lub_hc", ctypes.c_double), ("lub_hmin", ctypes.c_double),
         ("kernel", ctypes.c_int32), ("tile", ctypes.c_int32 * 3),
         ("lub_mode", ctypes.c_int32),
+        ("link_writes", ctypes.c_int32),
     ]
 
 
@@ -171,6 +172,7 @@ def make_params(p, precision="fp32", kernel="auto", tile=(0, 0, 0)):
     s.c0_mass_corr, s.k_hertz = p["c0_mass_corr"], p["k_hertz"]
     s.lub_hc, s.lub_hmin = p["lub_hc"], p["lub_hmin"]
     s.lub_mode = int(p.get("lub_mode", 1))
+    s.link_writes = int(p.get("link_writes", 1))
     s.kernel = KERNELS[kernel]
     for a in range(3):
         s.tile[a] = int(tile[a])
