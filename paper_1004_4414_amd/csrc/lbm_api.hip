@@ -105,6 +105,7 @@ void set_dev_params(lb_handle *h) {
     d.lub_mode = p.lub_mode;
     d.link_write = 1;  // set per step by the step's launcher
     d.redirect = 0;
+    d.multi_bits = h->prm.link_writes == 0;  // the sweep-side bounce reads INFO_MULTI
     d.any_color = 0;
     for (double c : h->h_color) d.any_color |= c != 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -165,7 +166,8 @@ size_t fluid_bytes(const lb_params *p) {
     size_t b = 0;
     const size_t Np = padded_sites(N);
     b += 2 * (size_t)(2 * Q) * Np * ts;  // two population buffers
-    b += 10 * Np * tc;                   // densities of two steps, Psi, shell force (padded to 4)
+    b += 8 * Np * tc;                    // densities, Psi, shell force (padded to 4)
+    if (p->link_writes == 0) b += 2 * Np * tc;  // densities of the previous step
     b += 3 * (size_t)N * 4;             // info, owner, stage
     b += 8 * (size_t)nblk(N) * 8 + 4096;
     return b;
@@ -494,7 +496,6 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         h->f[0] = dev_alloc(h, fsz);
         h->f[1] = dev_alloc(h, fsz);
         h->rho = dev_alloc(h, (size_t)2 * Np * h->csize);
-        h->rho_prev = dev_alloc(h, (size_t)2 * Np * h->csize);
         h->psi = dev_alloc(h, (size_t)2 * Np * h->csize);
         h->fsc = dev_alloc(h, (size_t)4 * Np * h->csize);
         h->info = (uint32_t *)dev_alloc(h, (size_t)h->N * 4);
@@ -505,6 +506,8 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
                                  ((p->ny + h->fused_ty - 1) / h->fused_ty) * ((p->nz + h->fused_tz - 1) / h->fused_tz);
         h->partial = (double *)dev_alloc(h, (size_t)std::max(8LL * h->n_partial, 2 * nfused + 16) * 8);
         h->dstate = (DevState *)dev_alloc(h, sizeof(DevState));
+        // the bounce's densities for the sweep-side bounce
+        if (p->link_writes == 0) h->rho_prev = dev_alloc(h, (size_t)2 * Np * h->csize);
         LB_HIP_CHECK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
         LB_HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         LB_HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));

@@ -264,8 +264,9 @@ struct DevParams {
     int any_color;  // any sphere with a non-zero colour (Sec. IV)
     // bounce-back of sphere links (set per launch): link_write = the link
     // kernel writes every bounced population into the solid site's slot;
-    // otherwise redirect = this sweep forms them itself (sweep_bounce)
-    int link_write, redirect, pad2;
+    // otherwise redirect = this sweep forms them itself (sweep_bounce);
+    // multi_bits: class words carry INFO_MULTI (lattices using that option)
+    int link_write, redirect, multi_bits;
     double rho_init[2];
     double rho_ref[2];  // populations are stored as f_i - zeta_i rho_ref^c
     double psi_e[2];    // rho0 exp(-rho_ref^c / rho0): Psi(rho_ref + d) - Psi(rho_ref) = -psi_e expm1(-d/rho0)
@@ -607,16 +608,11 @@ __device__ __forceinline__ long long site_of(int x, int y, int z, const DevParam
 }
 
 // the site's class word from the owner map: bounce-back directions of a
-// fluid site, or shell / interior / wall for the others
-__device__ __forceinline__ uint32_t compute_info_at(long long n, int x, int y, int z, const DevParams &P,
-                                                    const int32_t *__restrict__ owner);
-__device__ __forceinline__ uint32_t compute_info(long long n, const DevParams &P, const int32_t *__restrict__ owner) {
-    int x, y, z;
-    site_xyz(n, P, x, y, z);
-    return compute_info_at(n, x, y, z, P, owner);
-}
-__device__ __forceinline__ uint32_t compute_info_at(long long n, int x, int y, int z, const DevParams &P,
-                                                    const int32_t *__restrict__ owner) {
+// fluid site, or shell / interior / wall for the others; MULTI: with the
+// INFO_MULTI bit
+template <bool MULTI>
+__device__ __forceinline__ uint32_t class_word_at(long long n, int x, int y, int z, const DevParams &P,
+                                                  const int32_t *__restrict__ owner) {
     const int32_t own = owner[n];
     if (own == OWN_WALL_LO || own == OWN_WALL_HI) return (uint32_t)CLS_WALL << CLS_SHIFT;
     uint32_t mask = 0;
@@ -628,14 +624,25 @@ __device__ __forceinline__ uint32_t compute_info_at(long long n, int x, int y, i
         const int32_t o = owner[m];
         if (o != OWN_FLUID) {
             mask |= 1u << i;
-            multi = multi || (first != OWN_FLUID && o != first);
-            first = o;
+            if constexpr (MULTI) {
+                multi = multi || (first != OWN_FLUID && o != first);
+                first = o;
+            }
         } else {
             any_fluid = true;
         }
     }
     if (own == OWN_FLUID) return multi ? mask | INFO_MULTI : mask;
     return any_fluid ? ((uint32_t)CLS_SHELL << CLS_SHIFT) | mask : (uint32_t)CLS_SOLID << CLS_SHIFT;
+}
+__device__ __forceinline__ uint32_t compute_info_at(long long n, int x, int y, int z, const DevParams &P,
+                                                    const int32_t *__restrict__ owner) {
+    return P.multi_bits ? class_word_at<true>(n, x, y, z, P, owner) : class_word_at<false>(n, x, y, z, P, owner);
+}
+__device__ __forceinline__ uint32_t compute_info(long long n, const DevParams &P, const int32_t *__restrict__ owner) {
+    int x, y, z;
+    site_xyz(n, P, x, y, z);
+    return compute_info_at(n, x, y, z, P, owner);
 }
 
 // velocity of the solid at the midpoint of the link from fluid site x along

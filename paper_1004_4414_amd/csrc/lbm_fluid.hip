@@ -166,8 +166,11 @@ __device__ __forceinline__ void sweep_bounce_put(const DevParams &P, const DevPa
     });
 }
 
+// (the populations are not restrict-qualified where the sweep stores into them)
+template <typename S, bool BOUNCE>
+using DensityPops = typename std::conditional<BOUNCE, const S *, const S *__restrict__>::type;
 template <typename S, bool ROWS, bool BOUNCE = false, typename T = Cmp<S>>
-__device__ __forceinline__ void density_body(const DevParams &P, const S *f,
+__device__ __forceinline__ void density_body(const DevParams &P, DensityPops<S, BOUNCE> f,
                                              const uint32_t *__restrict__ info, T *__restrict__ rho,
                                              T *__restrict__ psi, double *__restrict__ partial, const Grid &g,
                                              const DevParticles &D, const int32_t *__restrict__ owner,
@@ -233,12 +236,21 @@ __device__ __forceinline__ void density_body(const DevParams &P, const S *f,
         }
     }
 }
-template <typename S, bool ROWS, bool BOUNCE, typename T = Cmp<S>>
-__global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *f,
+template <typename S, bool ROWS, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_density(DevParams P, const S *__restrict__ f,
                                                    const uint32_t *__restrict__ info, T *__restrict__ rho,
-                                                   T *__restrict__ psi, double *__restrict__ partial, DevParticles D,
-                                                   const int32_t *__restrict__ owner, const T *__restrict__ rho_prev) {
-    density_body<S, ROWS, BOUNCE>(P, f, info, rho, psi, partial, own_grid(), D, owner, rho_prev);
+                                                   T *__restrict__ psi, double *__restrict__ partial) {
+    density_body<S, ROWS, false>(P, f, info, rho, psi, partial, own_grid(), DevParticles{}, nullptr,
+                                 (const T *)nullptr);
+}
+// the variant that forms the pending bounced populations (it stores into f)
+template <typename S, bool ROWS, typename T = Cmp<S>>
+__global__ __launch_bounds__(BLOCK) void k_density_bounce(DevParams P, S *f, const uint32_t *__restrict__ info,
+                                                          T *__restrict__ rho, T *__restrict__ psi,
+                                                          double *__restrict__ partial, DevParticles D,
+                                                          const int32_t *__restrict__ owner,
+                                                          const T *__restrict__ rho_prev) {
+    density_body<S, ROWS, true>(P, f, info, rho, psi, partial, own_grid(), D, owner, rho_prev);
 }
 
 // fixed-order sum of the per-block masses: M(t), baseline M(0), sentinel.
@@ -664,20 +676,20 @@ void launch_density(lb_handle *h, const void *f, bool partial_sums) {
         using S = typename decltype(tag)::type;
         using T = Cmp<S>;
         const bool rows = h->prm.nx % (int)VB == 0;
-        const T *rp = (const T *)h->rho_prev;
-        if (h->dp.redirect) {  // the variant that forms the pending bounced populations
+        if (h->dp.redirect) {
+            const T *rp = (const T *)h->rho_prev;
             if (rows)
-                k_density<S, true, true><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho,
-                                                                      (T *)h->psi, part, h->dpart, h->owner, rp);
-            else
-                k_density<S, false, true><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho,
+                k_density_bounce<S, true><<<nb, BLOCK, 0, h->stream>>>(h->dp, (S *)f, h->info, (T *)h->rho,
                                                                        (T *)h->psi, part, h->dpart, h->owner, rp);
+            else
+                k_density_bounce<S, false><<<nb, BLOCK, 0, h->stream>>>(h->dp, (S *)f, h->info, (T *)h->rho,
+                                                                        (T *)h->psi, part, h->dpart, h->owner, rp);
         } else if (rows) {
-            k_density<S, true, false><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho,
-                                                                   (T *)h->psi, part, h->dpart, h->owner, rp);
+            k_density<S, true><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho, (T *)h->psi,
+                                                            part);
         } else {
-            k_density<S, false, false><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho,
-                                                                    (T *)h->psi, part, h->dpart, h->owner, rp);
+            k_density<S, false><<<nb, BLOCK, 0, h->stream>>>(h->dp, (const S *)f, h->info, (T *)h->rho, (T *)h->psi,
+                                                             part);
         }
     });
     LB_HIP_CHECK(hipGetLastError());
