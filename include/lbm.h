@@ -319,9 +319,10 @@ int lb_order_parameter_profile_noalloc(lb_handle *h, int32_t axis, double *out);
  * Batches: many lattices advanced by one graph launch.
  *
  * lb_batch_create captures steps_per_launch (even, >= 2) time steps of every
- * member into one HIP graph: members with the same precision and collision
- * model, the two-pass sweep and no walls as one launch per stage over all of
- * them, others each on a branch of its own; lb_batch_step replays it
+ * member into one HIP graph: members below 2^21 sites with the same
+ * precision and collision model, the two-pass sweep and no walls (at least
+ * two of them) as one launch per stage over all of them, the others each with
+ * its own launches on a branch of its own; lb_batch_step replays it
  * nlaunches times on `stream` (ordered after the members' pending work, and
  * the members' later calls are ordered after it).  A member stepped an odd
  * number of times outside the batch makes lb_batch_step fail (LB_ESTATE).  The kernels are exactly those

@@ -2,14 +2,16 @@
 // kernel autotuner.
 //
 // A batch captures `k` time steps of every member into one HIP graph; a
-// replay advances every member by k steps with one launch.  Members that share
-// precision and collision model, use the two-pass sweep and have no walls are
-// captured as shared launches: every stage of a step is one kernel launch over
-// all members, each block finding its member from block maps in device memory
-// and running the same body as the single-lattice kernel.  Other batches
-// capture each member's own launches on a stream of its own, forked from and
-// joined into the capture stream (independent branches).  Either way a
-// member's result is bitwise the same alone and in a batch.
+// replay advances every member by k steps with one launch.  Small members
+// that share precision and collision model, use the two-pass sweep and have
+// no walls are captured as shared launches: every stage of a step is one
+// kernel launch over all of them, each block finding its member from block
+// maps in device memory and running the same body as the single-lattice
+// kernel.  The other members (large ones, a lone one of the shared kind,
+// those of another kind) are captured with their own launches, each on a
+// stream of its own forked from and joined into the capture stream
+// (independent branches beside the shared launches).  Either way a member's
+// result is bitwise the same alone and in a batch.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -60,27 +62,39 @@ void release(lb_batch *b) {
 
 #define BATCH_CHECK(expr) LB_HIP_CHECK(expr)
 
-// Members that share precision and collision model, use the two-pass sweep
-// and have no walls are advanced by shared launches: the member tables (both
-// step parities) and the block maps go to the device once, and every stage of
-// a step is one launch over all members.
-bool shared_launches_fit(const std::vector<lb_handle *> &m) {
-    for (lb_handle *h : m) {
-        if (h->kernel != LB_KERNEL_TWOPASS || h->prm.wall_axis >= 0) return false;
-        if (h->prm.precision != m[0]->prm.precision || h->prm.velocity_mode != m[0]->prm.velocity_mode ||
-            h->prm.eq_order != m[0]->prm.eq_order)
-            return false;
+// Small members that share precision and collision model, use the two-pass
+// sweep and have no walls are advanced by shared launches: the member tables
+// (both step parities) and the block maps go to the device once, and every
+// stage of a step is one launch over all of them.  A member of SHARED_MAX_SITES
+// sites or more fills the GPU with its own launches, which take their
+// parameters from the kernel arguments: it keeps them, on a branch, as does
+// a lone member of the shared kind.
+constexpr long long SHARED_MAX_SITES = 1LL << 21;
+
+std::vector<int> shared_members(const std::vector<lb_handle *> &m) {
+    std::vector<int> sh;
+    for (int i = 0; i < (int)m.size(); ++i) {
+        const lb_handle *h = m[i];
+        if (h->kernel != LB_KERNEL_TWOPASS || h->prm.wall_axis >= 0 || h->N >= SHARED_MAX_SITES) continue;
+        if (!sh.empty()) {
+            const lb_handle *h0 = m[sh[0]];
+            if (h->prm.precision != h0->prm.precision || h->prm.velocity_mode != h0->prm.velocity_mode ||
+                h->prm.eq_order != h0->prm.eq_order)
+                continue;
+        }
+        sh.push_back(i);
     }
-    return true;
+    if (sh.size() < 2) sh.clear();
+    return sh;
 }
 
-void build_shared(lb_batch *b, lbm::BatchLaunch &L) {
+void build_shared(lb_batch *b, const std::vector<lb_handle *> &ms, lbm::BatchLaunch &L) {
     using namespace lbm;
-    const int nm = (int)b->m.size();
+    const int nm = (int)ms.size();
     std::vector<BatchMember> tab(2 * (size_t)nm);
     std::vector<int32_t> start((size_t)BM_COUNT * (nm + 1), 0);
     for (int i = 0; i < nm; ++i) {
-        lb_handle *h = b->m[i];
+        lb_handle *h = ms[i];
         const bool cells = h->dpart.pgx > 0 && h->np >= PAIR_CELLS_MIN_SPHERES;
         const int np = h->np, np256 = (h->np + BLOCK - 1) / BLOCK;
         const int cnt[BM_COUNT] = {(int)((h->N + BLOCK - 1) / BLOCK), np, np256, cells ? np : 0,
@@ -120,10 +134,10 @@ void build_shared(lb_batch *b, lbm::BatchLaunch &L) {
     L.nm = nm;
     L.any_rows = L.any_flat = 0;
     for (int i = 0; i < nm; ++i) {
-        if (b->m[i]->prm.nx % (int)VB == 0) L.any_rows = 1;
+        if (ms[i]->prm.nx % (int)VB == 0) L.any_rows = 1;
         else L.any_flat = 1;
     }
-    L.prm = b->m[0]->prm;
+    L.prm = ms[0]->prm;
 }
 
 }  // namespace
@@ -168,29 +182,38 @@ int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, vo
         BATCH_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
         joins.resize(n, nullptr);
         for (int i = 0; i < n; ++i) BATCH_CHECK(hipEventCreateWithFlags(&joins[i], hipEventDisableTiming));
-        b->shared = shared_launches_fit(b->m);
+        const std::vector<int> sh = shared_members(b->m);
+        std::vector<char> in_shared(n, 0);
+        std::vector<lb_handle *> shm;
+        for (int i : sh) {
+            in_shared[i] = 1;
+            shm.push_back(b->m[i]);
+        }
+        b->shared = !shm.empty();
         lbm::BatchLaunch L{};
-        if (b->shared) build_shared(b, L);
+        if (b->shared) build_shared(b, shm, L);
         BATCH_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        if (b->shared) {
+        BATCH_CHECK(hipEventRecord(fork, cs));
+        // the branches of the members with launches of their own ...
+        for (int i = 0; i < n; ++i) {
+            if (in_shared[i]) continue;
+            lb_handle *h = b->m[i];
+            BATCH_CHECK(hipStreamWaitEvent(b->branch[i], fork, 0));
+            saved[i] = h->stream;
+            h->stream = b->branch[i];
+            for (int s = 0; s < b->k; ++s) lbm::one_step(h);
+            h->stream = saved[i];
+            h->step -= b->k;  // the capture only recorded the steps
+            BATCH_CHECK(hipEventRecord(joins[i], b->branch[i]));
+        }
+        // ... beside the shared launches of the others
+        if (b->shared)
             for (int s = 0; s < b->k; ++s) {
                 lbm::launch_batch_fluid(L, s & 1, cs);
                 lbm::launch_batch_particles(L, s & 1, cs);
             }
-        } else {
-            BATCH_CHECK(hipEventRecord(fork, cs));
-            for (int i = 0; i < n; ++i) {
-                lb_handle *h = b->m[i];
-                BATCH_CHECK(hipStreamWaitEvent(b->branch[i], fork, 0));
-                saved[i] = h->stream;
-                h->stream = b->branch[i];
-                for (int s = 0; s < b->k; ++s) lbm::one_step(h);
-                h->stream = saved[i];
-                h->step -= b->k;  // the capture only recorded the steps
-                BATCH_CHECK(hipEventRecord(joins[i], b->branch[i]));
-                BATCH_CHECK(hipStreamWaitEvent(cs, joins[i], 0));
-            }
-        }
+        for (int i = 0; i < n; ++i)
+            if (!in_shared[i]) BATCH_CHECK(hipStreamWaitEvent(cs, joins[i], 0));
         BATCH_CHECK(hipStreamEndCapture(cs, &b->graph));
         BATCH_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     } catch (const lbm::HipFailure &e) {

@@ -135,6 +135,33 @@ def test_shared_launch_batch_with_cell_list_member():
     batch.close()
 
 
+def test_large_member_keeps_its_own_launches_beside_shared_ones():
+    """A member of 2^21 sites (128^3) is captured with its own launches on a
+    branch beside the shared launches of two small members; a lone small
+    member of the shared kind takes its own launches too.  All stay bitwise
+    equal to eager stepping."""
+    big = W.params(nx=128, ny=128, nz=128, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.08, seed=71)
+    rng = np.random.default_rng(71)
+    pos = W.random_sphere_positions((128, 128, 128), 40, 5.0, seed=71)
+    specs = [(big, W.make_particles(pos, 5.0, vel=rng.uniform(-0.02, 0.02, (40, 3))), "fp32")] + _members()[:2]
+    batched = [_make(s) for s in specs]
+    eager = [_make(s) for s in specs]
+    batch = lbm().Batch(batched, steps_per_launch=4)
+    for nl in (1, 2):
+        batch.step(nl)
+        for e in eager:
+            e.step(4 * nl)
+        for b, e in zip(batched, eager):
+            _same(b, e)
+    batch.close()
+    lone, lone_eager = _make(_members()[0]), _make(_members()[0])
+    batch = lbm().Batch([lone], steps_per_launch=2)
+    batch.step(3)
+    lone_eager.step(6)
+    _same(lone, lone_eager)
+    batch.close()
+
+
 def test_batch_membership_rules():
     L = lbm()
     a = _make(_members()[1])
