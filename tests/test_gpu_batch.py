@@ -162,6 +162,42 @@ def test_large_member_keeps_its_own_launches_beside_shared_ones():
     batch.close()
 
 
+def test_member_with_sweep_side_bounces_in_a_batch():
+    """A member whose bounced populations the density sweep forms
+    (link_writes = 0), stepped alone before, between and after replays of a
+    shared-launch batch (whose steps write every bounce from the link kernel),
+    stays bitwise equal to a twin that always writes them."""
+    p = W.params(nx=32, ny=32, nz=28, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.07, seed=81)
+    rng = np.random.default_rng(81)
+    pos = W.random_sphere_positions((32, 32, 28), 4, 3.5, seed=81)
+    parts = W.make_particles(pos, 3.5, vel=rng.uniform(-0.04, 0.04, (4, 3)), color=[0.05, 0.0, -0.05, 0.0])
+    lats = []
+    for lw in (0, 1):
+        lat = lbm().Lattice(dict(p, link_writes=lw), precision="fp32", kernel="twopass")
+        lat.add_particles(parts)
+        lats.append(lat)
+    a, b = lats
+    other = _make(_members()[1])
+    a.step(7)
+    b.step(7)
+    batch = lbm().Batch([a, other], steps_per_launch=4)
+    batch.step(2)
+    b.step(8)
+    a.step(2)
+    b.step(2)
+    batch.step(1)
+    b.step(4)
+    a.step(3)
+    b.step(3)
+    batch.close()
+    assert np.array_equal(a.owner(), b.owner())
+    assert np.array_equal(a.populations(), b.populations())
+    pa, pb = a.particles(), b.particles()
+    for k in ("R", "U", "W", "Ffluid", "Tfluid"):
+        assert np.array_equal(pa[k], pb[k]), k
+    assert a.observables()["covered_total"] == b.observables()["covered_total"]
+
+
 def test_batch_membership_rules():
     L = lbm()
     a = _make(_members()[1])

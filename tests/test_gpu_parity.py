@@ -651,8 +651,8 @@ def test_large_lattice_translation_invariance():
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_bounces_formed_in_the_sweep_equal_written_bounces(precision):
     """The next sweep forming the bounced populations of sphere links itself
-    (the default with the two-pass sweep) gives bitwise the state of the link
-    kernel writing them, through covering and uncovering, with observables, a
+    (lb_params.link_writes = 0 with the two-pass sweep) gives bitwise the state
+    of the link kernel writing them (the default), through covering and uncovering, with observables, a
     checkpoint and a particle-state reset (each of which writes the pending
     ones out) in between."""
     p = W.params(nx=32, ny=28, nz=24, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=0.07, seed=41)
