@@ -641,6 +641,8 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     launch_fold_events(h);  // the old spheres' event counts into the totals first
     free_particles(h);
     h->np = tot;
+    h->max_shell_cap = 0;
+    for (int p = 0; p < tot; ++p) h->max_shell_cap = std::max(h->max_shell_cap, (int)shell_cap[p]);
     DevParticles &D = h->dpart;
     double *dbl = (double *)dev_alloc(h, sizeof(double) * 34 * tot);
     int32_t *i32 = (int32_t *)dev_alloc(h, sizeof(int32_t) * 10 * tot);

@@ -333,16 +333,20 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize_mass(const double *__r
 // component; only its Psi - Psi(rho_ref) is stored (in the Psi array), since
 // every later use of a shell site's density goes through Psi.
 // ---------------------------------------------------------------------------
-constexpr int SHELL_THREADS = 256;  // one block per sphere, a virtual-fluid site per thread
+// A virtual-fluid site per thread; the single-lattice launch gives each
+// sphere one block per SHELL_THREADS sites of its list capacity (chunk c takes
+// sites c * SHELL_THREADS + t, blocks past the list end return at once), the
+// batch launch one block per sphere (nchunk = 1)
+constexpr int SHELL_THREADS = 256;
 template <typename T>
 __device__ __forceinline__ void shell_fill_body(const DevParams &P, const DevParticles &D,
                                                 const uint32_t *__restrict__ info, T *__restrict__ rho,
-                                                T *__restrict__ psi, const Grid &g) {
-    const int p = (int)g.bid;
+                                                T *__restrict__ psi, int p, int chunk, int nchunk) {
     const int cnt = min(D.shell_cnt[p], D.shell_cap[p]), off = D.shell_off[p];
+    if (chunk * SHELL_THREADS >= cnt) return;  // uniform over the block
     const double col = D.color[p];
     const T irho0 = (T)P.inv_rho0;
-    for (int k = threadIdx.x; k < cnt; k += SHELL_THREADS) {
+    for (int k = chunk * SHELL_THREADS + threadIdx.x; k < cnt; k += nchunk * SHELL_THREADS) {
         const long long s = D.shell[off + k];
         int x, y, z;
         site_xyz(s, P, x, y, z);
@@ -372,8 +376,10 @@ __device__ __forceinline__ void shell_fill_body(const DevParams &P, const DevPar
 template <typename T>
 __global__ __launch_bounds__(SHELL_THREADS) void k_shell_fill(DevParams P, DevParticles D,
                                                               const uint32_t *__restrict__ info, T *__restrict__ rho,
-                                                              T *__restrict__ psi) {
-    shell_fill_body(P, D, info, rho, psi, own_grid());
+                                                              T *__restrict__ psi, int nchunk) {
+    // chunk-major: the first chunks of every sphere are dispatched first
+    const int np = (int)(gridDim.x / (unsigned)nchunk);
+    shell_fill_body(P, D, info, rho, psi, (int)(blockIdx.x % (unsigned)np), (int)(blockIdx.x / (unsigned)np), nchunk);
 }
 
 // Psi^c(x + c_i) - Psi^c(rho_ref) of the 18 neighbours (pn[c][i-1]) and of
@@ -705,12 +711,14 @@ void launch_finalize_mass_n(lb_handle *h, int nb) {
 
 void launch_shell_fill(lb_handle *h) {
     if (h->np == 0) return;
+    const int nchunk = std::max(1, (h->max_shell_cap + SHELL_THREADS - 1) / SHELL_THREADS);
+    const unsigned nb = (unsigned)h->np * (unsigned)nchunk;
     if (h->prm.precision == LB_FP64)
-        k_shell_fill<double><<<h->np, SHELL_THREADS, 0, h->stream>>>(h->dp, h->dpart, h->info, (double *)h->rho,
-                                                             (double *)h->psi);
+        k_shell_fill<double><<<nb, SHELL_THREADS, 0, h->stream>>>(h->dp, h->dpart, h->info, (double *)h->rho,
+                                                                  (double *)h->psi, nchunk);
     else
-        k_shell_fill<float><<<h->np, SHELL_THREADS, 0, h->stream>>>(h->dp, h->dpart, h->info, (float *)h->rho,
-                                                                    (float *)h->psi);
+        k_shell_fill<float><<<nb, SHELL_THREADS, 0, h->stream>>>(h->dp, h->dpart, h->info, (float *)h->rho,
+                                                                 (float *)h->psi, nchunk);
     LB_HIP_CHECK(hipGetLastError());
 }
 
@@ -791,7 +799,7 @@ template <typename T>
 __global__ __launch_bounds__(SHELL_THREADS) void kb_shell_fill(BatchPlan B) {
     Grid g;
     const BatchMember &M = B.m[batch_member(B, BM_SPHERE, g)];
-    shell_fill_body(M.P, M.D, M.info, (T *)M.rho, (T *)M.psi, g);
+    shell_fill_body(M.P, M.D, M.info, (T *)M.rho, (T *)M.psi, (int)g.bid, 0, 1);
 }
 template <typename S, typename Mo, bool ROWS>
 __global__ __launch_bounds__(BLOCK) LBM_COLLIDE_ATTR void kb_collide_stream(BatchPlan B) {

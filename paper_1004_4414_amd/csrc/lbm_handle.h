@@ -45,6 +45,7 @@ struct lb_handle {
 
     // particles
     int np = 0;
+    int max_shell_cap = 0;  // the largest virtual-fluid list capacity of a sphere
     lbm::DevParticles dpart{};
     std::vector<void *> part_allocs;
     std::vector<double> h_rad, h_dens, h_color;
