@@ -200,7 +200,8 @@ void rebuild_map(lb_handle *h) {
     launch_map_commit(h, true);
     launch_info_dense(h);
     launch_fill_int(h, h->stage, h->N, STAGE_NONE);
-    launch_build_lists(h, true);
+    h->lists_pending = false;  // built afresh here
+    launch_build_lists(h, true, h->stream);
 }
 
 void free_particles(lb_handle *h) {
@@ -334,15 +335,28 @@ void enqueue_step(lb_handle *h) {
         h->dp.redirect = 0;
         h->dp.link_write = 1;
     }
+    // The virtual-fluid lists of the last map update are read first by this
+    // step's virtual-fluid fill, and the density sweep does not touch what
+    // they are built from: with the second stream they are built there, beside
+    // the sweep (a captured step builds them at its end, on the one stream).
+    bool lists_beside = false;
     if (fork) {
         LB_HIP_CHECK(hipEventRecord(h->ev_fork, h->stream));
         LB_HIP_CHECK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+        if (h->lists_pending) {
+            launch_build_lists(h, false, h->side);
+            LB_HIP_CHECK(hipEventRecord(h->ev_lists, h->side));
+            h->lists_pending = false;
+            lists_beside = true;
+        }
         launch_pair_forces(h, h->side);
         LB_HIP_CHECK(hipEventRecord(h->ev_join, h->side));
+    } else {
+        settle_lists(h);
     }
     if (h->kernel == LB_KERNEL_FUSED) {
         hipEvent_t t_col = h->timing_begin(0);
-        launch_fused(h, fin, fout);
+        launch_fused(h, fin, fout);  // its virtual fluid comes from the class words
         h->timing_end(0, t_col);
         launch_finalize_mass_n(h, h->n_fused_blocks);
     } else {
@@ -350,6 +364,7 @@ void enqueue_step(lb_handle *h) {
         launch_density(h, fin, true);
         h->timing_end(1, t_den);
         launch_finalize_mass(h);
+        if (lists_beside) LB_HIP_CHECK(hipStreamWaitEvent(h->stream, h->ev_lists, 0));
         launch_shell_fill(h);
         hipEvent_t t_col = h->timing_begin(0);
         launch_collide_stream(h, fin, fout);
@@ -357,6 +372,8 @@ void enqueue_step(lb_handle *h) {
     }
     launch_wall_links(h, fout);
     if (h->np) {
+        if (lists_beside && h->kernel == LB_KERNEL_FUSED)
+            LB_HIP_CHECK(hipStreamWaitEvent(h->stream, h->ev_lists, 0));
         launch_particle_fluid_force(h, fout);
         if (fork) LB_HIP_CHECK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
         else launch_pair_forces(h, h->stream);
@@ -367,7 +384,8 @@ void enqueue_step(lb_handle *h) {
         launch_cover_refill(h, fout);
         launch_map_commit(h, false);
         launch_map_info(h);
-        launch_build_lists(h, false);
+        if (fork) h->lists_pending = true;  // built beside the next step's sweep
+        else launch_build_lists(h, false, h->stream);
     }
     h->timing_end(2, t_step);
     h->cur = 1 - h->cur;
@@ -396,6 +414,12 @@ void lbm::settle_bounces(lb_handle *h) {
     if (!h->bounce_pending) return;
     launch_materialize(h, h->f[h->cur]);
     h->bounce_pending = false;
+}
+
+void lbm::settle_lists(lb_handle *h) {
+    if (!h->lists_pending) return;
+    launch_build_lists(h, false, h->stream);
+    h->lists_pending = false;
 }
 
 hipEvent_t lb_handle::timing_begin(int) {
@@ -511,6 +535,7 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         LB_HIP_CHECK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
         LB_HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         LB_HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        LB_HIP_CHECK(hipEventCreateWithFlags(&h->ev_lists, hipEventDisableTiming));
         LB_HIP_CHECK(hipMemsetAsync(h->dstate, 0, sizeof(DevState), h->stream));
         LB_HIP_CHECK(hipMemsetAsync(h->f[1], 0, fsz, h->stream));
         launch_fill_int(h, h->stage, h->N, STAGE_NONE);
@@ -538,6 +563,7 @@ void lb_destroy(lb_handle *h) {
     }
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_lists) (void)hipEventDestroy(h->ev_lists);
     release_events(h);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     h->ev_pool.clear();
@@ -795,6 +821,7 @@ int lb_step(lb_handle *h, int32_t nsteps) {
 int lb_synchronize(lb_handle *h) {
     if (!h) return LB_EINVAL;
     LB_API_BEGIN
+    settle_lists(h);  // their overflow check belongs to the steps taken
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
     return check_device_state(h);
     LB_API_END
@@ -804,6 +831,7 @@ int lb_observables(lb_handle *h, lb_observables_t *out) {
     if (!h || !out) return LB_EINVAL;
     LB_API_BEGIN
     settle_bounces(h);
+    settle_lists(h);
     std::memset(out, 0, sizeof(*out));
     launch_sums(h, h->f[h->cur]);
     launch_fold_events(h);
@@ -850,6 +878,7 @@ int lb_get_fields(lb_handle *h, double *rho, double *j, double *force, double *u
     if (!h) return LB_EINVAL;
     LB_API_BEGIN
     settle_bounces(h);
+    settle_lists(h);  // the virtual-fluid fill below reads them
     const long long N = h->N;
     if (!h->fields) h->fields = (double *)dev_alloc(h, sizeof(double) * 17 * N);
     launch_density(h, h->f[h->cur], false);
@@ -953,6 +982,7 @@ int lb_particle_counts(lb_handle *h, int32_t *links, int32_t *shell) {
     if (!h) return LB_EINVAL;
     if (!h->np) return LB_OK;
     LB_API_BEGIN
+    settle_lists(h);
     if (links)
         LB_HIP_CHECK(hipMemcpyAsync(links, h->dpart.link_cnt, 4 * h->np, hipMemcpyDeviceToHost, h->stream));
     if (shell)

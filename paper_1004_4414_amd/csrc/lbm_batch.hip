@@ -168,6 +168,7 @@ int lb_batch_create(lb_handle **members, int32_t n, int32_t steps_per_launch, vo
     try {
         for (lb_handle *h : b->m) {
             lbm::settle_bounces(h);  // the graph's first sweep pulls plainly
+            lbm::settle_lists(h);    // and its first virtual-fluid fill reads the lists
             h->flags_tracked = false;
             BATCH_CHECK(hipStreamSynchronize(h->stream));
         }
@@ -256,6 +257,7 @@ int lb_batch_step(lb_batch *b, int32_t nlaunches) {
         // left by steps outside the batch written out first) ...
         for (int i = 0; i < n; ++i) {
             lbm::settle_bounces(b->m[i]);
+            lbm::settle_lists(b->m[i]);
             b->m[i]->flags_tracked = false;
             BATCH_CHECK(hipEventRecord(b->ev_member[i], b->m[i]->stream));
             BATCH_CHECK(hipStreamWaitEvent(b->stream, b->ev_member[i], 0));

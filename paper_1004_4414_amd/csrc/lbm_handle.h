@@ -16,7 +16,7 @@ struct lb_handle {
     // the pair search runs on a stream of its own, forked from `stream` at the
     // start of a step and joined before the sphere forces are summed
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_lists = nullptr;
     int device = 0;  // the device current at lb_create
     lb_allocator alloc{};
     bool have_alloc = false;
@@ -63,6 +63,10 @@ struct lb_handle {
     // the last map update and chg_prev holds its change lists
     bool bounce_pending = false;
     bool flags_tracked = false;
+    // lists_pending: the virtual-fluid lists of the last map update are still
+    // to be built (the next step builds them on the second stream, beside its
+    // density sweep; readers of the lists build them first: settle_lists)
+    bool lists_pending = false;
     std::vector<void *> owned;  // every device allocation, freed by lb_destroy
 
     // event timing (measurement only): per kind, pairs of recorded events
@@ -80,6 +84,9 @@ void one_step(lb_handle *h);  // enqueue one time step on h->stream
 // write out every bounced population the last step left to the next sweep
 // (before any other reader of the stored populations)
 void settle_bounces(lb_handle *h);
+// build the virtual-fluid lists the last step left pending (before any other
+// reader of the lists or of their counts)
+void settle_lists(lb_handle *h);
 void launch_clear_flags(lb_handle *h);  // class-word flags of the map update, all sites
 void dev_free(lb_handle *h, void *p);
 
@@ -140,7 +147,7 @@ void launch_cover_refill(lb_handle *h, void *fout);
 void launch_map_commit(lb_handle *h, bool full);
 void launch_map_info(lb_handle *h);
 void launch_fold_events(lb_handle *h);  // per-sphere event counts into DevState
-void launch_build_lists(lb_handle *h, bool full);
+void launch_build_lists(lb_handle *h, bool full, hipStream_t s);
 
 // a batch advanced by shared launches: one launch per stage of the step for
 // all members (lbm_batch.hip builds it; the launchers are in lbm_fluid.hip and

@@ -1542,9 +1542,9 @@ void launch_map_info(lb_handle *h) {
     LB_HIP_CHECK(hipGetLastError());
 }
 
-void launch_build_lists(lb_handle *h, bool full) {
+void launch_build_lists(lb_handle *h, bool full, hipStream_t s) {
     if (!h->np) return;
-    k_build_lists<<<h->np, BLOCK, 0, h->stream>>>(h->dp, h->dpart, h->owner, h->info, h->dstate, full ? 1 : 0);
+    k_build_lists<<<h->np, BLOCK, 0, s>>>(h->dp, h->dpart, h->owner, h->info, h->dstate, full ? 1 : 0);
     LB_HIP_CHECK(hipGetLastError());
 }
 
