@@ -337,8 +337,9 @@ void enqueue_step(lb_handle *h) {
     }
     // The virtual-fluid lists of the last map update are read first by this
     // step's virtual-fluid fill, and the density sweep does not touch what
-    // they are built from: with the second stream they are built there, beside
-    // the sweep (a captured step builds them at its end, on the one stream).
+    // they are built from: with the second stream (and the two-pass sweep)
+    // they are built there, beside the density sweep (a captured step builds
+    // them at its end, on the one stream).
     bool lists_beside = false;
     if (fork) {
         LB_HIP_CHECK(hipEventRecord(h->ev_fork, h->stream));
@@ -372,8 +373,6 @@ void enqueue_step(lb_handle *h) {
     }
     launch_wall_links(h, fout);
     if (h->np) {
-        if (lists_beside && h->kernel == LB_KERNEL_FUSED)
-            LB_HIP_CHECK(hipStreamWaitEvent(h->stream, h->ev_lists, 0));
         launch_particle_fluid_force(h, fout);
         if (fork) LB_HIP_CHECK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
         else launch_pair_forces(h, h->stream);
@@ -384,7 +383,10 @@ void enqueue_step(lb_handle *h) {
         launch_cover_refill(h, fout);
         launch_map_commit(h, false);
         launch_map_info(h);
-        if (fork) h->lists_pending = true;  // built beside the next step's sweep
+        // built beside the next step's density sweep; the fused sweep, held
+        // to two wavefronts per SIMD by its registers, lost 0.23 ms per step
+        // to the walk beside it, so its lists are built here
+        if (fork && h->kernel == LB_KERNEL_TWOPASS) h->lists_pending = true;
         else launch_build_lists(h, false, h->stream);
     }
     h->timing_end(2, t_step);
