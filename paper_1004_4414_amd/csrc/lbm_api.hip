@@ -384,8 +384,8 @@ void enqueue_step(lb_handle *h) {
         launch_map_commit(h, false);
         launch_map_info(h);
         // built beside the next step's density sweep; the fused sweep, held
-        // to two wavefronts per SIMD by its registers, lost 0.23 ms per step
-        // to the walk beside it, so its lists are built here
+        // to two wavefronts per SIMD by its registers, took 0.23 ms longer
+        // with the walk beside it, so its lists are built here
         if (fork && h->kernel == LB_KERNEL_TWOPASS) h->lists_pending = true;
         else launch_build_lists(h, false, h->stream);
     }
