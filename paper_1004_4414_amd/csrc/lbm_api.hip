@@ -510,8 +510,10 @@ int lb_create(const lb_params *p, const lb_allocator *alloc, void *stream, lb_ha
         delete h;
         return LB_EINVAL;
     }
-    // automatic choice: the two-pass sweep, which the autotuner measures as the
-    // faster one on the boxes tried so far (32^3 to 256^3)
+    // automatic choice: the two-pass sweep, the faster one on the boxes tried
+    // (32^3 to 256^3) in FP64, FP16 and BF16 and from rest; at a developed
+    // 256^3 FP32 state the fused sweep is about 1% faster (lb_autotune picks
+    // per box)
     h->kernel = p->kernel == LB_KERNEL_AUTO ? LB_KERNEL_TWOPASS : p->kernel;
     for (int a = 0; a < 3; ++a) h->tile[a] = p->tile[a];
     choose_fused_tile(h);
