@@ -254,17 +254,21 @@ __global__ __launch_bounds__(BLOCK) void k_density_bounce(DevParams P, S *f, con
 }
 
 // fixed-order sum of the per-block masses: M(t), baseline M(0), sentinel.
-// FIN_BLOCKS blocks each sum a contiguous range of the partials (8
-// independent sums per thread, then a fixed tree); the last block to finish
-// (an integer counter) sums their results in block order and resets the
-// counter, so the total does not depend on which block finishes last.
+// fin_blocks(nb) blocks (one per 4096 partials, at most FIN_BLOCKS) each sum
+// a contiguous range of the partials (8 independent sums per thread, then a
+// fixed tree); the last block to finish (an integer counter) sums their
+// results in block order and resets the counter, so the total does not
+// depend on which block finishes last.  Blocks past fin_blocks(nb) return.
 constexpr int FIN_THREADS = 256;
+__host__ __device__ inline int fin_blocks(int nb) { return std::max(1, std::min(FIN_BLOCKS, (nb + 4095) / 4096)); }
 __device__ __forceinline__ void finalize_body(const double *__restrict__ partial, int nb, DevState *st,
                                               unsigned bid) {
     __shared__ double lds[2][FIN_THREADS];
     __shared__ int last;
     const int t = threadIdx.x;
-    const int chunk = (nb + FIN_BLOCKS - 1) / FIN_BLOCKS;
+    const int nf = fin_blocks(nb);
+    if ((int)bid >= nf) return;  // uniform over the block
+    const int chunk = (nb + nf - 1) / nf;
     const int b_lo = (int)bid * chunk, b_hi = min(nb, b_lo + chunk);
     double a[2][8];
 #pragma unroll
@@ -294,13 +298,13 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
         st->fin_part[2 * bid] = lds[0][0];
         st->fin_part[2 * bid + 1] = lds[1][0];
         __threadfence();
-        last = atomicAdd(&st->fin_count, 1u) == FIN_BLOCKS - 1;
+        last = atomicAdd(&st->fin_count, 1u) == (unsigned)nf - 1;
     }
     __syncthreads();
     if (!last) return;
     __threadfence();
     const volatile double *fp = st->fin_part;
-    for (int c = 0; c < 2; ++c) lds[c][t] = t < FIN_BLOCKS ? fp[2 * t + c] : 0.0;
+    for (int c = 0; c < 2; ++c) lds[c][t] = t < nf ? fp[2 * t + c] : 0.0;
     __syncthreads();
     for (int s = FIN_BLOCKS / 2; s > 0; s >>= 1) {
         if (t < s) {
@@ -705,7 +709,7 @@ void launch_density(lb_handle *h, const void *f, bool partial_sums) {
 void launch_finalize_mass(lb_handle *h) { launch_finalize_mass_n(h, (int)dense_blocks(h) * (BLOCK / 64)); }
 
 void launch_finalize_mass_n(lb_handle *h, int nb) {
-    k_finalize_mass<<<FIN_BLOCKS, FIN_THREADS, 0, h->stream>>>(h->partial, nb, h->dstate);
+    k_finalize_mass<<<fin_blocks(nb), FIN_THREADS, 0, h->stream>>>(h->partial, nb, h->dstate);
     LB_HIP_CHECK(hipGetLastError());
 }
 
