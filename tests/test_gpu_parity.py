@@ -425,6 +425,30 @@ def test_runs_are_bitwise_reproducible():
         assert np.array_equal(runs[0][1][k], runs[1][1][k])
 
 
+def test_readers_between_steps_leave_the_run_unchanged():
+    """Reading observables, fields, particle counts, populations and the
+    state between single steps (each call builds the virtual-fluid lists the
+    last step left to the next one first) gives bitwise the run of one
+    uninterrupted lb_step call, in both sweeps."""
+    p, parts = _prescribed_boxes(n=32, count=6, seed=11)
+    parts["prescribed"][:] = 0
+    for kernel in ("twopass", "fused"):
+        a = lbm().Lattice(p, precision="fp32", kernel=kernel)
+        a.add_particles(parts)
+        b = lbm().Lattice(p, precision="fp32", kernel=kernel)
+        b.add_particles(parts)
+        for s in range(12):
+            a.step(1)
+            [a.observables, a.fields, a.particle_counts, a.populations, a.synchronize, a.get_state][s % 6]()
+        b.step(12)
+        assert np.array_equal(a.populations(), b.populations()), kernel
+        assert np.array_equal(a.owner(), b.owner()), kernel
+        assert np.array_equal(a.particle_counts()[0], b.particle_counts()[0]), kernel
+        pa, pb = a.particles(), b.particles()
+        for k in pa:
+            assert np.array_equal(pa[k], pb[k]), (kernel, k)
+
+
 def test_checkpoint_roundtrip():
     p, parts = _prescribed_boxes(n=32, count=6, seed=10)
     a = lbm().Lattice(p, precision="fp32")
