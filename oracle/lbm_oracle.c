@@ -89,6 +89,7 @@ typedef struct {
     double k_hertz, lub_hc, lub_hmin;
     int32_t virtual_fluid; /* 1: paper's virtual fluid (Sec. IV); 0: empty particles */
     int32_t lub_mode;      /* 0: Eq. (22) as an explicit force; 1: pair impulses (see move_particles) */
+    int32_t force_average; /* 0: this step's fluid force; 1: mean over two steps (see move_particles) */
 } orc_params;
 
 typedef struct {
@@ -106,6 +107,8 @@ typedef struct {
     double *rad, *dens, *color, *mass, *inertia;
     int32_t *prescribed;
     double *Ffl, *Tfl;  /* fluid force / torque of the last step (links + Shan-Chen) */
+    double *Fprev, *Tprev; /* fluid force / torque of the step before (force_average) */
+    int32_t *have_prev;    /* 1 once a sphere has one */
     double *Ftot, *Ttot; /* total force / torque applied in the last step */
     double *P, *PT;     /* pending impulse / angular impulse from covering / uncovering */
     double wall_force[2][3];
@@ -289,6 +292,7 @@ void orc_destroy(orc_state *s) {
     free(s->owner); free(s->owner_new); free(s->is_shell);
     free(s->R); free(s->U); free(s->W); free(s->rad); free(s->dens); free(s->color);
     free(s->mass); free(s->inertia); free(s->prescribed); free(s->Ffl); free(s->Tfl);
+    free(s->Fprev); free(s->Tprev); free(s->have_prev);
     free(s->Ftot); free(s->Ttot); free(s->P); free(s->PT);
     free(s);
 }
@@ -337,6 +341,9 @@ int orc_add_particles(orc_state *s, int n, const double *pos, const double *vel,
         s->mass = realloc(s->mass, sizeof(double) * cap); s->inertia = realloc(s->inertia, sizeof(double) * cap);
         s->prescribed = realloc(s->prescribed, sizeof(int32_t) * cap);
         s->Ffl = realloc(s->Ffl, 3 * sizeof(double) * cap); s->Tfl = realloc(s->Tfl, 3 * sizeof(double) * cap);
+        s->Fprev = realloc(s->Fprev, 3 * sizeof(double) * cap);
+        s->Tprev = realloc(s->Tprev, 3 * sizeof(double) * cap);
+        s->have_prev = realloc(s->have_prev, sizeof(int32_t) * cap);
         s->Ftot = realloc(s->Ftot, 3 * sizeof(double) * cap); s->Ttot = realloc(s->Ttot, 3 * sizeof(double) * cap);
         s->P = realloc(s->P, 3 * sizeof(double) * cap); s->PT = realloc(s->PT, 3 * sizeof(double) * cap);
         s->cap = cap;
@@ -359,6 +366,7 @@ int orc_add_particles(orc_state *s, int n, const double *pos, const double *vel,
         s->inertia[p] = 0.4 * s->mass[p] * radius[k] * radius[k];
     }
     s->np = tot;
+    for (int p = 0; p < tot; ++p) s->have_prev[p] = 0;
     /* the fluid on sites that became solid is removed */
     build_owner_map(s, s->owner_new);
     for (long m = 0; m < s->N; ++m) {
@@ -621,6 +629,12 @@ static void shan_chen_on_particles(orc_state *s) {
 /*    pair's lubrication; sharing each sphere's mass among its contacts keeps */
 /*    the simultaneous impulses from overshooting.                           */
 /* A sphere with prescribed motion counts as infinitely heavy.                */
+/* Reading (force_average 1; the paper takes the link coupling from Ladd's    */
+/* method and states no such step): the fluid force and torque that enter     */
+/* the leap-frog are the mean of this step's and the previous step's, or this */
+/* step's alone in a sphere's first step.  The momentum the spheres take from */
+/* the fluid over steps 1..T is then the sum of the fluid forces plus half    */
+/* the first step's minus half the last step's.                               */
 /* ------------------------------------------------------------------------- */
 static void move_particles(orc_state *s) {
     const double L[3] = {s->nx, s->ny, s->nz};
@@ -628,11 +642,21 @@ static void move_particles(orc_state *s) {
     double nu = 0.0;
     for (int c = 0; c < NCOMP; ++c) nu += CS2 * (s->p.tau[c] - 0.5);
     nu /= NCOMP;
-    for (int p = 0; p < np; ++p)
+    for (int p = 0; p < np; ++p) {
+        const int avg = s->p.force_average && s->have_prev[p];
         for (int a = 0; a < 3; ++a) {
-            s->Ftot[3 * p + a] = s->Ffl[3 * p + a] + s->P[3 * p + a];
-            s->Ttot[3 * p + a] = s->Tfl[3 * p + a] + s->PT[3 * p + a];
+            double ff = s->Ffl[3 * p + a], tf = s->Tfl[3 * p + a];
+            if (avg) {
+                ff = 0.5 * (ff + s->Fprev[3 * p + a]);
+                tf = 0.5 * (tf + s->Tprev[3 * p + a]);
+            }
+            s->Fprev[3 * p + a] = s->Ffl[3 * p + a];
+            s->Tprev[3 * p + a] = s->Tfl[3 * p + a];
+            s->Ftot[3 * p + a] = ff + s->P[3 * p + a];
+            s->Ttot[3 * p + a] = tf + s->PT[3 * p + a];
         }
+        s->have_prev[p] = 1;
+    }
     /* Hertz repulsion; lubrication contacts (p < q, unit vector n from p to q) */
     int ncon = 0, capcon = 16;
     int *cp = malloc(sizeof(int) * capcon), *cq = malloc(sizeof(int) * capcon);
@@ -944,6 +968,7 @@ void orc_set_particle_state(orc_state *s, const double *in) {
             s->P[3 * p + a] = in[15 * p + 9 + a];
             s->PT[3 * p + a] = in[15 * p + 12 + a];
         }
+    for (int p = 0; p < s->np; ++p) s->have_prev[p] = 0;
     build_owner_map(s, s->owner_new);
     for (long n = 0; n < s->N; ++n) s->owner[n] = s->owner_new[n];
 }

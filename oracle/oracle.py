@@ -27,7 +27,7 @@ DEFAULTS = dict(
     rho_init=(0.35, 0.35), noise_amp=0.01, seed=1,
     body_accel=(0.0, 0.0, 0.0), wall_axis=-1, wall_vel=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
     c0_mass_corr=0.0, k_hertz=100.0, lub_hc=2.0 / 3.0, lub_hmin=0.1, lub_mode=1,
-    virtual_fluid=1,
+    force_average=0, virtual_fluid=1,
 )
 
 
@@ -43,6 +43,7 @@ class _Params(ctypes.Structure):
         ("c0_mass_corr", ctypes.c_double), ("k_hertz", ctypes.c_double),
         ("lub_hc", ctypes.c_double), ("lub_hmin", ctypes.c_double),
         ("virtual_fluid", ctypes.c_int32), ("lub_mode", ctypes.c_int32),
+        ("force_average", ctypes.c_int32),
     ]
 
 
@@ -137,6 +138,7 @@ class Oracle:
         s.lub_hc, s.lub_hmin = p["lub_hc"], p["lub_hmin"]
         s.virtual_fluid = int(p["virtual_fluid"])
         s.lub_mode = int(p["lub_mode"])
+        s.force_average = int(p["force_average"])
         self.shape = (s.nz, s.ny, s.nx)
         self.N = s.nx * s.ny * s.nz
         self._h = lib().orc_create(ctypes.byref(s))

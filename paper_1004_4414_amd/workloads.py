@@ -19,6 +19,7 @@ PARAM_DEFAULTS = dict(
     rho_init=(0.35, 0.35), noise_amp=0.01, seed=1,
     body_accel=(0.0, 0.0, 0.0), wall_axis=-1, wall_vel=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
     c0_mass_corr=0.0, k_hertz=100.0, lub_hc=2.0 / 3.0, lub_hmin=0.1, lub_mode=1,
+    force_average=0,
 )
 
 

@@ -93,9 +93,9 @@ def test_add_particles_validation():
     assert orc.add_particles(W.make_particles([[12, 12, 12]], 2.0)) == -5  # after stepping
 
 
-def _moving_spheres(c0=0.0, steps=60, g=0.06, seed=4):
+def _moving_spheres(c0=0.0, steps=60, g=0.06, seed=4, **kw):
     p = W.params(nx=20, ny=20, nz=20, rho_init=(0.36, 0.34), noise_amp=0.02, g_br=g, seed=seed,
-                 c0_mass_corr=c0)
+                 c0_mass_corr=c0, **kw)
     orc = O.Oracle(p)
     pos = [[5.2, 5.5, 6.1], [14.3, 6.2, 13.7], [9.6, 14.4, 4.8]]
     vel = [[0.04, 0.03, -0.02], [-0.03, 0.05, 0.01], [0.02, -0.04, 0.05]]
@@ -116,6 +116,41 @@ def test_moving_spheres_conserve_total_momentum():
     c = orc.counts()
     assert c["covered_total"] > 10 and c["uncovered_total"] > 10
     assert np.abs(total_momentum(orc) - p0).max() < 1e-12 * scale
+
+
+def test_force_average_shifts_the_momentum_balance_by_half_the_end_forces():
+    """force_average = 1 (the fluid force entering Eqs. (9), (10) is the mean
+    of this step's and the previous step's, this step's alone in the first):
+    over steps 1..T the spheres take from the fluid the sum of the fluid
+    forces plus half the first step's minus half the last step's, so fluid +
+    sphere momentum + pending impulses moves by exactly (F_1 - F_T) / 2 summed
+    over the spheres.  A weight other than 1/2, a stale or missing previous
+    force, or averaging in the first step breaks the balance or the first
+    step's equality with the plain run; the shift itself is far above the
+    rounding, so the plain conservation law would fail here."""
+    orc = _moving_spheres(force_average=1)
+    plain = _moving_spheres()
+    p0 = total_momentum(orc)
+    scale = orc.sums()["mass"].sum() * 0.05
+    orc.step(1)
+    plain.step(1)
+    a, b = orc.particles(), plain.particles()
+    for k in ("R", "U", "W", "Ftotal", "Ttotal"):
+        assert np.array_equal(a[k], b[k]), k
+    F1 = a["Ffluid"].sum(0)
+    prev = a
+    for _ in range(59):
+        pending = prev["PT"]
+        orc.step(1)
+        cur = orc.particles()
+        # the torque half: the applied torque is the mean of the two reported
+        # fluid torques plus the angular impulse pending before the step
+        assert np.allclose(cur["Ttotal"], 0.5 * (cur["Tfluid"] + prev["Tfluid"]) + pending, rtol=0, atol=1e-13)
+        prev = cur
+    shift = 0.5 * (F1 - prev["Ffluid"].sum(0))
+    assert np.abs(total_momentum(orc) - p0 - shift).max() < 1e-12 * scale
+    assert np.abs(shift).max() > 1e-6 * scale
+    assert orc.counts()["covered_total"] > 10
 
 
 def test_mass_changes_only_by_covering_refilling_and_the_wall_term():
