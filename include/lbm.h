@@ -114,6 +114,15 @@ typedef struct {
                                 two-pass sweep, outside a stream capture, the next step's density
                                 sweep forms each from the fluid site's own slot (only links next
                                 to a map change are written out by the map update) */
+    int32_t force_average;   /* the fluid force and torque (links of Eq. (16), the moving-wall
+                                term, covering and Shan-Chen force on the sphere) that enter
+                                Eqs. (9), (10), which the paper leaves to the coupling of the
+                                literature it builds on: 0 (default): this step's, as printed;
+                                1: the mean of this step's and the previous step's (a sphere's
+                                first step after lb_add_particles or lb_set_particle_state uses
+                                its own alone), which damps the step-to-step oscillation of the
+                                link force that makes light spheres (density near the fluid's)
+                                run away in long runs */
 } lb_params;
 
 typedef struct {
@@ -149,7 +158,7 @@ typedef struct {
  * (4, 2), velocity_mode 1, eq_order 3, rho_init 0.35 each, noise 0.01,
  * seed 1, no walls, no body force, C_0 = 0, K_Hertz = 100, h_c = 2/3,
  * h_min = 0.1 (the cut-off and clamp stated with Eq. (22)), lub_mode 1,
- * automatic kernel and tiles; the box is 16^3.  Start every lb_params from
+ * link_writes 1, force_average 0, automatic kernel and tiles; the box is 16^3.  Start every lb_params from
  * here: a zeroed struct selects lub_mode 0. */
 void lb_default_params(lb_params *p);
 
@@ -236,7 +245,8 @@ int lb_get_particles(lb_handle *h, lb_particle_state *out);
 
 /* Overwrite R, U, Omega and the pending impulses of every sphere (15 doubles
  * per sphere in that order) and rebuild the solid map, virtual-fluid sites
- * and links from the new positions without touching the fluid. */
+ * and links from the new positions without touching the fluid.  The fluid
+ * force of the previous step is forgotten (force_average starts anew). */
 int lb_set_particle_state(lb_handle *h, const double *state);
 
 /* Bounce-back links (fluid x, i with x + c_i inside the sphere) and
@@ -249,14 +259,16 @@ int lb_particle_counts(lb_handle *h, int32_t *links, int32_t *shell);
  * bytes written (or needed when buf is NULL).  Holds the lb_params the
  * lattice was created with, the step counter, the populations in their
  * storage type, every sphere's state, radius, density, colour and motion
- * flag, and the mass baseline of Eq. (31).  Errors: LB_EINVAL (buffer too
+ * flag, the previous step's fluid force and torque of each sphere
+ * (force_average), and the mass baseline of Eq. (31).  Errors: LB_EINVAL (buffer too
  * small), LB_EDEVICE. */
 int lb_get_state(lb_handle *h, void *buf, size_t *bytes);
 
 /* Restore a checkpoint written by lb_get_state.  The lattice must have the
  * same box, precision and model parameters (tau, g_br, rho0, weights,
  * velocity_mode, eq_order, rho_init, walls, body force, C_0, K_Hertz,
- * lubrication; the noise draw and kernel choice may differ) and, if it has
+ * lubrication, force averaging; the noise draw, kernel choice and
+ * link_writes may differ) and, if it has
  * spheres, the same number with the same radius, density, colour and motion
  * flag; a lattice without spheres that has not stepped takes the
  * checkpoint's spheres.  Errors: LB_EINVAL (not a checkpoint, another format

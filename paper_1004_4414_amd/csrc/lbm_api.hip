@@ -57,7 +57,7 @@ int fail(lb_handle *h, int code, const std::string &msg) {
     }
 
 const char *kStateMagic = "LBMSTATE";
-constexpr uint32_t kStateVersion = 2;
+constexpr uint32_t kStateVersion = 3;
 
 // upper bound of the lattice sites of a sphere's outermost solid layer: those
 // sites lie within sqrt(2) inside the surface, so their unit cells lie in the
@@ -106,6 +106,7 @@ void set_dev_params(lb_handle *h) {
     d.link_write = 1;  // set per step by the step's launcher
     d.redirect = 0;
     d.multi_bits = h->prm.link_writes == 0;  // the sweep-side bounce reads INFO_MULTI
+    d.force_avg = p.force_average;
     d.any_color = 0;
     for (double c : h->h_color) d.any_color |= c != 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -132,6 +133,7 @@ int validate_params(const lb_params *p, std::string &msg) {
     if (p->eq_order != 2 && p->eq_order != 3) return msg = "eq_order must be 2 or 3", LB_EINVAL;
     if (p->lub_mode != 0 && p->lub_mode != 1) return msg = "lub_mode must be 0 or 1", LB_EINVAL;
     if (p->link_writes != 0 && p->link_writes != 1) return msg = "link_writes must be 0 or 1", LB_EINVAL;
+    if (p->force_average != 0 && p->force_average != 1) return msg = "force_average must be 0 or 1", LB_EINVAL;
     if (p->wall_axis < -1 || p->wall_axis > 2) return msg = "wall_axis must be -1, 0, 1 or 2", LB_EINVAL;
     if (p->wall_axis >= 0 && (p->wall_axis == 0 ? p->nx : (p->wall_axis == 1 ? p->ny : p->nz)) < 3)
         return msg = "a box with walls needs at least 3 sites along the wall axis", LB_EINVAL;
@@ -475,6 +477,7 @@ void lb_default_params(lb_params *p) {
     p->kernel = LB_KERNEL_AUTO;
     p->lub_mode = 1;
     p->link_writes = 1;
+    p->force_average = 0;
 }
 
 // message of the last failed lb_create on this thread (lb_last_error(NULL))
@@ -710,6 +713,9 @@ int lb_add_particles(lb_handle *h, int32_t n, const lb_particle *parts) {
     D.ncont = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
     D.cont = (int32_t *)dev_alloc(h, sizeof(int32_t) * MAX_LUB_CONTACTS * (size_t)tot);
     D.vs = (double *)dev_alloc(h, sizeof(double) * 3 * (size_t)tot);
+    D.Fprev = (double *)dev_alloc(h, sizeof(double) * 6 * (size_t)tot);
+    LB_HIP_CHECK(hipMemsetAsync(D.Fprev, 0xff, sizeof(double) * 6 * (size_t)tot, h->stream));  // NaN: none yet
+    h->part_allocs.push_back(D.Fprev);
     D.Rscan = (double *)dev_alloc(h, sizeof(double) * 3 * (size_t)tot);
     D.margin = (double *)dev_alloc(h, sizeof(double) * (size_t)tot);
     D.nnbr = (int32_t *)dev_alloc(h, sizeof(int32_t) * (size_t)tot);
@@ -976,6 +982,7 @@ int lb_set_particle_state(lb_handle *h, const double *state) {
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.W, W.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.P, P.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
     LB_HIP_CHECK(hipMemcpyAsync(h->dpart.PT, PT.data(), 24 * np, hipMemcpyHostToDevice, h->stream));
+    LB_HIP_CHECK(hipMemsetAsync(h->dpart.Fprev, 0xff, 48 * (size_t)np, h->stream));  // no previous step
     rebuild_map(h);
     LB_HIP_CHECK(hipStreamSynchronize(h->stream));
     return check_device_state(h);
@@ -999,11 +1006,12 @@ int lb_particle_counts(lb_handle *h, int32_t *links, int32_t *shell) {
 // checkpoint layout: magic[8], version, np (u32 each), the lb_params the
 // lattice was created with, step (i64), DevState, populations (raw storage
 // type), then per sphere R U W P PT (15 doubles) radius density colour (3
-// doubles) prescribed (i32)
+// doubles) the previous step's fluid force and torque (6 doubles) prescribed
+// (i32)
 int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
     if (!h || !bytes) return LB_EINVAL;
     const size_t fsz = (size_t)2 * Q * padded_sites(h->N) * h->tsize;
-    const size_t need = 8 + 2 * 4 + sizeof(lb_params) + 8 + sizeof(DevState) + fsz + (size_t)h->np * (18 * 8 + 4);
+    const size_t need = 8 + 2 * 4 + sizeof(lb_params) + 8 + sizeof(DevState) + fsz + (size_t)h->np * (24 * 8 + 4);
     if (!buf) {
         *bytes = need;
         return LB_OK;
@@ -1029,17 +1037,19 @@ int lb_get_state(lb_handle *h, void *buf, size_t *bytes) {
     o += fsz;
     if (h->np) {
         const int np = h->np;
-        std::vector<double> d((size_t)34 * np);
+        std::vector<double> d((size_t)34 * np), fp((size_t)6 * np);
         LB_HIP_CHECK(hipMemcpyAsync(d.data(), h->dpart.R, d.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        LB_HIP_CHECK(hipMemcpyAsync(fp.data(), h->dpart.Fprev, fp.size() * 8, hipMemcpyDeviceToHost, h->stream));
         LB_HIP_CHECK(hipStreamSynchronize(h->stream));
         const int blocks[5] = {0, 3, 6, 24, 27};
         for (int p = 0; p < np; ++p) {
-            double v[18];
+            double v[24];
             for (int b = 0; b < 5; ++b)
                 for (int a = 0; a < 3; ++a) v[3 * b + a] = d[(size_t)blocks[b] * np + 3 * p + a];
             v[15] = h->h_rad[p];
             v[16] = h->h_dens[p];
             v[17] = h->h_color[p];
+            for (int k = 0; k < 6; ++k) v[18 + k] = fp[(size_t)6 * p + k];
             std::memcpy(o, v, sizeof(v));
             o += sizeof(v);
             const int32_t pr = h->h_prescribed[p];
@@ -1060,7 +1070,7 @@ static bool same_model(const lb_params &a, const lb_params &b) {
               a.rho0 == b.rho0 && a.w_face == b.w_face && a.w_edge == b.w_edge &&
               a.velocity_mode == b.velocity_mode && a.eq_order == b.eq_order && a.wall_axis == b.wall_axis &&
               a.c0_mass_corr == b.c0_mass_corr && a.k_hertz == b.k_hertz && a.lub_hc == b.lub_hc &&
-              a.lub_hmin == b.lub_hmin && a.lub_mode == b.lub_mode;
+              a.lub_hmin == b.lub_hmin && a.lub_mode == b.lub_mode && a.force_average == b.force_average;
     for (int c = 0; c < 2; ++c) eq = eq && a.tau[c] == b.tau[c] && a.rho_init[c] == b.rho_init[c];
     for (int k = 0; k < 3; ++k)
         eq = eq && a.body_accel[k] == b.body_accel[k] && a.wall_vel[0][k] == b.wall_vel[0][k] &&
@@ -1083,7 +1093,7 @@ int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
         return fail(h, LB_EINVAL, "checkpoint of a lattice with other parameters (box, precision or model)");
     const int np = (int)hdr[1];
     const size_t fsz = (size_t)2 * Q * padded_sites(h->N) * h->tsize;
-    if (bytes < head + fsz + (size_t)np * (18 * 8 + 4)) return fail(h, LB_EINVAL, "truncated checkpoint");
+    if (bytes < head + fsz + (size_t)np * (24 * 8 + 4)) return fail(h, LB_EINVAL, "truncated checkpoint");
     const char *p = in + 16 + sizeof(lb_params);
     int64_t st;
     std::memcpy(&st, p, 8);
@@ -1097,7 +1107,7 @@ int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
     {
         const char *q = p;
         for (int k = 0; k < np; ++k) {
-            double v[18];
+            double v[24];
             std::memcpy(v, q, sizeof(v));
             q += sizeof(v);
             int32_t pr;
@@ -1128,15 +1138,18 @@ int lb_set_state(lb_handle *h, const void *buf, size_t bytes) {
         const int rc = lb_add_particles(h, np, parts.data());
         if (rc != LB_OK) return rc;
     }
+    std::vector<double> fp((size_t)6 * np);  // read by the copy below until the final synchronisation
     if (np) {
         std::vector<double> s((size_t)15 * np);
         const char *q = p;
         for (int k = 0; k < np; ++k) {
             std::memcpy(&s[15 * k], q, 15 * 8);
-            q += 18 * 8 + 4;
+            std::memcpy(&fp[6 * k], q + 18 * 8, 6 * 8);
+            q += 24 * 8 + 4;
         }
         const int rc = lb_set_particle_state(h, s.data());
         if (rc != LB_OK) return rc;
+        LB_HIP_CHECK(hipMemcpyAsync(h->dpart.Fprev, fp.data(), fp.size() * 8, hipMemcpyHostToDevice, h->stream));
     }
     LB_HIP_CHECK(hipMemcpyAsync(h->f[h->cur], pops, fsz, hipMemcpyHostToDevice, h->stream));
     h->bounce_pending = false;  // a checkpoint holds every bounced population in its slot

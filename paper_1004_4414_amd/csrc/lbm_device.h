@@ -267,6 +267,7 @@ struct DevParams {
     // otherwise redirect = this sweep forms them itself (sweep_bounce);
     // multi_bits: class words carry INFO_MULTI (lattices using that option)
     int link_write, redirect, multi_bits;
+    int force_avg;  // the fluid force entering the leap-frog is averaged over two steps
     double rho_init[2];
     double rho_ref[2];  // populations are stored as f_i - zeta_i rho_ref^c
     double psi_e[2];    // rho0 exp(-rho_ref^c / rho0): Psi(rho_ref + d) - Psi(rho_ref) = -psi_e expm1(-d/rho0)
@@ -312,6 +313,8 @@ struct DevParticles {
     // nnbr > NB_CAP: too many to list, every sphere is tested instead
     int32_t *nbr, *nnbr;
     double *Ffl, *Tfl, *Ftot, *Ttot, *P, *PT;
+    // np x 6: the fluid force and torque of the previous step (NaN: none yet)
+    double *Fprev;
     double *rad, *mass, *inertia, *color;  // np each
     int32_t *prescribed;
     // per-particle list segments (offset into the flat arrays, capacity, count);

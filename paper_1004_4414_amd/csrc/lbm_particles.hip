@@ -680,13 +680,23 @@ __global__ __launch_bounds__(64) void k_pair_forces_cells(DevParams P, DevPartic
 
 // total force and torque of each sphere (fluid, pending impulses, pair forces
 // in that order of summation) and its velocity after every force but the
-// lubrication impulses
+// lubrication impulses.  With force_avg the fluid part is the mean of this
+// step's and the previous step's (this step's alone while no previous one is
+// kept); the previous one is kept in either case.
 __device__ __forceinline__ void forces_total_body(DevParams P, DevParticles D, const Grid &g) {
     const int p = g.bid * BLOCK + threadIdx.x;
     if (p >= P.np) return;
     for (int a = 0; a < 3; ++a) {
-        D.Ftot[3 * p + a] = D.Ffl[3 * p + a] + D.P[3 * p + a] + D.Ftot[3 * p + a];
-        D.Ttot[3 * p + a] = D.Tfl[3 * p + a] + D.PT[3 * p + a];
+        double ff = D.Ffl[3 * p + a], tf = D.Tfl[3 * p + a];
+        const double fp = D.Fprev[6 * p + a], tp = D.Fprev[6 * p + 3 + a];
+        D.Fprev[6 * p + a] = ff;
+        D.Fprev[6 * p + 3 + a] = tf;
+        if (P.force_avg && !isnan(fp)) {
+            ff = 0.5 * (ff + fp);
+            tf = 0.5 * (tf + tp);
+        }
+        D.Ftot[3 * p + a] = ff + D.P[3 * p + a] + D.Ftot[3 * p + a];
+        D.Ttot[3 * p + a] = tf + D.PT[3 * p + a];
         D.vs[3 * p + a] = D.U[3 * p + a] + (D.prescribed[p] ? 0.0 : D.Ftot[3 * p + a] / D.mass[p]);
     }
 }

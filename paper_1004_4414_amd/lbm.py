@@ -54,6 +54,7 @@ class Params(ctypes.Structure):
         ("kernel", ctypes.c_int32), ("tile", ctypes.c_int32 * 3),
         ("lub_mode", ctypes.c_int32),
         ("link_writes", ctypes.c_int32),
+        ("force_average", ctypes.c_int32),
     ]
 
 
@@ -173,6 +174,7 @@ def make_params(p, precision="fp32", kernel="auto", tile=(0, 0, 0)):
     s.lub_hc, s.lub_hmin = p["lub_hc"], p["lub_hmin"]
     s.lub_mode = int(p.get("lub_mode", 1))
     s.link_writes = int(p.get("link_writes", 1))
+    s.force_average = int(p.get("force_average", 0))
     s.kernel = KERNELS[kernel]
     for a in range(3):
         s.tile[a] = int(tile[a])

@@ -79,7 +79,8 @@ def test_shared_launch_batch_matches_eager_stepping(precision):
     """Members of one precision and model are advanced by one launch per stage
     over all of them; uneven boxes (row-aligned 64 x 36 x 20 with spheres,
     ragged 40 x 24 x 20 without, 36^3 with spheres) stay bitwise equal to
-    eager stepping."""
+    eager stepping; the 36^3 member averages its spheres' fluid force over
+    two steps (force_average)."""
     specs = []
     p1 = W.params(nx=64, ny=36, nz=20, rho_init=(0.4, 0.3), noise_amp=0.02, g_br=0.08, seed=51)
     rng = np.random.default_rng(51)
@@ -88,7 +89,8 @@ def test_shared_launch_batch_matches_eager_stepping(precision):
                   precision))
     specs.append((W.params(nx=40, ny=24, nz=20, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.09, seed=52),
                   None, precision))
-    p3 = W.params(nx=36, ny=36, nz=36, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.08, seed=53)
+    p3 = W.params(nx=36, ny=36, nz=36, rho_init=(0.35, 0.35), noise_amp=0.02, g_br=0.08, seed=53,
+                  force_average=1)
     pos3 = W.random_sphere_positions((36, 36, 36), 3, 5.0, seed=53)
     specs.append((p3, W.make_particles(pos3, 5.0, vel=rng.uniform(-0.02, 0.02, (3, 3))), precision))
     batched = [_make(s) for s in specs]

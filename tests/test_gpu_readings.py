@@ -54,6 +54,74 @@ def test_mass_correction_fp64_end_to_end():
     assert np.abs(ref0.sums()["mass"] - sr["mass"]).max() > 1e-6
 
 
+@pytest.mark.parametrize("kernel", ["twopass", "fused"])
+def test_force_average_fp64_end_to_end(kernel):
+    """force_average = 1 (the fluid force and torque entering Eqs. (9), (10)
+    averaged over two steps) with moving spheres, FP64 end to end: fields,
+    bookkeeping, sphere states and every force against the oracle after 60
+    steps, with both sweeps; the averaged run differs from the plain one."""
+    p, parts = _moving_spheres(0.0)
+    p = dict(p, force_average=1)
+    gpu = lbm().Lattice(p, precision="fp64", kernel=kernel)
+    gpu.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    gpu.step(60)
+    ref.step(60)
+    compare_fields(gpu, ref, p, tol_rho=1e-9, tol_u=1e-8)
+    compare_bookkeeping(gpu, ref)
+    Pg, Pr = gpu.particles(), ref.particles()
+    for k in PKEYS + ("Ttotal",):
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-9, k
+    plain = Oracle(dict(p, force_average=0))
+    assert plain.add_particles(parts) == 0
+    plain.step(60)
+    assert np.abs(plain.particles()["U"] - Pr["U"]).max() > 1e-6
+
+
+def test_checkpoint_carries_the_previous_fluid_force():
+    """With force_average = 1 a lattice restored from a checkpoint continues
+    bitwise as the original (the checkpoint holds each sphere's fluid force
+    and torque of the step before); a lattice without the averaging refuses
+    the checkpoint, and a state overwrite starts the averaging anew as the
+    oracle does."""
+    L = lbm()
+    p, parts = _moving_spheres(0.0)
+    p = dict(p, force_average=1)
+    a = L.Lattice(p, precision="fp32")
+    a.add_particles(parts)
+    a.step(15)
+    blob = a.get_state()
+    b = L.Lattice(p, precision="fp32")
+    b.set_state(blob)
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.populations(), b.populations())
+    Pa, Pb = a.particles(), b.particles()
+    for k in Pa:
+        assert np.array_equal(Pa[k], Pb[k]), k
+    c = L.Lattice(dict(p, force_average=0), precision="fp32")
+    with pytest.raises(L.LBError) as e:
+        c.set_state(blob)
+    assert e.value.code == L.LB_EINVAL
+    # overwrite: no previous force afterwards, in both implementations
+    g = L.Lattice(p, precision="fp64")
+    g.add_particles(parts)
+    ref = Oracle(p)
+    assert ref.add_particles(parts) == 0
+    g.step(5)
+    ref.step(5)
+    Pr = ref.particles()
+    g.set_particle_state(Pr["R"], Pr["U"], Pr["W"], Pr["P"], Pr["PT"])
+    ref.set_particle_state(Pr["R"], Pr["U"], Pr["W"], Pr["P"], Pr["PT"])
+    g.set_populations(ref.populations())
+    g.step(3)
+    ref.step(3)
+    Pg, Pr = g.particles(), ref.particles()
+    for k in PKEYS + ("Ttotal",):
+        assert np.abs(Pg[k] - Pr[k]).max() < 1e-10, k
+
+
 def test_mass_correction_factor_on_refilled_sites_fp64():
     """The closed form of Eq. (31) on the GPU: after one step the fluid is
     rescaled so that Delta rho^c / N is the same for both components; in the
