@@ -129,10 +129,12 @@ def config(name):
 def _job(rng, edge, ratio_red, fraction, radius, theta, steps, seed, total=0.7):
     """one box of an ensemble: periodic cube, solvent ratio red:blue, spheres
     at the volume fraction, contact angle theta (degrees; the caller converts
-    it to a particle colour)"""
+    it to a particle colour).  Its spheres' fluid force is averaged over two
+    steps (force_average 1): with the force of each step alone, light spheres
+    in some of these dense random boxes run away within a few thousand steps"""
     box = (edge, edge, edge)
     p = params(nx=edge, ny=edge, nz=edge, rho_init=(total * ratio_red, total * (1.0 - ratio_red)),
-               noise_amp=0.01, g_br=0.08, seed=seed)
+               noise_amp=0.01, g_br=0.08, seed=seed, force_average=1)
     n = max(1, sphere_count(box, fraction, radius))
     # dense packings (up to 0.3) leave a smaller gap so that random addition
     # does not jam
