@@ -87,7 +87,7 @@ def _oracle_sample(seconds_budget):
     from paper_1004_4414_amd import workloads as W
     n = 64
     count = W.sphere_count((n, n, n), 0.15, 5.0)
-    p = W.params(nx=n, ny=n, nz=n, rho_init=(0.35, 0.35), noise_amp=0.01, g_br=0.08, seed=1003)
+    p = W.params(nx=n, ny=n, nz=n, rho_init=(0.35, 0.35), noise_amp=0.01, g_br=0.08, seed=1003, force_average=1)
     parts = W.make_particles(W.random_sphere_positions((n, n, n), count, 5.0, seed=1003), 5.0)
     orc = Oracle(p)
     orc.add_particles(parts)
@@ -384,7 +384,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "bijel256: 256^3 periodic, 50:50 at 0.35+-0.01, g=0.08, tau=1, "
-                        f"4806 spheres r=5 (volume fraction 0.15), neutral wettability, {precision.upper()} populations"
+                        f"4806 spheres r=5 (volume fraction 0.15), neutral wettability, sphere fluid force averaged "
+                        f"over two steps, {precision.upper()} populations"
             if args.workload == "bijel256" else args.workload,
             "sites": N,
             "spheres": len(parts["radius"]),

@@ -959,6 +959,19 @@ void orc_get_particles(const orc_state *s, double *out) {
 /* overwrite the kinematic state R, U, W and the pending impulses P, PT
  * (per particle 15 doubles) and rebuild the solid map without touching the
  * fluid; for loading a shared state */
+/* Test device: give every sphere a previous step's fluid force and torque
+ * (6 doubles per sphere: force, torque), as if it had stepped with them, so
+ * that a state taken from a run with force_average 1 continues that run. */
+void orc_set_previous_fluid_force(orc_state *s, const double *in) {
+    for (int p = 0; p < s->np; ++p) {
+        for (int a = 0; a < 3; ++a) {
+            s->Fprev[3 * p + a] = in[6 * p + a];
+            s->Tprev[3 * p + a] = in[6 * p + 3 + a];
+        }
+        s->have_prev[p] = 1;
+    }
+}
+
 void orc_set_particle_state(orc_state *s, const double *in) {
     for (int p = 0; p < s->np; ++p)
         for (int a = 0; a < 3; ++a) {

@@ -82,6 +82,7 @@ def lib():
         L.orc_num_particles.argtypes = [vp]
         L.orc_get_particles.argtypes = [vp, dp]
         L.orc_set_particle_state.argtypes = [vp, dp]
+        L.orc_set_previous_fluid_force.argtypes = [vp, dp]
         L.orc_particle_counts.argtypes = [vp, ip, ip]
         L.orc_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.orc_sums.argtypes = [vp, dp]
@@ -182,6 +183,12 @@ class Oracle:
             [np.asarray(R, float), np.asarray(U, float), np.asarray(W, float),
              z if P is None else np.asarray(P, float), z if PT is None else np.asarray(PT, float)], axis=1))
         lib().orc_set_particle_state(self._h, _dp(buf))
+
+    def set_previous_fluid_force(self, F, T):
+        """the fluid force and torque (n,3) each sphere took in the step before,
+        for force_average 1 (set after set_particle_state, which forgets them)"""
+        buf = np.ascontiguousarray(np.concatenate([np.asarray(F, float), np.asarray(T, float)], axis=1))
+        lib().orc_set_previous_fluid_force(self._h, _dp(buf))
 
     # -- stepping ------------------------------------------------------------
     def step(self, n=1):

@@ -107,7 +107,9 @@ def config(name):
       of radius 4 (about 10% volume), neutral wettability, particle density 1,
       FP32, 1000 steps.
     * ``bijel256``: 256^3, 50:50 at 0.35 +- 0.01, g = 0.08, 4806 spheres of
-      radius 5 (volume fraction 0.15), neutral wettability, FP32, 10000 steps.
+      radius 5 (volume fraction 0.15), neutral wettability, FP32, 10000 steps,
+      the spheres' fluid force averaged over two steps (force_average 1: with
+      each step's force alone the run breaks down near step 5,300).
     """
     if name == "spinodal32":
         p = params(nx=32, ny=32, nz=32, rho_init=(0.7, 0.7), noise_amp=0.01, g_br=0.1, seed=1001)
@@ -120,7 +122,8 @@ def config(name):
     if name == "bijel256":
         box = (256, 256, 256)
         n = sphere_count(box, 0.15, 5.0)
-        p = params(nx=256, ny=256, nz=256, rho_init=(0.35, 0.35), noise_amp=0.01, g_br=0.08, seed=1003)
+        p = params(nx=256, ny=256, nz=256, rho_init=(0.35, 0.35), noise_amp=0.01, g_br=0.08, seed=1003,
+                   force_average=1)
         pos = random_sphere_positions(box, n, 5.0, seed=1003)
         return p, make_particles(pos, 5.0), 10000, "fp32"
     raise KeyError(name)

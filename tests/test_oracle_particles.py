@@ -153,6 +153,32 @@ def test_force_average_shifts_the_momentum_balance_by_half_the_end_forces():
     assert orc.counts()["covered_total"] > 10
 
 
+def test_previous_fluid_force_setter_continues_an_averaged_run():
+    """A state copied mid-run (positions, velocities, pending impulses,
+    populations) into a fresh oracle with force_average 1 continues the
+    original bitwise once each sphere's previous fluid force and torque are
+    handed over too, and differs without them (the copy then starts the
+    average anew)."""
+    a = _moving_spheres(force_average=1)
+    a.step(10)
+    Pa = a.particles()
+    copies = []
+    for hand_over in (True, False):
+        b = _moving_spheres(force_average=1)
+        b.set_particle_state(Pa["R"], Pa["U"], Pa["W"], Pa["P"], Pa["PT"])
+        if hand_over:
+            b.set_previous_fluid_force(Pa["Ffluid"], Pa["Tfluid"])
+        b.set_populations(a.populations())
+        b.step(5)
+        copies.append(b)
+    a.step(5)
+    Pa, Pb, Pc = a.particles(), copies[0].particles(), copies[1].particles()
+    for k in ("R", "U", "W", "Ftotal", "Ttotal"):
+        assert np.array_equal(Pa[k], Pb[k]), k
+    assert np.array_equal(a.populations(), copies[0].populations())
+    assert not np.array_equal(Pa["U"], Pc["U"])
+
+
 def test_mass_changes_only_by_covering_refilling_and_the_wall_term():
     """The moving-wall term of the bounce-back, covering and refilling are the
     only sources of fluid mass; everything else conserves it exactly."""
