@@ -162,7 +162,7 @@ typedef struct {
  * here: a zeroed struct selects lub_mode 0. */
 void lb_default_params(lb_params *p);
 
-/* Create a lattice: two fluid components "distributed randomly" (Sec. VI),
+/* Create a lattice: two fluid components with random initial densities (Sec. VI),
  * rho^c(x) = rho_init^c + noise_amp (2U - 1) with U the SplitMix64 draw of
  * index 2n + c, at rest in the equilibrium of Eq. (3) (f_i = zeta_i rho^c),
  * plus the two wall planes if wall_axis >= 0.

@@ -183,9 +183,9 @@ static void equilibrium(double rho, const double u[3], int order, double feq[Q])
 /* Eq. (5): effective mass */
 static double psi_of(double rho, double rho0) { return rho0 * (1.0 - exp(-rho / rho0)); }
 
-/* neighbour weight W_i of the sum in Eq. (4).  Reading: the paper says only
- * "nearest neighbours"; all 18 non-rest D3Q19 neighbours are used, faces
- * weighted w_face and edges w_edge. */
+/* neighbour weight W_i of the sum in Eq. (4).  Reading: the paper restricts
+ * the sum to the nearest neighbours without naming the set; all 18 non-rest
+ * D3Q19 neighbours are used, faces weighted w_face and edges w_edge. */
 static double sc_weight(const orc_state *s, int i) {
     int n2 = CV[i][0] * CV[i][0] + CV[i][1] * CV[i][1] + CV[i][2] * CV[i][2];
     if (n2 == 1) return s->p.w_face;
@@ -270,7 +270,7 @@ orc_state *orc_create(const orc_params *prm) {
             else if (pos[a] == L[a] - 1) s->owner[n] = WALL_HI;
         }
     }
-    /* Initial fluids "distributed randomly": rho^c = rho_init^c + noise*(2U-1),
+    /* Initial fluids at random (Sec. VI): rho^c = rho_init^c + noise*(2U-1),
      * U from SplitMix64 at draw index 2n + c; f = equilibrium at rest. */
     for (long n = 0; n < N; ++n) {
         if (s->owner[n] != FLUID) continue;
@@ -467,7 +467,7 @@ static void collide(orc_state *s) {
         if (s->owner[n] != FLUID) continue;
         double ubar[3] = {0.0, 0.0, 0.0};
         if (s->p.velocity_mode == 0) {
-            /* Reading: "u is the macroscopic bulk velocity of the fluid" is the
+            /* Reading: the bulk fluid velocity in the equilibrium is taken as the
              * Shan-Chen common velocity u' = sum_c (j^c/tau^c) / sum_c (rho^c/tau^c) */
             double den = 0.0, num[3] = {0.0, 0.0, 0.0};
             for (int c = 0; c < NCOMP; ++c) {

@@ -2,8 +2,8 @@
 the benchmark.
 
 This module holds no arithmetic of the method itself: it only draws particle
-positions (random sequential addition, as in the paper's "initial positions
-... chosen at random", Sec. VI) and assembles the parameter sets of the
+positions (random sequential addition: the paper places its spheres at random
+initial positions, Sec. VI) and assembles the parameter sets of the
 benchmark workloads.  The random initial fluid densities are drawn by each
 implementation from its own SplitMix64 generator keyed by ``seed``.
 """
