@@ -132,6 +132,9 @@ void build_shared(lb_batch *b, const std::vector<lb_handle *> &ms, lbm::BatchLau
     for (int par = 0; par < 2; ++par) L.plan[par] = BatchPlan{dt + (size_t)par * nm, ds, nm};
     for (int k = 0; k < BM_COUNT; ++k) L.total[k] = start[(size_t)k * (nm + 1) + nm];
     L.nm = nm;
+    L.fin_stride = 1;
+    for (int i = 0; i < nm; ++i)
+        L.fin_stride = std::max(L.fin_stride, fin_blocks((start[i + 1] - start[i]) * (int)(BLOCK / 64)));
     L.any_rows = L.any_flat = 0;
     for (int i = 0; i < nm; ++i) {
         if (ms[i]->prm.nx % (int)VB == 0) L.any_rows = 1;

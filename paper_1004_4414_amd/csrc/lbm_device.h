@@ -281,7 +281,13 @@ struct DevParams {
 };
 
 // device-resident scalars of a handle
-constexpr int FIN_BLOCKS = 64;  // blocks of the fixed-order mass reduction
+constexpr int FIN_BLOCKS = 256;   // most blocks of the fixed-order mass reduction
+constexpr int FIN_PER_BLOCK = 1024;  // per-wavefront partial masses summed by one of them
+// blocks of the mass reduction over nb partials
+__host__ __device__ inline int fin_blocks(int nb) {
+    const int n = (nb + FIN_PER_BLOCK - 1) / FIN_PER_BLOCK;
+    return n < 1 ? 1 : (n > FIN_BLOCKS ? FIN_BLOCKS : n);
+}
 struct DevState {
     double M0[2];      // fluid mass at the start of the first step
     double Mstep[2];   // fluid mass at the start of the current step

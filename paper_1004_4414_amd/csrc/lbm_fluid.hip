@@ -254,13 +254,13 @@ __global__ __launch_bounds__(BLOCK) void k_density_bounce(DevParams P, S *f, con
 }
 
 // fixed-order sum of the per-block masses: M(t), baseline M(0), sentinel.
-// fin_blocks(nb) blocks (one per 4096 partials, at most FIN_BLOCKS) each sum
-// a contiguous range of the partials (8 independent sums per thread, then a
-// fixed tree); the last block to finish (an integer counter) sums their
+// fin_blocks(nb) blocks (one per FIN_PER_BLOCK partials, at most FIN_BLOCKS)
+// each sum a contiguous range of the partials (8 independent sums per thread,
+// then a fixed tree); the last block to finish (an integer counter) sums their
 // results in block order and resets the counter, so the total does not
 // depend on which block finishes last.  Blocks past fin_blocks(nb) return.
 constexpr int FIN_THREADS = 256;
-__host__ __device__ inline int fin_blocks(int nb) { return std::max(1, std::min(FIN_BLOCKS, (nb + 4095) / 4096)); }
+static_assert(FIN_BLOCKS <= FIN_THREADS, "the last block sums one block result per thread");
 __device__ __forceinline__ void finalize_body(const double *__restrict__ partial, int nb, DevState *st,
                                               unsigned bid) {
     __shared__ double lds[2][FIN_THREADS];
@@ -793,11 +793,12 @@ __global__ __launch_bounds__(BLOCK) void kb_density(BatchPlan B) {
     density_body<S, ROWS, false>(M.P, (const S *)M.fin, M.info, (T *)M.rho, (T *)M.psi, M.partial, g, M.D, M.owner,
                                  (const T *)nullptr);
 }
-__global__ __launch_bounds__(FIN_THREADS) void kb_finalize_mass(BatchPlan B) {
-    const int m = (int)(blockIdx.x / FIN_BLOCKS);
+// stride: blocks per member, the most fin_blocks() of any member
+__global__ __launch_bounds__(FIN_THREADS) void kb_finalize_mass(BatchPlan B, int stride) {
+    const int m = (int)(blockIdx.x / stride);
     const BatchMember &M = B.m[m];
     const int *st = B.start + BM_DENSE * (B.nm + 1);
-    finalize_body(M.partial, (st[m + 1] - st[m]) * (BLOCK / 64), M.dstate, blockIdx.x % FIN_BLOCKS);
+    finalize_body(M.partial, (st[m + 1] - st[m]) * (BLOCK / 64), M.dstate, blockIdx.x % stride);
 }
 template <typename T>
 __global__ __launch_bounds__(SHELL_THREADS) void kb_shell_fill(BatchPlan B) {
@@ -823,7 +824,7 @@ void launch_batch_fluid(const BatchLaunch &L, int parity, hipStream_t s) {
         using T = Cmp<S>;
         if (L.any_rows) kb_density<S, true><<<nd, BLOCK, 0, s>>>(B);
         if (L.any_flat) kb_density<S, false><<<nd, BLOCK, 0, s>>>(B);
-        kb_finalize_mass<<<(unsigned)(L.nm * FIN_BLOCKS), FIN_THREADS, 0, s>>>(B);
+        kb_finalize_mass<<<(unsigned)(L.nm * L.fin_stride), FIN_THREADS, 0, s>>>(B, L.fin_stride);
         if (L.total[BM_SPHERE] > 0) kb_shell_fill<T><<<(unsigned)L.total[BM_SPHERE], SHELL_THREADS, 0, s>>>(B);
         with_model(L.prm, [&](auto m) {
             if (L.any_rows) kb_collide_stream<S, decltype(m), true><<<nd, BLOCK, 0, s>>>(B);

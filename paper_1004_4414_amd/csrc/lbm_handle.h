@@ -157,6 +157,7 @@ struct BatchLaunch {
     BatchPlan plan[2];       // device tables for the two step parities (fin / fout swapped)
     int total[BM_COUNT];     // blocks of each map over all members
     int nm;
+    int fin_stride;          // blocks per member of the mass total: the most fin_blocks() of any member
     int any_rows, any_flat;  // members with row-aligned addressing (nx % 64 == 0), and without
     lb_params prm;           // precision and collision model shared by the members
 };
