@@ -114,9 +114,10 @@ typedef struct {
                                 two-pass sweep, outside a stream capture, the next step's density
                                 sweep forms each from the fluid site's own slot (only links next
                                 to a map change are written out by the map update) */
-    int32_t force_average;   /* the fluid force and torque (links of Eq. (16), the moving-wall
-                                term, covering and Shan-Chen force on the sphere) that enter
-                                Eqs. (9), (10), which the paper leaves to the coupling of the
+    int32_t force_average;   /* the fluid force and torque that enter Eqs. (9), (10) (the link
+                                momentum of Eq. (17) with its moving-wall term, and the Shan-Chen
+                                force on the virtual fluid; the covering and refilling impulses
+                                are not included), a step the paper leaves to the coupling of the
                                 literature it builds on: 0 (default): this step's, as printed;
                                 1: the mean of this step's and the previous step's (a sphere's
                                 first step after lb_add_particles or lb_set_particle_state uses
