@@ -178,7 +178,7 @@ size_t fluid_bytes(const lb_params *p) {
 size_t particle_bytes(const lb_params *p, int np, double max_r) {
     const size_t sc = (size_t)shell_capacity(max_r);
     const size_t cells = (size_t)((p->nx + 7) / 8) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
-    size_t b = (size_t)np * (53 * 8 + (22 + MAX_LUB_CONTACTS + CAND_CAP + NB_CAP) * 4 + MAX_LUB_CONTACTS * 32) +
+    size_t b = (size_t)np * (59 * 8 + (22 + MAX_LUB_CONTACTS + CAND_CAP + NB_CAP) * 4 + MAX_LUB_CONTACTS * 32) +
                4 * cells;
     const double reach = 2.0 * max_r + std::max(p->lub_hc, NB_REACH);  // cell list of the pair search
     b += 8 * (size_t)(p->nx / reach + 1) * (size_t)(p->ny / reach + 1) * (size_t)(p->nz / reach + 1);
