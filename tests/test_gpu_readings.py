@@ -1,8 +1,9 @@
 """GPU-vs-oracle parity of the parts of the method whose reading the oracle
 pins in closed form: the mass correction of Eq. (31), both integrations of
-the lubrication of Eq. (22), the per-axis speed limit of the map update, the
-checkpoint's parameter check, and developed (event-rich) states of the 64^3
-sphere workload in FP32 against the 1e-5 gate."""
+the lubrication of Eq. (22), the two-step average of the sphere fluid force
+(and the checkpoint that carries it), the per-axis speed limit of the map
+update, the checkpoint's parameter check, and developed (event-rich) states
+of the 64^3 sphere workload in FP32 against the 1e-5 gate."""
 import numpy as np
 import pytest
 
