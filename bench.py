@@ -231,7 +231,7 @@ def bench_ensemble(args):
     done = len(jobs) - len(failed)
     jph = done / t_batch * 3600.0
     return {
-        "metric": "jobs/hour (batched ensemble of 64 boxes, 2000 steps each)",
+        "metric": f"jobs/hour (batched ensemble of 64 boxes, {steps} steps each)",
         "value": round(jph, 1), "unit": "jobs/hour", "n_gpus": 1, "steps": steps, "warmup": 0,
         "ms_per_step": round(t_batch / steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
