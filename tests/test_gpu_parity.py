@@ -537,14 +537,16 @@ def _crop_step(p, shape, f0, P0, radius, centre, W=48, reach=18):
 W_ = W
 
 
-@pytest.mark.parametrize("warm", [3, 1000])
-def test_bijel256_full_size_crops_and_invariants(warm):
+@pytest.mark.parametrize("kernel,warm", [("twopass", 3), ("twopass", 1000), ("fused", 1000)])
+def test_bijel256_full_size_crops_and_invariants(kernel, warm):
     """One FP32 step of the 256^3 workload (4806 spheres, force averaged over
     two steps) from the state after `warm` steps, compared on 48^3 oracle
     windows (around three spheres and one random site) and by its full-size
-    invariants."""
+    invariants; the two-pass sweep as the benchmark runs it, and the fused
+    sweep in its 64 x 4 x 128 tiles at the developed state."""
     p, parts, _, _ = W.config("bijel256")
-    gpu = lbm().Lattice(p, precision="fp32")
+    tile = (64, 4, 128) if kernel == "fused" else (0, 0, 0)
+    gpu = lbm().Lattice(p, precision="fp32", kernel=kernel, tile=tile)
     gpu.add_particles(parts)
     gpu.step(warm)
     o0 = gpu.observables()
@@ -598,7 +600,7 @@ def test_bijel256_full_size_crops_and_invariants(warm):
         ur = Fr["u"][core, core, core]
         du = np.abs(Fg["u"][core, core, core] - ur).max(axis=-1)
         eu = du[~refilled].max()
-        print(f"window {kind} warm {warm}: velocity error {du.max():.2e} over all fluid sites, "
+        print(f"window {kind} {kernel} warm {warm}: velocity error {du.max():.2e} over all fluid sites, "
               f"{eu:.2e} without the {int(refilled.sum())} refilled ones, max |u| {np.abs(ur).max():.2e}")
         assert eu <= 1e-5 * np.abs(ur).max(), (kind, eu, np.abs(ur).max(), int(refilled.sum()))
         if kind == "sphere":
